@@ -1,0 +1,338 @@
+/*
+ * p1e_oracle.c -- plain FP64 reference ("oracle") for P1 finite-element energies.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the package smoke check and the CPU-baseline
+ * leg of the benchmark load this code. The product path never links, imports or calls it,
+ * and it shares no code with the product (its own geometry, densities, patches, sums).
+ *
+ * It follows Moskovka & Valdman, "Fast MATLAB evaluation of nonlinear energies using FEM in
+ * 2D and 3D: Nodal elements" (arXiv 2109.01158), written as slow, obvious element loops:
+ *
+ *   geometry     Section 4.1: element sizes |T| and P1 basis gradients from the vertex
+ *                coordinates (B = [x_1-x_0, ..., x_dim-x_0], grad phi_l = row l of B^-1 for
+ *                l >= 1, grad phi_0 = -sum of the others).
+ *   F_T          eq. (Dv): F_T[j][m] = sum_l v[I(T,l)][j] * d phi_{T,l} / d x_m.
+ *   densities    eq. (neoHook): W = C1 (|F|^2 - dim - 2 log det F) + D1 (det F - 1)^2;
+ *                eq. (pLaplacian): W = |grad v|^p / p.
+ *   J_grad       eq. (Denergy): sum over elements of |T| W(F_T), element order,
+ *                Neumaier-compensated.
+ *   b = M f      Section 3.2, eqs. (mass2D), (linearTerm2): consistent P1 mass matrix with
+ *                element entries |T| (1 + delta_ab) / ((dim+1)(dim+2)).
+ *   exact grad   Section 6.2, eq. (dWFv): dW/dF from the chain rule with d det F / dF_jm the
+ *                signed 2x2 minor (cofactor) and d I1 / dF_jm = 2 F_jm, scattered per element.
+ *   patch FD     Section 6.1, eqs. (CD), (CDS), (jgradpm), (sumpatch): for every free DOF n of
+ *                node i, perturb v_n by +eps and -eps, recompute F_T (eq. Dv) on every element
+ *                of the nodal patch T^i and difference the two patch sums of |T| W.
+ *
+ * Conventions (readings of the paper): J = J_grad - b.v (the linear part enters with a minus
+ * sign); det F <= 0 or a non-finite density makes the element "bad": the energy is +Inf and
+ * the bad elements are counted. For the p-Laplacian the gradient of |g|^p/p at g = 0 is 0.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no OpenMP: single-threaded on purpose).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORC_PLAPLACE = 1, ORC_NEOHOOKE = 2 };
+
+typedef struct {
+  int32_t dim;    /* 2 or 3 */
+  int32_t ncomp;  /* d: 1 (scalar) or dim (vector) */
+  int32_t kind;   /* ORC_PLAPLACE or ORC_NEOHOOKE */
+  int32_t pad_;
+  int64_t nn, ne;
+  const int32_t *conn;   /* [ne][dim+1] */
+  const double *coords;  /* [nn][dim] */
+  double p, C1, D1;
+} orc_problem;
+
+/* ---------------------------------------------------------------- Neumaier sum */
+typedef struct { double s, c; } orc_acc;
+
+static void acc_add(orc_acc *a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+  else a->c += (x - t) + a->s;
+  a->s = t;
+}
+static double acc_result(const orc_acc *a) { return a->s + a->c; }
+
+/* ---------------------------------------------------------------- small matrices */
+static double det2(double a, double b, double c, double d) { return a * d - b * c; }
+
+static double det_mat(int dim, double A[3][3]) {
+  if (dim == 2) return det2(A[0][0], A[0][1], A[1][0], A[1][1]);
+  return A[0][0] * A[1][1] * A[2][2] + A[0][2] * A[1][0] * A[2][1] + A[0][1] * A[1][2] * A[2][0]
+       - A[0][2] * A[1][1] * A[2][0] - A[0][1] * A[1][0] * A[2][2] - A[0][0] * A[1][2] * A[2][1];
+}
+
+/* cof[j][m] = (-1)^(j+m) * det(A with row j and column m removed) */
+static void cofactor(int dim, double A[3][3], double cof[3][3]) {
+  if (dim == 2) {
+    cof[0][0] = A[1][1];
+    cof[0][1] = -A[1][0];
+    cof[1][0] = -A[0][1];
+    cof[1][1] = A[0][0];
+    return;
+  }
+  for (int j = 0; j < 3; ++j) {
+    for (int m = 0; m < 3; ++m) {
+      double sub[2][2];
+      int r = 0;
+      for (int jj = 0; jj < 3; ++jj) {
+        if (jj == j) continue;
+        int c = 0;
+        for (int mm = 0; mm < 3; ++mm) {
+          if (mm == m) continue;
+          sub[r][c++] = A[jj][mm];
+        }
+        ++r;
+      }
+      double minor = det2(sub[0][0], sub[0][1], sub[1][0], sub[1][1]);
+      cof[j][m] = ((j + m) % 2 == 0) ? minor : -minor;
+    }
+  }
+}
+
+/* ---------------------------------------------------------------- geometry */
+/* vol[e] = |det B|/dim!, dphi[e][l][m] = d phi_l / d x_m for element e. Returns the number of
+ * elements with det B == 0 (degenerate). */
+int64_t orc_geometry(const orc_problem *P, double *vol, double *dphi) {
+  const int dim = P->dim, k = dim + 1;
+  int64_t ndegen = 0;
+  for (int64_t e = 0; e < P->ne; ++e) {
+    const int32_t *T = P->conn + e * k;
+    double B[3][3] = {{0}};
+    for (int l = 1; l <= dim; ++l)
+      for (int m = 0; m < dim; ++m)
+        B[m][l - 1] = P->coords[(int64_t)T[l] * dim + m] - P->coords[(int64_t)T[0] * dim + m];
+    double det = det_mat(dim, B);
+    double fact = (dim == 2) ? 2.0 : 6.0;
+    vol[e] = fabs(det) / fact;
+    if (det == 0.0) ++ndegen;
+    /* B^-1 = cof(B)^T / det B; row (l-1) of B^-1 is grad phi_l */
+    double cof[3][3];
+    cofactor(dim, B, cof);
+    double *g = dphi + e * k * dim;
+    for (int m = 0; m < dim; ++m) g[m] = 0.0;
+    for (int l = 1; l <= dim; ++l) {
+      for (int m = 0; m < dim; ++m) {
+        double binv_lm = cof[m][l - 1] / det; /* (B^-1)[l-1][m] = cof(B)[m][l-1] / det */
+        g[l * dim + m] = binv_lm;
+        g[m] -= binv_lm;
+      }
+    }
+  }
+  return ndegen;
+}
+
+/* ---------------------------------------------------------------- F_T and densities */
+/* F[j][m] = sum_l v[I(T,l)][j] * dphi_l[m]  (eq. Dv) */
+static void element_F(const orc_problem *P, const double *v, const int32_t *T,
+                      const double *dphi_e, double F[3][3]) {
+  const int dim = P->dim, d = P->ncomp;
+  for (int j = 0; j < 3; ++j)
+    for (int m = 0; m < 3; ++m) F[j][m] = 0.0;
+  for (int l = 0; l <= dim; ++l)
+    for (int j = 0; j < d; ++j)
+      for (int m = 0; m < dim; ++m)
+        F[j][m] += v[(int64_t)T[l] * d + j] * dphi_e[l * dim + m];
+}
+
+/* W(F); sets *bad when det F <= 0 or the value is not finite */
+static double density(const orc_problem *P, double F[3][3], int *bad) {
+  const int dim = P->dim;
+  double W;
+  if (P->kind == ORC_NEOHOOKE) {
+    double I1 = 0.0;
+    for (int j = 0; j < dim; ++j)
+      for (int m = 0; m < dim; ++m) I1 += F[j][m] * F[j][m];
+    double det = det_mat(dim, F);
+    if (!(det > 0.0)) { *bad = 1; return INFINITY; }
+    W = P->C1 * (I1 - dim - 2.0 * log(det)) + P->D1 * (det - 1.0) * (det - 1.0);
+  } else {
+    double s = 0.0;
+    for (int m = 0; m < dim; ++m) s += F[0][m] * F[0][m];
+    W = pow(sqrt(s), P->p) / P->p;
+  }
+  if (!isfinite(W)) { *bad = 1; return INFINITY; }
+  return W;
+}
+
+/* dW/dF (d x dim), Section 6.2 */
+static void density_dF(const orc_problem *P, double F[3][3], double D[3][3], int *bad) {
+  const int dim = P->dim;
+  for (int j = 0; j < 3; ++j)
+    for (int m = 0; m < 3; ++m) D[j][m] = 0.0;
+  if (P->kind == ORC_NEOHOOKE) {
+    double det = det_mat(dim, F);
+    if (!(det > 0.0)) { *bad = 1; return; }
+    double cof[3][3];
+    cofactor(dim, F, cof);
+    for (int j = 0; j < dim; ++j)
+      for (int m = 0; m < dim; ++m)
+        D[j][m] = P->C1 * (2.0 * F[j][m] - (2.0 / det) * cof[j][m])
+                + 2.0 * P->D1 * (det - 1.0) * cof[j][m];
+  } else {
+    double s = 0.0;
+    for (int m = 0; m < dim; ++m) s += F[0][m] * F[0][m];
+    double norm = sqrt(s);
+    double scale = (norm > 0.0) ? pow(norm, P->p - 2.0) : 0.0;
+    for (int m = 0; m < dim; ++m) D[0][m] = scale * F[0][m];
+  }
+  for (int j = 0; j < 3; ++j)
+    for (int m = 0; m < 3; ++m)
+      if (!isfinite(D[j][m])) *bad = 1;
+}
+
+/* ---------------------------------------------------------------- energy */
+/* J_grad = sum_T |T| W(F_T) (eq. Denergy). v is the full nodal field [nn][d]. Returns the
+ * number of bad elements (then *jgrad = +Inf). */
+int64_t orc_energy(const orc_problem *P, const double *v, const double *vol, const double *dphi,
+                   double *jgrad) {
+  const int dim = P->dim, k = dim + 1;
+  orc_acc acc = {0.0, 0.0};
+  int64_t nbad = 0;
+  for (int64_t e = 0; e < P->ne; ++e) {
+    double F[3][3];
+    element_F(P, v, P->conn + e * k, dphi + e * k * dim, F);
+    int bad = 0;
+    double W = density(P, F, &bad);
+    if (bad) { ++nbad; continue; }
+    acc_add(&acc, vol[e] * W);
+  }
+  *jgrad = nbad ? INFINITY : acc_result(&acc);
+  return nbad;
+}
+
+/* Per-element densities W(F_T) (bad elements get +Inf). */
+void orc_densities(const orc_problem *P, const double *v, const double *dphi, double *W_out) {
+  const int dim = P->dim, k = dim + 1;
+  for (int64_t e = 0; e < P->ne; ++e) {
+    double F[3][3];
+    element_F(P, v, P->conn + e * k, dphi + e * k * dim, F);
+    int bad = 0;
+    W_out[e] = density(P, F, &bad);
+  }
+}
+
+/* ---------------------------------------------------------------- b = M f */
+void orc_load_vector(const orc_problem *P, const double *vol, const double *f, double *b) {
+  const int dim = P->dim, k = dim + 1, d = P->ncomp;
+  memset(b, 0, sizeof(double) * (size_t)P->nn * d);
+  const double denom = (double)((dim + 1) * (dim + 2));
+  for (int64_t e = 0; e < P->ne; ++e) {
+    const int32_t *T = P->conn + e * k;
+    for (int a = 0; a < k; ++a)
+      for (int c = 0; c < k; ++c) {
+        double Mac = vol[e] * (a == c ? 2.0 : 1.0) / denom;
+        for (int j = 0; j < d; ++j)
+          b[(int64_t)T[a] * d + j] += Mac * f[(int64_t)T[c] * d + j];
+      }
+  }
+}
+
+/* compensated dot product sum_n x_n y_n */
+double orc_dot(int64_t n, const double *x, const double *y) {
+  orc_acc acc = {0.0, 0.0};
+  for (int64_t i = 0; i < n; ++i) acc_add(&acc, x[i] * y[i]);
+  return acc_result(&acc);
+}
+
+/* ---------------------------------------------------------------- exact gradient */
+/* g[i][j] = sum_{T containing i} |T| sum_m dW/dF_jm(F_T) dphi_{T,l(i)}[m], all nodes, no load
+ * term. Element-loop scatter. Returns the number of bad elements. */
+int64_t orc_grad_exact(const orc_problem *P, const double *v, const double *vol,
+                       const double *dphi, double *g) {
+  const int dim = P->dim, k = dim + 1, d = P->ncomp;
+  memset(g, 0, sizeof(double) * (size_t)P->nn * d);
+  int64_t nbad = 0;
+  for (int64_t e = 0; e < P->ne; ++e) {
+    const int32_t *T = P->conn + e * k;
+    const double *dp = dphi + e * k * dim;
+    double F[3][3], D[3][3];
+    element_F(P, v, T, dp, F);
+    int bad = 0;
+    density_dF(P, F, D, &bad);
+    if (bad) { ++nbad; continue; }
+    for (int l = 0; l < k; ++l)
+      for (int j = 0; j < d; ++j) {
+        double s = 0.0;
+        for (int m = 0; m < dim; ++m) s += D[j][m] * dp[l * dim + m];
+        g[(int64_t)T[l] * d + j] += vol[e] * s;
+      }
+  }
+  return nbad;
+}
+
+/* ---------------------------------------------------------------- nodal patches */
+/* patch_ptr[nn+1], patch_elem[(dim+1) ne]: elements containing node i in ascending order. */
+void orc_patches(const orc_problem *P, int64_t *patch_ptr, int64_t *patch_elem) {
+  const int k = P->dim + 1;
+  memset(patch_ptr, 0, sizeof(int64_t) * (size_t)(P->nn + 1));
+  for (int64_t e = 0; e < P->ne; ++e)
+    for (int l = 0; l < k; ++l) patch_ptr[P->conn[e * k + l] + 1] += 1;
+  for (int64_t i = 0; i < P->nn; ++i) patch_ptr[i + 1] += patch_ptr[i];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(P->nn > 0 ? P->nn : 1));
+  for (int64_t i = 0; i < P->nn; ++i) fill[i] = patch_ptr[i];
+  for (int64_t e = 0; e < P->ne; ++e)
+    for (int l = 0; l < k; ++l) {
+      int32_t i = P->conn[e * k + l];
+      patch_elem[fill[i]++] = e;
+    }
+  free(fill);
+}
+
+/* ---------------------------------------------------------------- patch central differences */
+/* For every DOF listed in dofs[0..ndofs) (global DOF index n = d*i + j), with e_n the n-th unit
+ * vector:  g = [ sum_{T in T^i} |T| W(F_T(v + eps e_n)) - sum_{T in T^i} |T| W(F_T(v - eps e_n)) ]
+ *              / (2 eps).
+ * F_T(v +- eps e_n) is recomputed from the perturbed nodal values by eq. (Dv). The optional
+ * cond[] receives sum_{T in T^i} |T| (|W+|_abs + |W-|_abs), the magnitude of the summed terms,
+ * with |W|_abs the sum of the absolute values of the density's terms (rounding scale).
+ * v is modified during the call and restored. Returns the number of bad evaluations. */
+int64_t orc_grad_patch_fd(const orc_problem *P, double *v, const double *vol,
+                          const double *dphi, const int64_t *patch_ptr,
+                          const int64_t *patch_elem, double eps, int64_t ndofs,
+                          const int64_t *dofs, double *g, double *cond) {
+  const int dim = P->dim, k = dim + 1, d = P->ncomp;
+  int64_t nbad = 0;
+  for (int64_t q = 0; q < ndofs; ++q) {
+    const int64_t n = dofs[q];
+    const int64_t i = n / d;
+    const double v0 = v[n];
+    double S[2];
+    double C = 0.0;
+    for (int sgn = 0; sgn < 2; ++sgn) {
+      v[n] = (sgn == 0) ? v0 + eps : v0 - eps;
+      orc_acc acc = {0.0, 0.0};
+      for (int64_t t = patch_ptr[i]; t < patch_ptr[i + 1]; ++t) {
+        const int64_t e = patch_elem[t];
+        double F[3][3];
+        element_F(P, v, P->conn + e * k, dphi + e * k * dim, F);
+        int bad = 0;
+        double W = density(P, F, &bad);
+        if (bad) { ++nbad; continue; }
+        acc_add(&acc, vol[e] * W);
+        double Wabs;
+        if (P->kind == ORC_NEOHOOKE) {
+          double I1 = 0.0;
+          for (int j = 0; j < dim; ++j)
+            for (int m = 0; m < dim; ++m) I1 += F[j][m] * F[j][m];
+          double det = det_mat(dim, F);
+          Wabs = P->C1 * (I1 + dim + 2.0 * fabs(log(det))) + P->D1 * (det - 1.0) * (det - 1.0);
+        } else {
+          Wabs = fabs(W);
+        }
+        C += vol[e] * Wabs;
+      }
+      S[sgn] = acc_result(&acc);
+    }
+    v[n] = v0;
+    g[q] = (S[0] - S[1]) / (2.0 * eps);
+    if (cond) cond[q] = C;
+  }
+  return nbad;
+}

@@ -1,0 +1,173 @@
+"""Seeded problem instances shaped like the paper's workloads.
+
+A :class:`Problem` carries everything both sides consume: mesh, Dirichlet mask and values
+per DOF, nodal load f (its P1 interpolant is the loading functional), material data and a
+full nodal trial field ``v`` (the deformation for Neo-Hookean, the scalar field for the
+p-Laplacian). Free DOFs are the DOFs with ``dirichlet == 0``, numbered in ascending global
+DOF order n = d*i + j (node-major, interleaved components).
+
+Amplitude rule for random displacements: the literal amplitude 1e-3 inverts elements on the
+fine meshes, so the displacement amplitude is ``min(1e-3, 0.15*h)`` with h the cell edge.
+For axis-aligned right triangles and Kuhn tetrahedra every displacement-gradient entry is a
+difference of two nodal values over h, hence bounded by 0.3, which keeps det F > 0.
+"""
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .meshes import kuhn_bar_level, kuhn_box_mesh, lshape_tri_mesh, rect_tri_mesh
+
+
+@dataclass
+class Problem:
+    name: str
+    dim: int
+    ncomp: int
+    kind: str                 # "plaplace" or "neohooke"
+    coords: np.ndarray        # f64 [nn, dim]
+    conn: np.ndarray          # i32 [ne, dim+1]
+    dirichlet: np.ndarray     # u8  [nn, ncomp], 1 = prescribed
+    dirichlet_values: np.ndarray  # f64 [nn, ncomp]
+    load: np.ndarray          # f64 [nn, ncomp], nodal values of f
+    v: np.ndarray             # f64 [nn, ncomp], trial field (full, Dirichlet values included)
+    p: float = 2.0
+    E: float = 0.0
+    nu: float = 0.0
+    eps: float = 1e-6         # central-difference step
+    h: float = 0.0
+    amp: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nn(self):
+        return self.coords.shape[0]
+
+    @property
+    def ne(self):
+        return self.conn.shape[0]
+
+    @property
+    def free_mask(self):
+        """Boolean mask over the flattened DOF vector (ascending DOF order)."""
+        return self.dirichlet.reshape(-1) == 0
+
+    @property
+    def n_free_dofs(self):
+        return int(self.free_mask.sum())
+
+    def vhat(self, v=None):
+        """Restriction of a full nodal field to the free DOFs, ascending DOF order."""
+        v = self.v if v is None else v
+        return np.ascontiguousarray(v.reshape(-1)[self.free_mask], dtype=np.float64)
+
+
+def _dirichlet_on(coords, ncomp, pred):
+    on = pred(coords)
+    mask = np.zeros((coords.shape[0], ncomp), dtype=np.uint8)
+    mask[on, :] = 1
+    return mask
+
+
+def plaplace_square(n=32, p=3.0, f=-10.0, seed=0, eps=1e-6, amp=1.0):
+    """Unit square, (n+1)^2 nodes, 2n^2 right triangles, zero Dirichlet boundary,
+    interior v ~ amp*U[-1,1]."""
+    coords, conn = rect_tri_mesh(n, n)
+    tol = 0.5 / n
+    dmask = _dirichlet_on(
+        coords, 1,
+        lambda X: (X[:, 0] < tol) | (X[:, 0] > 1 - tol) | (X[:, 1] < tol) | (X[:, 1] > 1 - tol))
+    rng = np.random.default_rng(seed)
+    v = amp * rng.uniform(-1.0, 1.0, size=(coords.shape[0], 1))
+    v[dmask == 1] = 0.0
+    return Problem(
+        name=f"plaplace_square_n{n}_p{p:g}", dim=2, ncomp=1, kind="plaplace",
+        coords=coords, conn=conn, dirichlet=dmask,
+        dirichlet_values=np.zeros((coords.shape[0], 1)),
+        load=np.full((coords.shape[0], 1), float(f)), v=v, p=float(p), eps=eps, h=1.0 / n,
+        amp=amp)
+
+
+def _neohooke_random(coords, conn, dim, dmask, load_vec, seed, h, eps, name, amp=None):
+    if amp is None:
+        amp = min(1e-3, 0.15 * h)
+    rng = np.random.default_rng(seed)
+    u = amp * rng.uniform(-1.0, 1.0, size=(coords.shape[0], dim))
+    u[dmask == 1] = 0.0
+    v = coords + u
+    load = np.tile(np.asarray(load_vec, dtype=np.float64), (coords.shape[0], 1))
+    return Problem(
+        name=name, dim=dim, ncomp=dim, kind="neohooke", coords=coords, conn=conn,
+        dirichlet=dmask, dirichlet_values=np.where(dmask == 1, coords, 0.0), load=load, v=v,
+        E=2e8, nu=0.3, eps=eps, h=h, amp=amp)
+
+
+def neohooke_beam_2d(nx=2240, ny=224, lx=2.0, ly=0.2, seed=0, eps=1e-6, amp=None):
+    """Beam [0,lx]x[0,ly], left edge clamped (v = x), f = (0, -3.5e7)."""
+    coords, conn = rect_tri_mesh(nx, ny, 0.0, lx, 0.0, ly)
+    h = lx / nx
+    dmask = _dirichlet_on(coords, 2, lambda X: X[:, 0] < 0.5 * h)
+    return _neohooke_random(coords, conn, 2, dmask, (0.0, -3.5e7), seed, h, eps,
+                            f"neohooke_beam_{nx}x{ny}", amp)
+
+
+def neohooke_box_3d(nx=460, ny=46, nz=46, lx=1.0, ly=0.1, lz=0.1, seed=0, eps=1e-6, amp=None):
+    """Box [0,lx]x[0,ly]x[0,lz], Kuhn tets, face x = 0 clamped (v = x), f = (0,-3.5e7,0)."""
+    coords, conn = kuhn_box_mesh(nx, ny, nz, 0.0, lx, 0.0, ly, 0.0, lz)
+    h = lx / nx
+    dmask = _dirichlet_on(coords, 3, lambda X: X[:, 0] < 0.5 * h)
+    return _neohooke_random(coords, conn, 3, dmask, (0.0, -3.5e7, 0.0), seed, h, eps,
+                            f"neohooke_box_{nx}x{ny}x{nz}", amp)
+
+
+def twisted_bar(level, alpha=2.0 * np.pi, lx=0.4, ly=0.01, lz=0.01):
+    """Benchmark-2 workload: Kuhn bar at ``level``, both end walls prescribed, and the
+    twist deformation (x, R(alpha x / lx) (y, z)) at every node, no load."""
+    coords, conn = kuhn_bar_level(level, lx, ly, lz)
+    h = lx / (80 * 2 ** (level - 1))
+    dmask = _dirichlet_on(coords, 3, lambda X: (X[:, 0] < 0.5 * h) | (X[:, 0] > lx - 0.5 * h))
+    x, y, z = coords[:, 0], coords[:, 1], coords[:, 2]
+    th = alpha * x / lx
+    v = np.stack([x, np.cos(th) * y + np.sin(th) * z, -np.sin(th) * y + np.cos(th) * z], axis=1)
+    return Problem(
+        name=f"twisted_bar_L{level}", dim=3, ncomp=3, kind="neohooke", coords=coords,
+        conn=conn, dirichlet=dmask, dirichlet_values=np.where(dmask == 1, v, 0.0),
+        load=np.zeros_like(coords), v=v, E=2e8, nu=0.3, eps=1e-8, h=h, amp=0.0,
+        meta={"alpha": alpha, "lx": lx, "ly": ly, "lz": lz})
+
+
+def plaplace_lshape(n, p=3.0, f=-10.0, seed=0, amp=1.0, eps=1e-5):
+    """L-shape of three unit squares, n cells per unit length, zero Dirichlet boundary."""
+    coords, conn = lshape_tri_mesh(n)
+    # boundary nodes: on the outer square boundary or on the two re-entrant edges
+    X = coords
+    t = 0.5 / n
+    on = ((np.abs(X[:, 0]) > 1 - t) | (np.abs(X[:, 1]) > 1 - t)
+          | ((X[:, 0] > -t) & (np.abs(X[:, 1]) < t))
+          | ((np.abs(X[:, 0]) < t) & (X[:, 1] < t)))
+    dmask = on.astype(np.uint8)[:, None]
+    rng = np.random.default_rng(seed)
+    v = amp * rng.uniform(-1.0, 1.0, size=(coords.shape[0], 1))
+    v[dmask == 1] = 0.0
+    return Problem(
+        name=f"plaplace_lshape_n{n}", dim=2, ncomp=1, kind="plaplace", coords=coords,
+        conn=conn, dirichlet=dmask, dirichlet_values=np.zeros((coords.shape[0], 1)),
+        load=np.full((coords.shape[0], 1), float(f)), v=v, p=float(p), eps=eps, h=1.0 / n,
+        amp=amp)
+
+
+# The five workloads: small p-Laplacian, 2D beam, 3D box (the headline), the serving mix
+# (built by the serving driver, not here) and the large 3D box for exact vs FD.
+CONFIGS = {
+    "plap_square_33": dict(fn=plaplace_square, kw=dict(n=32, p=3.0, f=-10.0, seed=0, eps=1e-6)),
+    "nh2d_beam_1M": dict(fn=neohooke_beam_2d, kw=dict(nx=2240, ny=224, seed=0, eps=1e-6)),
+    "nh3d_box_6M": dict(fn=neohooke_box_3d, kw=dict(nx=460, ny=46, nz=46, seed=0, eps=1e-6)),
+    "nh3d_box_48M": dict(fn=neohooke_box_3d, kw=dict(nx=930, ny=93, nz=93, seed=0, eps=1e-8)),
+}
+
+
+def config_problem(name, **override):
+    c = CONFIGS[name]
+    kw = dict(c["kw"])
+    kw.update(override)
+    return c["fn"](**kw)

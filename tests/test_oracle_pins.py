@@ -1,0 +1,328 @@
+"""Pins of the FP64 oracle to facts that do not come from the oracle itself.
+
+Each test names what it pins: values printed in the paper (tests/golden/), closed forms,
+invariants of the densities, special cases that reduce to textbook objects, and brute force
+on tiny meshes. Together they are chosen so that a dropped term, a wrong sign, a wrong index
+or a transposed operand anywhere in the oracle fails at least one of them.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import p1e_synth as S
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _rand_rotation(rng, dim):
+    A = rng.standard_normal((dim, dim))
+    Q, R = np.linalg.qr(A)
+    Q = Q * np.sign(np.diag(R))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    return Q
+
+
+# ----------------------------------------------------------------------------- printed values
+@pytest.mark.parametrize("level", [1, 2, 3, 4])
+def test_table2_twisted_bar_energy(oracle_mod, level):
+    """Table 2: J_grad of the twisted bar, all printed digits (4 decimals)."""
+    g = _gold("table2_twisted_bar.json")
+    P = S.twisted_bar(level)
+    O = oracle_mod.Oracle(P)
+    r = O.energy(P.v)
+    assert r["nbad"] == 0
+    assert P.n_free_dofs == g["free_dofs"][level - 1]
+    assert round(r["Jgrad"], 4) == pytest.approx(g["jgrad_printed"][level - 1], abs=1e-12)
+
+
+@pytest.mark.slow
+def test_table2_twisted_bar_energy_level5(oracle_mod):
+    g = _gold("table2_twisted_bar.json")
+    P = S.twisted_bar(5)
+    r = oracle_mod.Oracle(P).energy(P.v)
+    assert round(r["Jgrad"], 4) == pytest.approx(g["jgrad_printed"][4], abs=1e-12)
+
+
+def test_twist_closed_form_limit(oracle_mod):
+    """Benchmark 2 continuum energy: the discrete energies converge to it at O(h^2)."""
+    g = _gold("table2_twisted_bar.json")
+    C1, _ = oracle_mod.neohooke_constants(2e8, 0.3)
+    a, lx, ly, lz = 2 * np.pi, 0.4, 0.01, 0.01
+    closed = a * a * C1 * ly * lz * (ly * ly + lz * lz) / (12 * lx)
+    # the paper prints the value with "approximately" to 6 decimals
+    assert closed == pytest.approx(g["continuum_jgrad"], abs=1e-6)
+    errs = []
+    for L in (2, 3, 4):
+        P = S.twisted_bar(L)
+        errs.append(oracle_mod.Oracle(P).energy(P.v)["Jgrad"] - closed)
+    assert all(e > 0 for e in errs)
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert all(3.3 < r < 4.5 for r in ratios), ratios
+
+
+def test_table1_counts_and_patch_rows(oracle_mod):
+    """Table 1 node/element/free-DOF counts; 7584 free-node patch rows at level 1."""
+    g = _gold("table1_mesh_counts.json")
+    for L in (1, 2, 3, 4):
+        P = S.twisted_bar(L)
+        assert (P.nn, P.ne, P.n_free_dofs) == (g["nn"][L - 1], g["ne"][L - 1],
+                                               g["free_dofs"][L - 1])
+    P = S.twisted_bar(1)
+    O = oracle_mod.Oracle(P)
+    ptr, _ = O.patches()
+    sizes = np.diff(ptr)
+    free_node = P.dirichlet.max(axis=1) == 0
+    assert free_node.sum() == g["level1_free_nodes"]
+    assert (~free_node).sum() == g["level1_dirichlet_nodes"]
+    assert sizes[free_node].sum() == g["level1_patch_rows"]
+    assert sizes.sum() == 4 * P.ne
+
+
+def test_fig1_lshape_counts(oracle_mod):
+    """Example 1 / Fig. 1: 24 triangles, 21 nodes, interior patches of 6 triangles;
+    Table 6 free-DOF counts of the L-shape levels."""
+    g = _gold("fig1_lshape.json")
+    P = S.plaplace_lshape(2)
+    assert (P.ne, P.nn) == (g["example_ne"], g["example_nn"])
+    ptr, _ = oracle_mod.Oracle(P).patches()
+    interior = P.dirichlet[:, 0] == 0
+    assert np.all(np.diff(ptr)[interior] == g["interior_patch_size"])
+    for L, nf in zip(g["table6_levels"], g["table6_free_dofs"]):
+        assert S.plaplace_lshape(2 ** (L + 1)).n_free_dofs == nf
+
+
+# ----------------------------------------------------------------------------- geometry
+def test_patch_areas_sum_to_domain(oracle_mod):
+    """sum_T |T| = |Omega| and sum_i area(T^i) = (dim+1)|Omega|; interior valences 24 / 6."""
+    P = S.neohooke_box_3d(6, 4, 5, 1.0, 0.4, 0.5)
+    O = oracle_mod.Oracle(P)
+    assert O.vol.sum() == pytest.approx(1.0 * 0.4 * 0.5, rel=1e-14)
+    ptr, ent = O.patches()
+    area = np.add.reduceat(O.vol[ent], ptr[:-1])
+    assert area.sum() == pytest.approx(4 * 0.2, rel=1e-14)
+    X = P.coords
+    inner = ((X[:, 0] > 1e-9) & (X[:, 0] < 1 - 1e-9) & (X[:, 1] > 1e-9) & (X[:, 1] < 0.4 - 1e-9)
+             & (X[:, 2] > 1e-9) & (X[:, 2] < 0.5 - 1e-9))
+    assert np.all(np.diff(ptr)[inner] == 24)
+    P2 = S.plaplace_square(8)
+    O2 = oracle_mod.Oracle(P2)
+    assert O2.vol.sum() == pytest.approx(1.0, rel=1e-14)
+    ptr2, _ = O2.patches()
+    assert np.all(np.diff(ptr2)[P2.dirichlet[:, 0] == 0] == 6)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_affine_fields_are_reproduced(oracle_mod, dim):
+    """A P1 field v = A x + c has F = A on every element, so J_grad = |Omega| W(A); this pins
+    the basis gradients (values, signs and orientation) and the gather of eq. (Dv)."""
+    rng = np.random.default_rng(3)
+    if dim == 2:
+        P = S.neohooke_beam_2d(7, 5, 1.0, 0.7)
+    else:
+        P = S.neohooke_box_3d(4, 3, 5, 1.0, 0.6, 0.9)
+    A = np.eye(dim) + 0.2 * rng.standard_normal((dim, dim))
+    assert np.linalg.det(A) > 0
+    c = rng.standard_normal(dim)
+    v = P.coords @ A.T + c
+    O = oracle_mod.Oracle(P)
+    W = O.densities(v)
+    assert np.allclose(W, W[0], rtol=1e-12, atol=0)
+    r = O.energy(v)
+    assert r["Jgrad"] == pytest.approx(O.vol.sum() * W[0], rel=1e-12)
+    # the exact gradient of an affine field: interior nodes are in equilibrium
+    g, nbad = O.grad_exact_full(v)
+    assert nbad == 0
+    g = g.reshape(-1, dim)
+    X = P.coords
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    inner = np.all((X > lo + 1e-9) & (X < hi - 1e-9), axis=1)
+    assert np.abs(g[inner]).max() <= 1e-12 * np.abs(g).max()
+
+
+# ----------------------------------------------------------------------------- Neo-Hookean
+@pytest.mark.parametrize("dim", [2, 3])
+def test_neohooke_identity_and_rigid_motions(oracle_mod, dim):
+    """W(I) = 0; J_grad is invariant under rigid motions v -> Qv + c (frame indifference)."""
+    rng = np.random.default_rng(11)
+    P = (S.neohooke_beam_2d(6, 4, 1.0, 0.5, amp=0.02) if dim == 2
+         else S.neohooke_box_3d(4, 3, 3, 1.0, 0.7, 0.6, amp=0.05))
+    O = oracle_mod.Oracle(P)
+    # W(I) = 0: only the rounding of F = I (about 1e-16) remains
+    assert abs(O.energy(P.coords)["Jgrad"]) < 1e-14 * O.C1 * O.vol.sum()
+    Q = _rand_rotation(rng, dim)
+    c = rng.standard_normal(dim)
+    j0 = O.energy(P.v)["Jgrad"]
+    j1 = O.energy(P.v @ Q.T + c)["Jgrad"]
+    assert j0 > 0
+    assert j1 == pytest.approx(j0, rel=1e-9)
+    # a pure rotation of the reference configuration stores no energy
+    assert abs(O.energy(P.coords @ Q.T + c)["Jgrad"]) < 1e-6 * O.C1 * O.vol.sum()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_neohooke_small_strain_limit(oracle_mod, dim):
+    """For F = I + s H, W / s^2 -> 2 C1 |sym H|^2 + D1 (tr H)^2 (linearised elasticity with
+    shear modulus 2 C1 and bulk term D1); pins both constants and the log term's sign."""
+    rng = np.random.default_rng(5)
+    P = S.neohooke_beam_2d(2, 2, 1.0, 1.0) if dim == 2 else S.neohooke_box_3d(1, 1, 1)
+    O = oracle_mod.Oracle(P)
+    for _ in range(3):
+        H = rng.standard_normal((dim, dim))
+        sym = 0.5 * (H + H.T)
+        lin = 2 * O.C1 * np.sum(sym * sym) + O.D1 * np.trace(H) ** 2
+        for s in (1e-3, 5e-4):
+            v = P.coords @ (np.eye(dim) + s * H).T
+            W = O.densities(v)[0]
+            assert W / s**2 == pytest.approx(lin, rel=30 * s)
+
+
+def test_neohooke_nonnegative_and_bad_elements(oracle_mod):
+    """W >= 0 whenever det F > 0 (AM-GM on the singular values); det F <= 0 gives +Inf
+    and a bad-element count."""
+    rng = np.random.default_rng(8)
+    P = S.neohooke_box_3d(3, 3, 3, amp=0.1)
+    O = oracle_mod.Oracle(P)
+    for _ in range(5):
+        A = np.eye(3) + 0.8 * rng.standard_normal((3, 3))
+        if np.linalg.det(A) <= 0:
+            continue
+        assert O.densities(P.coords @ A.T).min() >= 0
+    v = P.coords.copy()
+    v[:, 0] *= -1.0  # reflection: det F = -1 everywhere
+    r = O.energy(v)
+    assert r["nbad"] == P.ne and r["J"] == np.inf
+
+
+# ----------------------------------------------------------------------------- p-Laplacian
+def _five_point(n):
+    """Dirichlet 5-point Laplacian (4, -1) on the interior nodes of an n x n cell grid."""
+    m = n - 1
+    T = sp.diags([-np.ones(m - 1), 2 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1])
+    I = sp.identity(m)
+    return (sp.kron(I, T) + sp.kron(T, I)).tocsr()
+
+
+def test_p2_is_quadratic_form_with_5point_stencil(oracle_mod):
+    """p = 2: J = 1/2 v^T K v - b^T v with K the 5-point stencil and b_i = f h^2 at
+    interior nodes (consistent mass row sums)."""
+    n = 12
+    P = S.plaplace_square(n=n, p=2.0, f=-10.0, seed=1)
+    O = oracle_mod.Oracle(P)
+    vh = P.vhat()
+    K = _five_point(n)
+    r = O.energy(P.v)
+    assert r["Jgrad"] == pytest.approx(0.5 * vh @ (K @ vh), rel=1e-13)
+    bhat = O.b[O.free]
+    assert np.allclose(bhat, -10.0 / n**2, rtol=1e-13, atol=0)
+    assert r["J"] == pytest.approx(0.5 * vh @ (K @ vh) - bhat @ vh, rel=1e-13)
+    assert np.allclose(O.grad_exact(P.v), K @ vh - bhat, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("p", [1.5, 3.0, 5.0])
+def test_plaplace_homogeneity_and_euler(oracle_mod, p):
+    """J_grad(lam v) = |lam|^p J_grad(v); grad J_grad(v) . v = p J_grad(v) (v = 0 on the
+    Dirichlet boundary)."""
+    P = S.plaplace_square(n=10, p=p, seed=2)
+    O = oracle_mod.Oracle(P)
+    j1 = O.energy(P.v)["Jgrad"]
+    for lam in (0.5, -2.0):
+        assert O.energy(lam * P.v)["Jgrad"] == pytest.approx(abs(lam) ** p * j1, rel=1e-12)
+    g, _ = O.grad_exact_full(P.v)
+    assert g @ P.v.reshape(-1) == pytest.approx(p * j1, rel=1e-12)
+
+
+# ----------------------------------------------------------------------------- load vector
+def test_load_vector_integrates_linear_loads(oracle_mod):
+    """sum_i (M f)_i = integral of the P1 load; exact for a linear f on a box."""
+    P = S.neohooke_box_3d(5, 3, 4, 2.0, 0.6, 0.8)
+    O = oracle_mod.Oracle(P)
+    X = P.coords
+    f = np.stack([1.0 + X[:, 0], 2.0 - X[:, 1], 3.0 * X[:, 2]], axis=1)
+    P.load = f
+    O2 = oracle_mod.Oracle(P)
+    vol = 2.0 * 0.6 * 0.8
+    want = [vol * (1 + 1.0), vol * (2 - 0.3), vol * 3 * 0.4]
+    got = O2.b.reshape(-1, 3).sum(axis=0)
+    assert np.allclose(got, want, rtol=1e-13)
+    # b . v is the L2 product of P1 functions: integral of x * x over the box for f = v = x
+    P.load = np.stack([X[:, 0]] * 3, axis=1)
+    O3 = oracle_mod.Oracle(P)
+    v = np.stack([X[:, 0]] * 3, axis=1)
+    exact = 3 * (2.0**3 / 3) * 0.6 * 0.8
+    h2 = (2.0 / 5) ** 2
+    assert O3.b @ v.reshape(-1) == pytest.approx(exact, rel=2 * h2)
+
+
+# ----------------------------------------------------------------------------- gradients
+def _tiny_problems():
+    return [
+        S.plaplace_square(n=5, p=3.0, seed=4),
+        S.plaplace_square(n=4, p=1.5, seed=6),
+        S.neohooke_beam_2d(4, 3, 1.0, 0.6, amp=0.05, seed=7),
+        S.neohooke_box_3d(3, 2, 2, 1.0, 0.7, 0.6, amp=0.04, seed=9),
+    ]
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_exact_gradient_matches_brute_force(oracle_mod, idx):
+    """Exact gradient vs central differences of the whole energy J; error ~ eps^2."""
+    P = _tiny_problems()[idx]
+    O = oracle_mod.Oracle(P)
+    ge = O.grad_exact(P.v)
+    scale = np.abs(ge).max()
+    errs = []
+    for eps in (1e-3 * P.h, 0.5e-3 * P.h):
+        gb = O.grad_brute_fd(P.v, eps)
+        errs.append(np.abs(gb - ge).max() / scale)
+    assert errs[0] < 1e-5
+    assert 2.5 < errs[0] / errs[1] < 5.5, errs
+
+
+def test_gradient_translation_and_rotation_invariance(oracle_mod):
+    """Over all nodes and with f = 0: sum_i g_ij = 0 (translation) and sum_i g_i (x) v_i is
+    symmetric (rotation invariance of the Neo-Hookean energy)."""
+    P = S.neohooke_box_3d(4, 3, 3, 1.0, 0.6, 0.6, amp=0.03, seed=12)
+    O = oracle_mod.Oracle(P)
+    g, _ = O.grad_exact_full(P.v)
+    g = g.reshape(-1, 3)
+    s = np.abs(g).max()
+    assert np.abs(g.sum(axis=0)).max() < 1e-11 * s * P.nn
+    M = g.T @ P.v
+    assert np.abs(M - M.T).max() < 1e-11 * np.abs(M).max()
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_patch_fd_equals_brute_force_fd(oracle_mod, idx):
+    """Section 6.1: the patch sums reproduce the full-energy central difference. With a
+    dyadic field and step the perturbed values are exact, so only rounding separates them."""
+    P = _tiny_problems()[idx]
+    eps = 2.0 ** -14
+    v = np.round(P.v * 2.0**30) / 2.0**30
+    O = oracle_mod.Oracle(P)
+    gp, cond = O.grad_patch_fd(v, eps, with_cond=True)
+    gb = O.grad_brute_fd(v, eps)
+    Jabs = O.energy(v)["Jgrad"] + np.abs(O.b).sum()
+    tol = 64 * 2.0**-53 * (cond + 2 * Jabs) / (2 * eps) + 1e-12 * np.abs(gb)
+    assert np.all(np.abs(gp - gb) <= tol)
+    # and it approximates the exact gradient to O(eps^2)
+    ge = O.grad_exact(v)
+    assert np.abs(gp - ge).max() < 1e-5 * np.abs(ge).max()
+
+
+def test_patch_fd_sampled_positions(oracle_mod):
+    """Sampled evaluation returns the same values as the full sweep."""
+    P = S.neohooke_box_3d(3, 3, 2, amp=0.02, seed=1)
+    O = oracle_mod.Oracle(P)
+    full = O.grad_patch_fd(P.v, 1e-6)
+    pos = np.array([0, 5, 17, len(full) - 1])
+    assert np.array_equal(O.grad_patch_fd(P.v, 1e-6, sample=pos), full[pos])
