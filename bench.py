@@ -1,0 +1,191 @@
+"""Benchmark: elements/s of J + exact grad J for 3D Neo-Hookean on ~6M tetrahedra (one GPU).
+
+One step = one energy-and-gradient evaluation through the autograd hook
+(``p1_energy(vhat).backward()``: prepass, element energy + forces, patch gather, compensated
+finalize) on the 460x46x46-cube Kuhn box (5,840,160 tets), mixed precision, inputs resident in
+HBM. Prints ONE JSON line. Extra fields report the FP64 path, the patch central-difference
+gradient on the same mesh, the dominant kernel against the HBM roofline (HIP events inside the
+timed region) and the FP64 oracle timed on the host CPU.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="nh3d_box_6M")
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip FP64 and FD extra timings")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(info, prec):
+    """Compulsory HBM bytes of one J + exact grad J call, per kernel (each array touched once).
+
+    Element pass: connectivity 4(dim+1) B, B^-1 and |T| (dim^2 + 1) words, the nodal field
+    once per node, element forces (dim+1) d words written. Gather: patch entries 4 B each,
+    row pointer and row info 8 B per free node, forces read once, b read and g written per
+    free DOF. Prepass: per node the DOF map 4 B, vhat, x, b read once and the nodal field
+    written."""
+    ne, nn, nf, nfd, nnz = (info["ne"], info["nn"], info["n_free_nodes"], info["n_free_dofs"],
+                            info["nnz"])
+    dim, d = info["dim"], info["ncomp"]
+    w = 4 if prec == "mixed" else 8
+    ns = 4 if d == 3 else d
+    elem = ne * (4 * (dim + 1) + w * (dim * dim + 1) + w * (dim + 1) * d) + nn * ns * w
+    gather = 4 * nnz + 8 * nf + w * (dim + 1) * d * ne + 16 * nfd
+    prepass = nn * (4 + 8 * dim) + 16 * nfd + nn * ns * w
+    return {"k_element_force": elem, "k_gather": gather, "k_prepass": prepass}
+
+
+def cpu_baseline(prob, target_s=12.0):
+    """The FP64 oracle (single-threaded C loops) on the same mesh: energy + exact gradient,
+    repeated until about target_s seconds of CPU time."""
+    import oracle
+    oracle.build(force=False)
+    O = oracle.Oracle(prob)
+    reps, t = 0, 0.0
+    while t < target_s and reps < 20:
+        t0 = time.perf_counter()
+        O.energy(prob.v)
+        O.grad_exact(prob.v)
+        t += time.perf_counter() - t0
+        reps += 1
+    return {"value": prob.ne * reps / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} x (energy + exact gradient) over the full {prob.ne}-element mesh, "
+                      f"{t:.1f} s, single thread"}
+
+
+def main():
+    a = _args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print(json.dumps({"error": "single-GPU build: bench.py measures one MI355X only; "
+                          "multi-GPU sharding is described in DESIGN.md, not implemented",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+
+    import torch
+    import p1e_synth as S
+    import paper_2109_01158_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = S.config_problem(a.config)
+    modes = P.P1E_MIXED if a.prec == "mixed" else P.P1E_FP64
+    if not a.no_extras:
+        modes |= P.P1E_FP64 | P.P1E_FD
+    t0 = time.perf_counter()
+    mesh = P.Mesh.from_problem(prob, modes=modes, device=dev)
+    setup_s = time.perf_counter() - t0
+    info = mesh.info
+    vhat0 = torch.tensor(prob.vhat(), device=dev)
+    vhat = vhat0.clone().requires_grad_(True)
+
+    def step():
+        vhat.grad = None
+        J = P.p1_energy(vhat, mesh, a.prec)
+        J.backward()
+        return J
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    # timed region; the library brackets each of its kernels with HIP events on its stream
+    P.prof_reset()
+    P.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        J = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.prof_enable(False)
+    kern = P.prof_collect()
+    ms = (t1 - t0) * 1e3 / a.steps
+    value = info["ne"] / (ms * 1e-3)
+    Jv = float(J.item())
+
+    abytes = algorithmic_bytes(info, a.prec)
+    kstats = {k: {"launches": c, "avg_us": 1e3 * t / c} for k, (c, t) in kern.items()}
+    dom = max(kstats, key=lambda k: kstats[k]["avg_us"])
+    dom_bytes = abytes.get(dom)
+    achieved = dom_bytes / (kstats[dom]["avg_us"] * 1e-6) / 1e9 if dom_bytes else None
+    for k, s in kstats.items():
+        if k in abytes:
+            s["alg_GBs"] = abytes[k] / (s["avg_us"] * 1e-6) / 1e9
+    step_bytes = sum(abytes.values())
+
+    extras = {}
+    if not a.no_extras:
+        # FP64 J + grad J and the FP64 patch central differences on the same mesh
+        g = torch.empty_like(vhat0)
+        out3 = torch.empty(3, dtype=torch.float64, device=dev)
+        flag = torch.empty(1, dtype=torch.int32, device=dev)
+        for name, fn in (("fp64_jgrad", lambda: mesh.grad_exact(vhat0, "fp64", g=g, out3=out3,
+                                                                  flag=flag)),
+                         ("patch_fd_fp64", lambda: mesh.grad_patch_fd(vhat0, prob.eps))):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            n = max(3, a.steps // 2)
+            t0 = time.perf_counter()
+            for _ in range(n):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / n
+            extras[name] = {"elements_per_s": info["ne"] / dt, "ms": dt * 1e3}
+
+    out = {
+        "metric": "elements/s for J+grad J (3D Neo-Hookean, 6M tets)",
+        "value": value,
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32+fp64" if a.prec == "mixed" else "fp64",
+        "data": "synthetic (seeded mesh and displacement field)",
+        "config": {
+            "workload": f"{a.config}: 3D Neo-Hookean box [0,1]x[0,0.1]^2, 460x46x46 cubes x 6 Kuhn "
+                        f"tets, E=2e8 nu=0.3, x=0 face clamped, u=amp*U[-1,1] (amp={prob.amp:.3g}); "
+                        f"J + exact grad J through the autograd hook, {a.prec}",
+            "ne": info["ne"], "nn": info["nn"], "n_free_dofs": info["n_free_dofs"],
+            "patch_incidences": info["nnz"], "parallelism": "single GPU",
+        },
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": None, "alg_bytes_per_launch": dom_bytes,
+                     "alg_bytes_per_element": dom_bytes / info["ne"] if dom_bytes else None},
+        "step_alg_bytes_per_element": step_bytes / info["ne"],
+        "step_alg_GBs": step_bytes / (ms * 1e-3) / 1e9,
+        "kernels": kstats,
+        "J": Jv,
+        "setup_s": setup_s,
+        "extras": extras,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * p1e.h -- C ABI of libp1e: P1 finite-element energies and their gradients on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Moskovka & Valdman, "Fast MATLAB evaluation of nonlinear energies using FEM in 2D
+ * and 3D: Nodal elements" (arXiv 2109.01158). For a P1 (linear nodal) field v on a triangle
+ * or tetrahedron mesh the library evaluates, for every element at once,
+ *
+ *     J(v) = J_grad(v) - b . v,   J_grad(v) = sum_T |T| W(F_T(v))      (Sections 1, 3.1, 3.2)
+ *
+ * with b = M f (consistent P1 mass matrix times the nodal load), and the gradient of J over
+ * every free degree of freedom at once, either exactly (Section 6.2) or by patch central
+ * differences (Section 6.1). Densities: compressible Neo-Hookean (eq. neoHook, 2D and 3D)
+ * and the scalar p-Laplacian (eq. pLaplacian).
+ *
+ * Conventions shared by every entry point
+ *   - DOF numbering: DOF n = d*i + j for node i and component j (Section 5, eq. bvvectors).
+ *     A DOF is free unless the mesh description prescribes it (Dirichlet). The vector
+ *     "vhat" holds the free DOFs of v in ascending n; gradients come back in the same order.
+ *   - Sign of the linear part: J = J_grad - b.v, so dJ/dv = dJ_grad/dv - b.
+ *   - Neo-Hookean v is the deformation (v = x is the undeformed state); the Dirichlet
+ *     values of v are taken from the mesh description.
+ *   - An element with det F <= 0 or a non-finite density is "bad": the energy becomes +Inf
+ *     and the number of bad elements is written to *flag. Gradients are then undefined.
+ *   - Device pointers: every pointer named *_dev, vhat, g, out3, flag is device memory on the
+ *     current HIP device; "stream" is a hipStream_t (NULL = default stream). Compute entry
+ *     points only enqueue work on that stream and return without synchronising.
+ *   - Memory: the library never allocates device memory. p1e_mesh_bind places the mesh and
+ *     all scratch arrays in one caller-owned device buffer that the caller keeps alive until
+ *     p1e_mesh_destroy (or a re-bind). Host arrays passed to p1e_mesh_create are copied.
+ *   - Threads: a mesh handle is not thread-safe, and two calls on the same mesh must not
+ *     overlap on the device (they share its scratch arrays); distinct handles are independent.
+ *   - Errors: entry points return P1E_OK (0) or a negative status; p1e_last_error() gives a
+ *     thread-local message for the last failure on the calling thread. No C++ exception
+ *     crosses this interface.
+ */
+#ifndef P1E_H
+#define P1E_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define P1E_OK 0
+#define P1E_EINVAL (-1)  /* bad argument (null pointer, dimension, index out of range, ...) */
+#define P1E_EDEGEN (-2)  /* a degenerate element (zero size) in the mesh */
+#define P1E_ENOMEM (-3)  /* device buffer too small for what was asked */
+#define P1E_EHIP (-4)    /* a HIP runtime call or kernel launch failed */
+#define P1E_EDOMAIN (-5) /* no admissible point (bad elements) where one was required */
+#define P1E_EBUSY (-6)   /* queue full */
+#define P1E_ESTATE (-7)  /* call made in the wrong state (e.g. mesh not bound for a mode) */
+
+/* ------------------------------------------------------------------ energy kinds */
+#define P1E_PLAPLACE 1 /* W(g) = |g|^p / p, scalar field (d = 1), p > 1 (eq. pLaplacian) */
+#define P1E_NEOHOOKE 2 /* W(F) = C1 (|F|^2 - dim - 2 log det F) + D1 (det F - 1)^2,
+                          vector field (d = dim) (eq. neoHook) */
+
+/* ------------------------------------------------------------------ precision modes */
+/* Each compute call names one mode; p1e_mesh_bind takes a bit mask of the modes to prepare. */
+#define P1E_FP64 1  /* all element arithmetic, sums and gradients in FP64 */
+#define P1E_MIXED 2 /* element arithmetic in FP32 on the displacement gradient; log det F,
+                       the energy sum (compensated) and gradient accumulation in FP64 */
+#define P1E_FD 4    /* bind-only bit: arrays for the patch central-difference gradient (FP64) */
+
+typedef struct p1e_mesh p1e_mesh;
+
+/* Mesh and problem description (all arrays are host memory, row-major, 0-based). */
+typedef struct p1e_mesh_desc {
+  int32_t dim;   /* 2 (triangles) or 3 (tetrahedra) */
+  int32_t ncomp; /* d: 1 for P1E_PLAPLACE, dim for P1E_NEOHOOKE */
+  int32_t kind;  /* P1E_PLAPLACE or P1E_NEOHOOKE */
+  int32_t reserved;
+  int64_t nn; /* number of nodes, 1 <= nn < 2^28 */
+  int64_t ne; /* number of elements, 0 <= ne < 2^29 */
+  const int32_t *conn;       /* [ne][dim+1] vertex indices, distinct, in [0, nn) */
+  const double *coords;      /* [nn][dim] node coordinates */
+  const uint8_t *dirichlet;  /* [nn][ncomp], nonzero = prescribed DOF; NULL = none */
+  const double *dirichlet_values; /* [nn][ncomp] values of prescribed DOFs; NULL = 0 */
+  const double *load;        /* [nn][ncomp] nodal values of the P1 load f; NULL = 0 */
+  double p;                  /* p-Laplacian exponent, p > 1 */
+  double C1, D1;             /* Neo-Hookean constants (C1 = mu/2, D1 = K/2 in Benchmark 2) */
+} p1e_mesh_desc;
+
+typedef struct p1e_mesh_info {
+  int64_t nn, ne;
+  int64_t n_free_nodes; /* nodes with at least one free DOF (Remark 1) */
+  int64_t n_free_dofs;  /* length of vhat and of gradients */
+  int64_t nnz;          /* patch incidences of free nodes: sum over free nodes of |T^i| */
+  int32_t dim, ncomp, kind, max_valence; /* max_valence = largest |T^i| */
+  double total_volume, min_volume, max_volume;
+  double dirichlet_bv; /* sum over prescribed DOFs of b_n v_n (constant part of b.v) */
+  uint64_t alignment;  /* required alignment of the bound device buffer (bytes) */
+} p1e_mesh_info;
+
+/* Build a mesh handle: validates the description, computes element geometry (|T| and basis
+ * gradients, Section 4.1), the free-node patch lists (Section 4.2, stored as one row of
+ * (element, local vertex) pairs per free node), the DOF maps and b = M f (Section 3.2).
+ * Host-only; needs no GPU. Returns P1E_EINVAL or P1E_EDEGEN on bad input. */
+int p1e_mesh_create(const p1e_mesh_desc *desc, p1e_mesh **out);
+
+/* Release the handle (host memory only; the bound device buffer belongs to the caller). */
+void p1e_mesh_destroy(p1e_mesh *mesh);
+
+int p1e_mesh_get_info(const p1e_mesh *mesh, p1e_mesh_info *out);
+
+/* Device bytes p1e_mesh_bind needs for the modes in mask (P1E_FP64 | P1E_MIXED | P1E_FD).
+ * Returns 0 for an invalid mask or handle. */
+uint64_t p1e_workspace_bytes(const p1e_mesh *mesh, int mode_mask);
+
+/* Lay the mesh arrays and scratch out in the caller-owned device buffer dev_buf (aligned to
+ * info.alignment, at least p1e_workspace_bytes(mesh, mode_mask) bytes) and upload them on
+ * stream. Synchronises stream before returning. P1E_ENOMEM if bytes is too small. */
+int p1e_mesh_bind(p1e_mesh *mesh, void *dev_buf, uint64_t bytes, int mode_mask, void *stream);
+
+/* Energy (Section 5). vhat: [n_free_dofs] FP64. out3: 3 doubles {J, J_grad, b.v}.
+ * flag: 1 int32 = number of bad elements. prec: P1E_FP64 or P1E_MIXED (must be bound). */
+int p1e_energy(p1e_mesh *mesh, const double *vhat, int prec, double *out3, int32_t *flag,
+               void *stream);
+
+/* Exact gradient (Section 6.2): g[n] = dJ/dv_n for the free DOFs, FP64, in vhat order.
+ * Element forces |T| dW/dF grad phi are formed per element and gathered per free node over
+ * its patch (no atomics). out3 (nullable) receives the energy of the same call, as in
+ * p1e_energy; flag receives the bad-element count. */
+int p1e_grad_exact(p1e_mesh *mesh, const double *vhat, int prec, double *g, double *out3,
+                   int32_t *flag, void *stream);
+
+/* Patch central differences (Section 6.1, eqs. CD, CDS, sumpatch), FP64 throughout:
+ * g[n] = [sum_{T in T^(n)} |T| W(F_T(v + eps e_n)) - sum |T| W(F_T(v - eps e_n))]/(2 eps) - b_n
+ * with an absolute step eps > 0 for every DOF. Only the perturbed row of F_T changes
+ * (F_T +- eps e_j (x) grad phi_l). Needs the P1E_FD bind bit. flag as above. */
+int p1e_grad_patch_fd(p1e_mesh *mesh, const double *vhat, double eps, double *g,
+                      int32_t *flag, void *stream);
+
+/* Thread-local message of the last failure ("" if none). */
+const char *p1e_last_error(void);
+
+/* ------------------------------------------------------------------ kernel timing
+ * For measurement harnesses: while enabled, every kernel the library launches is bracketed
+ * by HIP events on its launch stream. p1e_prof_collect synchronises the recorded events and
+ * returns, per kernel name, the launch count and the summed duration in milliseconds
+ * (names are written as one '\n'-separated string into names[names_cap]). */
+int p1e_prof_enable(int on);
+int p1e_prof_reset(void);
+int p1e_prof_collect(char *names, int64_t names_cap, int64_t *counts, double *total_ms,
+                     int32_t cap, int32_t *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P1E_H */

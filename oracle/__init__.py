@@ -71,7 +71,7 @@ def _load():
         lib.orc_grad_exact.restype = i64
         lib.orc_patches.argtypes = [P, vp, vp]
         lib.orc_patches.restype = None
-        lib.orc_grad_patch_fd.argtypes = [P, vp, vp, vp, vp, vp, dbl, i64, vp, vp, vp]
+        lib.orc_grad_patch_fd.argtypes = [P, vp, vp, vp, vp, vp, dbl, i64, vp, vp, vp, vp]
         lib.orc_grad_patch_fd.restype = i64
         _lib = lib
     return _lib
@@ -179,18 +179,20 @@ class Oracle:
 
     def grad_patch_fd(self, v, eps, sample=None, with_cond=False):
         """Patch central differences on free DOFs (or on free-DOF positions ``sample``),
-        minus b. With ``with_cond`` also returns the per-DOF rounding scale."""
+        minus b. With ``with_cond`` also returns the per-DOF rounding scales
+        (cond = sum |T|(|W+|_abs + |W-|_abs), gabs = sum |T||W+ - W-|/(2 eps))."""
         v = self._full(v).copy()
         ptr, ent = self.patches()
         pos = np.arange(self.free_dofs.size) if sample is None else np.asarray(sample, np.int64)
         dofs = np.ascontiguousarray(self.free_dofs[pos])
         g = np.zeros(dofs.size)
         cond = np.zeros(dofs.size)
+        gabs = np.zeros(dofs.size)
         self.lib.orc_grad_patch_fd(ctypes.byref(self._P), _ptr(v), _ptr(self.vol),
                                    _ptr(self.dphi), _ptr(ptr), _ptr(ent), float(eps),
-                                   dofs.size, _ptr(dofs), _ptr(g), _ptr(cond))
+                                   dofs.size, _ptr(dofs), _ptr(g), _ptr(cond), _ptr(gabs))
         g = g - self.b[dofs]
-        return (g, cond) if with_cond else g
+        return (g, cond, gabs) if with_cond else g
 
     def grad_brute_fd(self, v, eps):
         """Central differences of the full energy J (all elements re-evaluated): tiny

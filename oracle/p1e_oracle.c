@@ -286,53 +286,58 @@ void orc_patches(const orc_problem *P, int64_t *patch_ptr, int64_t *patch_elem) 
 }
 
 /* ---------------------------------------------------------------- patch central differences */
+/* |W|_abs: the sum of the magnitudes of the density's terms (rounding scale of W) */
+static double density_abs(const orc_problem *P, double F[3][3], double W) {
+  if (P->kind != ORC_NEOHOOKE) return fabs(W);
+  const int dim = P->dim;
+  double I1 = 0.0;
+  for (int j = 0; j < dim; ++j)
+    for (int m = 0; m < dim; ++m) I1 += F[j][m] * F[j][m];
+  double det = det_mat(dim, F);
+  return P->C1 * (I1 + dim + 2.0 * fabs(log(det))) + P->D1 * (det - 1.0) * (det - 1.0);
+}
+
 /* For every DOF listed in dofs[0..ndofs) (global DOF index n = d*i + j), with e_n the n-th unit
  * vector:  g = [ sum_{T in T^i} |T| W(F_T(v + eps e_n)) - sum_{T in T^i} |T| W(F_T(v - eps e_n)) ]
  *              / (2 eps).
- * F_T(v +- eps e_n) is recomputed from the perturbed nodal values by eq. (Dv). The optional
- * cond[] receives sum_{T in T^i} |T| (|W+|_abs + |W-|_abs), the magnitude of the summed terms,
- * with |W|_abs the sum of the absolute values of the density's terms (rounding scale).
+ * F_T(v +- eps e_n) is recomputed from the perturbed nodal values by eq. (Dv); the two patch
+ * sums are accumulated separately (Neumaier, ascending element order) and then differenced.
+ * Optional rounding scales per DOF: cond[q] = sum_T |T| (|W+|_abs + |W-|_abs) and
+ * gabs[q] = sum_T |T| |W+ - W-| / (2 eps).
  * v is modified during the call and restored. Returns the number of bad evaluations. */
 int64_t orc_grad_patch_fd(const orc_problem *P, double *v, const double *vol,
                           const double *dphi, const int64_t *patch_ptr,
                           const int64_t *patch_elem, double eps, int64_t ndofs,
-                          const int64_t *dofs, double *g, double *cond) {
-  const int dim = P->dim, k = dim + 1, d = P->ncomp;
+                          const int64_t *dofs, double *g, double *cond, double *gabs) {
+  const int dim = P->dim, k = dim + 1;
+  const int d = P->ncomp;
   int64_t nbad = 0;
   for (int64_t q = 0; q < ndofs; ++q) {
     const int64_t n = dofs[q];
     const int64_t i = n / d;
     const double v0 = v[n];
-    double S[2];
-    double C = 0.0;
-    for (int sgn = 0; sgn < 2; ++sgn) {
-      v[n] = (sgn == 0) ? v0 + eps : v0 - eps;
-      orc_acc acc = {0.0, 0.0};
-      for (int64_t t = patch_ptr[i]; t < patch_ptr[i + 1]; ++t) {
-        const int64_t e = patch_elem[t];
-        double F[3][3];
-        element_F(P, v, P->conn + e * k, dphi + e * k * dim, F);
-        int bad = 0;
-        double W = density(P, F, &bad);
-        if (bad) { ++nbad; continue; }
-        acc_add(&acc, vol[e] * W);
-        double Wabs;
-        if (P->kind == ORC_NEOHOOKE) {
-          double I1 = 0.0;
-          for (int j = 0; j < dim; ++j)
-            for (int m = 0; m < dim; ++m) I1 += F[j][m] * F[j][m];
-          double det = det_mat(dim, F);
-          Wabs = P->C1 * (I1 + dim + 2.0 * fabs(log(det))) + P->D1 * (det - 1.0) * (det - 1.0);
-        } else {
-          Wabs = fabs(W);
-        }
-        C += vol[e] * Wabs;
-      }
-      S[sgn] = acc_result(&acc);
+    orc_acc Sp = {0.0, 0.0}, Sm = {0.0, 0.0};
+    double C = 0.0, A = 0.0;
+    for (int64_t t = patch_ptr[i]; t < patch_ptr[i + 1]; ++t) {
+      const int64_t e = patch_elem[t];
+      double Fp[3][3], Fm[3][3];
+      v[n] = v0 + eps;
+      element_F(P, v, P->conn + e * k, dphi + e * k * dim, Fp);
+      v[n] = v0 - eps;
+      element_F(P, v, P->conn + e * k, dphi + e * k * dim, Fm);
+      v[n] = v0;
+      int bad = 0;
+      double Wp = density(P, Fp, &bad);
+      double Wm = density(P, Fm, &bad);
+      if (bad) { ++nbad; continue; }
+      acc_add(&Sp, vol[e] * Wp);
+      acc_add(&Sm, vol[e] * Wm);
+      C += vol[e] * (density_abs(P, Fp, Wp) + density_abs(P, Fm, Wm));
+      A += fabs(vol[e] * (Wp - Wm)) / (2.0 * eps);
     }
-    v[n] = v0;
-    g[q] = (S[0] - S[1]) / (2.0 * eps);
+    g[q] = (acc_result(&Sp) - acc_result(&Sm)) / (2.0 * eps);
     if (cond) cond[q] = C;
+    if (gabs) gabs[q] = A;
   }
   return nbad;
 }

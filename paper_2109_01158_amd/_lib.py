@@ -1,0 +1,104 @@
+"""ctypes view of libp1e.so (declarations in include/p1e.h).
+
+torch is imported first so that the process has exactly one HIP runtime: libp1e.so links
+against libamdhip64.so.7, which then resolves to the runtime torch already loaded.
+The product has no fallback: if the library is missing, importing this module fails.
+"""
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime libp1e.so binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libp1e.so")
+
+P1E_OK = 0
+P1E_EINVAL = -1
+P1E_EDEGEN = -2
+P1E_ENOMEM = -3
+P1E_EHIP = -4
+P1E_EDOMAIN = -5
+P1E_EBUSY = -6
+P1E_ESTATE = -7
+
+P1E_PLAPLACE = 1
+P1E_NEOHOOKE = 2
+
+P1E_FP64 = 1
+P1E_MIXED = 2
+P1E_FD = 4
+
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EDEGEN", -3: "ENOMEM", -4: "EHIP", -5: "EDOMAIN",
+                -6: "EBUSY", -7: "ESTATE"}
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("ncomp", ctypes.c_int32), ("kind", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("nn", ctypes.c_int64), ("ne", ctypes.c_int64),
+        ("conn", ctypes.c_void_p), ("coords", ctypes.c_void_p), ("dirichlet", ctypes.c_void_p),
+        ("dirichlet_values", ctypes.c_void_p), ("load", ctypes.c_void_p),
+        ("p", ctypes.c_double), ("C1", ctypes.c_double), ("D1", ctypes.c_double),
+    ]
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [
+        ("nn", ctypes.c_int64), ("ne", ctypes.c_int64), ("n_free_nodes", ctypes.c_int64),
+        ("n_free_dofs", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("dim", ctypes.c_int32), ("ncomp", ctypes.c_int32), ("kind", ctypes.c_int32),
+        ("max_valence", ctypes.c_int32),
+        ("total_volume", ctypes.c_double), ("min_volume", ctypes.c_double),
+        ("max_volume", ctypes.c_double), ("dirichlet_bv", ctypes.c_double),
+        ("alignment", ctypes.c_uint64),
+    ]
+
+
+class P1EError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"p1e status {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libp1e.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2109_01158_amd.build` (there is no fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                              ctypes.c_double)
+    sig = {
+        "p1e_mesh_create": ([ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)], ctypes.c_int),
+        "p1e_mesh_destroy": ([vp], None),
+        "p1e_mesh_get_info": ([vp, ctypes.POINTER(MeshInfo)], ctypes.c_int),
+        "p1e_workspace_bytes": ([vp, ctypes.c_int], u64),
+        "p1e_mesh_bind": ([vp, vp, u64, ctypes.c_int, vp], ctypes.c_int),
+        "p1e_energy": ([vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
+        "p1e_grad_exact": ([vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
+        "p1e_grad_patch_fd": ([vp, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "p1e_last_error": ([], ctypes.c_char_p),
+        "p1e_prof_enable": ([ctypes.c_int], ctypes.c_int),
+        "p1e_prof_reset": ([], ctypes.c_int),
+        "p1e_prof_collect": ([vp, i64, vp, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def check(status):
+    """Raise P1EError for a negative status, with the library's thread-local message."""
+    if status != P1E_OK:
+        raise P1EError(status, lib().p1e_last_error().decode(errors="replace"))
+    return status

@@ -1,0 +1,205 @@
+"""Python binding of libp1e: argument marshalling only.
+
+The functions ``mesh_create``, ``mesh_get_info``, ``workspace_bytes``, ``mesh_bind``,
+``energy``, ``grad_exact`` and ``grad_patch_fd`` mirror the C entry points ``p1e_*`` one to
+one. :class:`Mesh` bundles a handle with its torch-owned device buffer. Every step of the
+computation runs in libp1e's HIP kernels; torch only provides device memory and streams.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import P1E_FD, P1E_FP64, P1E_MIXED, P1E_NEOHOOKE, P1E_PLAPLACE, check
+
+PREC = {"fp64": P1E_FP64, "mixed": P1E_MIXED, P1E_FP64: P1E_FP64, P1E_MIXED: P1E_MIXED}
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if (t is not None and t.numel() > 0) else None
+
+
+def _stream_ptr(stream, device):
+    s = torch.cuda.current_stream(device) if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def neohooke_constants(E, nu):
+    """Benchmark 2: C1 = mu/2, D1 = K/2, mu = E/(2(1+nu)), K = E/(3(1-2nu))."""
+    mu = E / (2.0 * (1.0 + nu))
+    K = E / (3.0 * (1.0 - 2.0 * nu))
+    return mu / 2.0, K / 2.0
+
+
+# ------------------------------------------------------------------ 1:1 entry points
+def mesh_create(dim, kind, conn, coords, dirichlet=None, dirichlet_values=None, load=None,
+                p=2.0, C1=0.0, D1=0.0):
+    """p1e_mesh_create. kind: "plaplace" | "neohooke". Arrays are host numpy; returns an
+    opaque handle (int)."""
+    k = P1E_NEOHOOKE if kind in ("neohooke", P1E_NEOHOOKE) else P1E_PLAPLACE
+    ncomp = dim if k == P1E_NEOHOOKE else 1
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    dmask = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    dval = None if dirichlet_values is None else np.ascontiguousarray(dirichlet_values,
+                                                                     dtype=np.float64)
+    f = None if load is None else np.ascontiguousarray(load, dtype=np.float64)
+    desc = L.MeshDesc(dim, ncomp, k, 0, coords.shape[0] if coords.ndim else 0,
+                      conn.shape[0] if conn.size else 0,
+                      _ptr(conn) if conn.size else None, _ptr(coords), _ptr(dmask), _ptr(dval),
+                      _ptr(f), float(p), float(C1), float(D1))
+    h = ctypes.c_void_p()
+    check(L.lib().p1e_mesh_create(ctypes.byref(desc), ctypes.byref(h)))
+    return h.value
+
+
+def mesh_destroy(handle):
+    L.lib().p1e_mesh_destroy(ctypes.c_void_p(handle))
+
+
+def mesh_get_info(handle):
+    info = L.MeshInfo()
+    check(L.lib().p1e_mesh_get_info(ctypes.c_void_p(handle), ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in L.MeshInfo._fields_}
+
+
+def workspace_bytes(handle, mode_mask):
+    return int(L.lib().p1e_workspace_bytes(ctypes.c_void_p(handle), int(mode_mask)))
+
+
+def mesh_bind(handle, buf, nbytes, mode_mask, stream=None):
+    """p1e_mesh_bind on a device buffer given as a torch uint8 tensor (or raw pointer)."""
+    ptr = buf.data_ptr() if isinstance(buf, torch.Tensor) else int(buf)
+    dev = buf.device if isinstance(buf, torch.Tensor) else None
+    check(L.lib().p1e_mesh_bind(ctypes.c_void_p(handle), ctypes.c_void_p(ptr), int(nbytes),
+                                int(mode_mask), _stream_ptr(stream, dev)))
+
+
+def energy(handle, vhat, prec, out3, flag, stream=None):
+    """p1e_energy on device tensors: vhat f64[n_free_dofs], out3 f64[3], flag i32[1]."""
+    check(L.lib().p1e_energy(ctypes.c_void_p(handle), _dptr(vhat), PREC[prec], _dptr(out3),
+                             _dptr(flag), _stream_ptr(stream, out3.device)))
+
+
+def grad_exact(handle, vhat, prec, g, out3, flag, stream=None):
+    """p1e_grad_exact on device tensors; out3 may be None."""
+    check(L.lib().p1e_grad_exact(ctypes.c_void_p(handle), _dptr(vhat), PREC[prec], _dptr(g),
+                                 _dptr(out3), _dptr(flag), _stream_ptr(stream, flag.device)))
+
+
+def grad_patch_fd(handle, vhat, eps, g, flag, stream=None):
+    """p1e_grad_patch_fd on device tensors."""
+    check(L.lib().p1e_grad_patch_fd(ctypes.c_void_p(handle), _dptr(vhat), float(eps), _dptr(g),
+                                    _dptr(flag), _stream_ptr(stream, flag.device)))
+
+
+# ------------------------------------------------------------------ kernel timing
+def prof_enable(on=True):
+    check(L.lib().p1e_prof_enable(1 if on else 0))
+
+
+def prof_reset():
+    check(L.lib().p1e_prof_reset())
+
+
+def prof_collect():
+    """{kernel name: (launches, total ms)} for the launches recorded while enabled."""
+    cap = 64
+    names = ctypes.create_string_buffer(8192)
+    counts = (ctypes.c_int64 * cap)()
+    ms = (ctypes.c_double * cap)()
+    n = ctypes.c_int32(0)
+    check(L.lib().p1e_prof_collect(names, 8192, counts, ms, cap, ctypes.byref(n)))
+    keys = names.value.decode().split("\n")[: n.value]
+    return {k: (counts[i], ms[i]) for i, k in enumerate(keys)}
+
+
+# ------------------------------------------------------------------ convenience wrapper
+class Mesh:
+    """A mesh handle bound to a torch-owned device buffer.
+
+    ``modes`` is a mask of P1E_FP64 | P1E_MIXED | P1E_FD: which precisions the buffer holds
+    arrays for.
+    """
+
+    def __init__(self, dim, kind, conn, coords, dirichlet=None, dirichlet_values=None,
+                 load=None, p=2.0, C1=0.0, D1=0.0, modes=P1E_FP64 | P1E_MIXED,
+                 device="cuda", stream=None):
+        self.handle = mesh_create(dim, kind, conn, coords, dirichlet, dirichlet_values, load,
+                                  p, C1, D1)
+        self.info = mesh_get_info(self.handle)
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.modes = modes
+        self.nbytes = workspace_bytes(self.handle, modes)
+        align = int(self.info["alignment"])
+        self._buf = torch.empty(self.nbytes + align, dtype=torch.uint8, device=self.device)
+        off = (-self._buf.data_ptr()) % align
+        self.buf = self._buf[off: off + self.nbytes]
+        with torch.cuda.device(self.device):
+            mesh_bind(self.handle, self.buf, self.nbytes, modes, stream)
+        self.n_free_dofs = int(self.info["n_free_dofs"])
+
+    @classmethod
+    def from_problem(cls, prob, modes=P1E_FP64 | P1E_MIXED, device="cuda", stream=None):
+        """Build from an object with the fields of ``p1e_synth.Problem``."""
+        if prob.kind == "neohooke":
+            C1, D1 = neohooke_constants(prob.E, prob.nu)
+            p = 2.0
+        else:
+            C1 = D1 = 0.0
+            p = prob.p
+        return cls(prob.dim, prob.kind, prob.conn, prob.coords, prob.dirichlet,
+                   prob.dirichlet_values, prob.load, p=p, C1=C1, D1=D1, modes=modes,
+                   device=device, stream=stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mesh_destroy(self.handle)
+            self.handle = None
+            self._buf = self.buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_vhat(self, vhat):
+        if (not isinstance(vhat, torch.Tensor) or vhat.dtype != torch.float64
+                or vhat.device != self.device or not vhat.is_contiguous()
+                or vhat.numel() != self.n_free_dofs):
+            raise ValueError(f"vhat must be a contiguous float64 tensor of {self.n_free_dofs} "
+                             f"entries on {self.device}")
+
+    def energy(self, vhat, prec="mixed", stream=None):
+        """Returns (out3 = [J, J_grad, b.v] f64 tensor, flag i32[1]) -- asynchronous."""
+        self._check_vhat(vhat)
+        out3 = torch.empty(3, dtype=torch.float64, device=self.device)
+        flag = torch.empty(1, dtype=torch.int32, device=self.device)
+        energy(self.handle, vhat, prec, out3, flag, stream)
+        return out3, flag
+
+    def grad_exact(self, vhat, prec="mixed", stream=None, g=None, out3=None, flag=None):
+        """Returns (g, out3, flag): exact dJ/dvhat, the energy of the same call, bad count."""
+        self._check_vhat(vhat)
+        g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device) if g is None else g
+        out3 = torch.empty(3, dtype=torch.float64, device=self.device) if out3 is None else out3
+        flag = torch.empty(1, dtype=torch.int32, device=self.device) if flag is None else flag
+        grad_exact(self.handle, vhat, prec, g, out3, flag, stream)
+        return g, out3, flag
+
+    def grad_patch_fd(self, vhat, eps, stream=None):
+        """Returns (g, flag): patch central-difference gradient (FP64)."""
+        self._check_vhat(vhat)
+        g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device)
+        flag = torch.empty(1, dtype=torch.int32, device=self.device)
+        grad_patch_fd(self.handle, vhat, eps, g, flag, stream)
+        return g, flag

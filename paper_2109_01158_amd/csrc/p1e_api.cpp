@@ -1,0 +1,525 @@
+// p1e_api.cpp -- host side of libp1e: argument validation, mesh setup (element geometry,
+// free-node patch rows, DOF maps, load vector), device buffer layout and the C entry points.
+//
+// Setup follows Sections 3-4 of Moskovka & Valdman (arXiv 2109.01158): element sizes and
+// basis gradients (Section 4.1), nodal patches of free nodes (Section 4.2, Remark 1) and the
+// linear term b = M f (Section 3.2). The paper stores each patch as long matrices that
+// replicate element data per patch row; here a patch row is one 4-byte (element, local
+// vertex) pair and element data is stored once, so the gradient gathers through it.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "p1e_internal.h"
+
+namespace p1e {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// ------------------------------------------------------------------------- kernel timing
+namespace {
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+struct ProfAgg {
+  std::string name;
+  int64_t count;
+  double ms;
+};
+std::vector<ProfAgg> g_prof_agg;
+thread_local ProfRec *g_prof_open = nullptr;
+thread_local ProfRec g_prof_cur;
+}  // namespace
+
+void prof_begin(const char *name, hipStream_t s) {
+  if (!g_prof_on) return;
+  g_prof_cur.name = name;
+  if (hipEventCreate(&g_prof_cur.a) != hipSuccess) return;
+  if (hipEventCreate(&g_prof_cur.b) != hipSuccess) {
+    (void)hipEventDestroy(g_prof_cur.a);
+    return;
+  }
+  (void)hipEventRecord(g_prof_cur.a, s);
+  g_prof_open = &g_prof_cur;
+}
+
+void prof_end(hipStream_t s) {
+  if (!g_prof_on || g_prof_open == nullptr) return;
+  (void)hipEventRecord(g_prof_cur.b, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_pending.push_back(g_prof_cur);
+  g_prof_open = nullptr;
+}
+
+// ------------------------------------------------------------------------- buffer layout
+static uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+static int node_stride(int d) { return d == 3 ? 4 : d; }
+
+uint64_t u_bytes(const p1e_mesh *m, int modes) {
+  uint64_t es = (modes & (P1E_FP64 | P1E_FD)) ? 8 : 4;
+  return (uint64_t)m->nn * node_stride(m->d) * es;
+}
+
+uint64_t r_bytes(const p1e_mesh *m, int modes) {
+  uint64_t es = (modes & (P1E_FP64 | P1E_FD)) ? 8 : 4;
+  return (uint64_t)m->ne * m->k * m->d * es;
+}
+
+int64_t part_slots(const p1e_mesh *m) {
+  int64_t n = std::max<int64_t>(nblocks(m->ne), nblocks(m->nn));
+  return std::max<int64_t>(n, 1);
+}
+
+struct Layout {
+  uint64_t node_info, xref, vD, bhat, conn, geo64, geo32, row_ptr, ent, row_info, u, r, part,
+      badp, total;
+};
+
+static Layout make_layout(const p1e_mesh *m, int modes) {
+  Layout L{};
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = off;
+    off = align_up(off + std::max<uint64_t>(bytes, 1));
+    return at;
+  };
+  const int dd = m->dim * m->dim + 1;
+  L.node_info = take(4ull * m->nn);
+  L.xref = take(m->kind == P1E_NEOHOOKE ? 8ull * m->nn * m->dim : 0);
+  L.vD = take(8ull * m->nn * m->d);
+  L.bhat = take(8ull * m->nfd);
+  L.conn = take(4ull * m->ne * m->k);
+  L.geo64 = take((modes & (P1E_FP64 | P1E_FD)) ? 8ull * dd * m->ne : 0);
+  L.geo32 = take((modes & P1E_MIXED) ? 4ull * dd * m->ne : 0);
+  L.row_ptr = take(4ull * (m->nf + 1));
+  L.ent = take(4ull * m->nnz);
+  L.row_info = take(4ull * m->nf);
+  L.u = take(u_bytes(m, modes));
+  L.r = take(r_bytes(m, modes));
+  L.part = take(16ull * 2 * part_slots(m));  // element partials, then node partials
+  L.badp = take(4ull * part_slots(m));
+  L.total = off;
+  return L;
+}
+
+}  // namespace p1e
+
+using namespace p1e;
+
+// ------------------------------------------------------------------------- setup helpers
+namespace {
+
+// Neumaier-compensated accumulator for host sums
+struct HostAcc {
+  double s = 0.0, c = 0.0;
+  void add(double x) {
+    double t = s + x;
+    c += (std::fabs(s) >= std::fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+
+// Inverse of the edge matrix B = [x1-x0, ..., x_dim-x0] (columns) via its adjugate.
+// Returns det B; Binv[l][m] = (B^-1)[l][m], whose row l is grad phi_{l+1}.
+double edge_inverse(int dim, const double *X, const int32_t *T, double Binv[3][3],
+                    double *hmax) {
+  double B[3][3] = {{0}};
+  double h = 0.0;
+  for (int c = 0; c < dim; ++c) {
+    double len2 = 0.0;
+    for (int r = 0; r < dim; ++r) {
+      B[r][c] = X[(int64_t)T[c + 1] * dim + r] - X[(int64_t)T[0] * dim + r];
+      len2 += B[r][c] * B[r][c];
+    }
+    h = std::max(h, std::sqrt(len2));
+  }
+  *hmax = h;
+  if (dim == 2) {
+    double det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+    Binv[0][0] = B[1][1] / det;
+    Binv[0][1] = -B[0][1] / det;
+    Binv[1][0] = -B[1][0] / det;
+    Binv[1][1] = B[0][0] / det;
+    return det;
+  }
+  double c00 = B[1][1] * B[2][2] - B[1][2] * B[2][1];
+  double c01 = B[1][2] * B[2][0] - B[1][0] * B[2][2];
+  double c02 = B[1][0] * B[2][1] - B[1][1] * B[2][0];
+  double det = B[0][0] * c00 + B[0][1] * c01 + B[0][2] * c02;
+  // adj(B)[l][m] = cof(B)[m][l]
+  Binv[0][0] = c00 / det;
+  Binv[1][0] = c01 / det;
+  Binv[2][0] = c02 / det;
+  Binv[0][1] = (B[0][2] * B[2][1] - B[0][1] * B[2][2]) / det;
+  Binv[1][1] = (B[0][0] * B[2][2] - B[0][2] * B[2][0]) / det;
+  Binv[2][1] = (B[0][1] * B[2][0] - B[0][0] * B[2][1]) / det;
+  Binv[0][2] = (B[0][1] * B[1][2] - B[0][2] * B[1][1]) / det;
+  Binv[1][2] = (B[0][2] * B[1][0] - B[0][0] * B[1][2]) / det;
+  Binv[2][2] = (B[0][0] * B[1][1] - B[0][1] * B[1][0]) / det;
+  return det;
+}
+
+int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
+  m->dim = D->dim;
+  m->d = D->ncomp;
+  m->kind = D->kind;
+  m->k = D->dim + 1;
+  m->nn = D->nn;
+  m->ne = D->ne;
+  m->p = D->p;
+  m->C1 = D->C1;
+  m->D1 = D->D1;
+  const int dim = m->dim, d = m->d, k = m->k;
+  const int64_t nn = m->nn, ne = m->ne;
+
+  // ---- element geometry (Section 4.1) and connectivity in structure-of-arrays form
+  const int dd = dim * dim + 1;
+  m->conn.resize((size_t)k * ne);
+  m->geo64.resize((size_t)dd * ne);
+  double vmin = INFINITY, vmax = 0.0;
+  HostAcc vsum;
+  const double fact = dim == 2 ? 2.0 : 6.0;
+  for (int64_t e = 0; e < ne; ++e) {
+    const int32_t *T = D->conn + e * k;
+    for (int l = 0; l < k; ++l) {
+      if (T[l] < 0 || T[l] >= nn)
+        return fail(P1E_EINVAL, "element " + std::to_string(e) + ": vertex index out of range");
+      for (int l2 = 0; l2 < l; ++l2)
+        if (T[l2] == T[l])
+          return fail(P1E_EINVAL, "element " + std::to_string(e) + ": repeated vertex");
+      m->conn[(size_t)l * ne + e] = T[l];
+    }
+    double Bi[3][3], h;
+    double det = edge_inverse(dim, D->coords, T, Bi, &h);
+    if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * std::pow(h, dim))
+      return fail(P1E_EDEGEN, "element " + std::to_string(e) + " is degenerate");
+    double vol = std::fabs(det) / fact;
+    for (int l = 0; l < dim; ++l)
+      for (int c = 0; c < dim; ++c) m->geo64[(size_t)(l * dim + c) * ne + e] = Bi[l][c];
+    m->geo64[(size_t)(dim * dim) * ne + e] = vol;
+    vmin = std::min(vmin, vol);
+    vmax = std::max(vmax, vol);
+    vsum.add(vol);
+  }
+  m->total_vol = vsum.value();
+  m->min_vol = ne ? vmin : 0.0;
+  m->max_vol = vmax;
+
+  // ---- DOF maps: free DOFs in ascending n = d*i + j (Remark 1: a node is free if any of
+  // its components is free)
+  m->node_info.resize(nn);
+  m->vD.assign((size_t)nn * d, 0.0);
+  int64_t nfd = 0, nf = 0;
+  std::vector<int32_t> free_row(nn, -1);
+  for (int64_t i = 0; i < nn; ++i) {
+    int mask = 0;
+    for (int j = 0; j < d; ++j) {
+      bool fixed = D->dirichlet && D->dirichlet[i * d + j];
+      if (!fixed) mask |= 1 << j;
+      if (fixed && D->dirichlet_values) m->vD[i * d + j] = D->dirichlet_values[i * d + j];
+    }
+    if (nfd >= (int64_t(1) << 28)) return fail(P1E_EINVAL, "too many free DOFs (>= 2^28)");
+    m->node_info[i] = (int32_t)((nfd << 3) | mask);
+    nfd += __builtin_popcount(mask);
+    if (mask) free_row[i] = (int32_t)nf++;
+  }
+  m->nfd = nfd;
+  m->nf = nf;
+
+  // ---- free-node patch rows (Section 4.2) as CSR of (element << 2 | local vertex),
+  // elements ascending within each row (counting sort over the element loop)
+  m->row_ptr.assign(nf + 1, 0);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int l = 0; l < k; ++l) {
+      int32_t r = free_row[D->conn[e * k + l]];
+      if (r >= 0) m->row_ptr[r + 1] += 1;
+    }
+  int maxv = 0;
+  for (int64_t r = 0; r < nf; ++r) {
+    maxv = std::max(maxv, m->row_ptr[r + 1]);
+    m->row_ptr[r + 1] += m->row_ptr[r];
+  }
+  m->max_valence = maxv;
+  m->nnz = m->row_ptr[nf];
+  m->ent.resize(m->nnz);
+  {
+    std::vector<int32_t> fill(m->row_ptr.begin(), m->row_ptr.end() - 1);
+    for (int64_t e = 0; e < ne; ++e)
+      for (int l = 0; l < k; ++l) {
+        int32_t r = free_row[D->conn[e * k + l]];
+        if (r >= 0) m->ent[fill[r]++] = ((uint32_t)e << 2) | (uint32_t)l;
+      }
+  }
+  m->row_info.resize(nf);
+  for (int64_t i = 0; i < nn; ++i)
+    if (free_row[i] >= 0) m->row_info[free_row[i]] = m->node_info[i];
+
+  // ---- b = M f (Section 3.2): element mass matrix |T| (1 + delta_ab) / ((dim+1)(dim+2)),
+  // so b_a += |T| (sum_c f_c + f_a) / ((dim+1)(dim+2))
+  std::vector<double> b((size_t)nn * d, 0.0);
+  if (D->load) {
+    const double den = (double)(k * (k + 1));
+    for (int64_t e = 0; e < ne; ++e) {
+      const int32_t *T = D->conn + e * k;
+      double vol = m->geo64[(size_t)(dim * dim) * ne + e];
+      for (int j = 0; j < d; ++j) {
+        double fs = 0.0;
+        for (int c = 0; c < k; ++c) fs += D->load[(int64_t)T[c] * d + j];
+        for (int a = 0; a < k; ++a)
+          b[(int64_t)T[a] * d + j] += vol * (fs + D->load[(int64_t)T[a] * d + j]) / den;
+      }
+    }
+  }
+  m->bhat.resize(nfd);
+  HostAcc dbv;
+  for (int64_t i = 0; i < nn; ++i) {
+    int mask = m->node_info[i] & 7;
+    int64_t fb = m->node_info[i] >> 3;
+    for (int j = 0; j < d; ++j) {
+      if (mask >> j & 1) m->bhat[fb++] = b[i * d + j];
+      else dbv.add(b[i * d + j] * m->vD[i * d + j]);
+    }
+  }
+  m->dirichlet_bv = dbv.value();
+
+  if (m->kind == P1E_NEOHOOKE) m->xref.assign(D->coords, D->coords + (size_t)nn * dim);
+  return P1E_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------- C entry points
+extern "C" {
+
+const char *p1e_last_error(void) { return g_last_error.c_str(); }
+
+int p1e_mesh_create(const p1e_mesh_desc *D, p1e_mesh **out) {
+  if (!D || !out) return fail(P1E_EINVAL, "null argument");
+  *out = nullptr;
+  if (D->dim != 2 && D->dim != 3) return fail(P1E_EINVAL, "dim must be 2 or 3");
+  if (D->kind == P1E_NEOHOOKE) {
+    if (D->ncomp != D->dim) return fail(P1E_EINVAL, "Neo-Hookean needs ncomp == dim");
+    if (!std::isfinite(D->C1) || !std::isfinite(D->D1))
+      return fail(P1E_EINVAL, "C1 and D1 must be finite");
+  } else if (D->kind == P1E_PLAPLACE) {
+    if (D->ncomp != 1) return fail(P1E_EINVAL, "p-Laplacian needs ncomp == 1");
+    if (!(D->p > 1.0) || !std::isfinite(D->p)) return fail(P1E_EINVAL, "p must be > 1");
+  } else {
+    return fail(P1E_EINVAL, "unknown energy kind");
+  }
+  if (D->nn < 1 || D->nn >= (int64_t(1) << 28)) return fail(P1E_EINVAL, "nn out of range");
+  if (D->ne < 0 || D->ne >= (int64_t(1) << 29)) return fail(P1E_EINVAL, "ne out of range");
+  if (!D->coords) return fail(P1E_EINVAL, "coords is null");
+  if (D->ne > 0 && !D->conn) return fail(P1E_EINVAL, "conn is null");
+  p1e_mesh *m = new (std::nothrow) p1e_mesh();
+  if (!m) return fail(P1E_EINVAL, "out of host memory");
+  int rc;
+  try {
+    rc = build_mesh(D, m);
+  } catch (const std::bad_alloc &) {
+    rc = fail(P1E_EINVAL, "out of host memory");
+  }
+  if (rc != P1E_OK) {
+    delete m;
+    return rc;
+  }
+  *out = m;
+  g_last_error.clear();
+  return P1E_OK;
+}
+
+void p1e_mesh_destroy(p1e_mesh *m) { delete m; }
+
+int p1e_mesh_get_info(const p1e_mesh *m, p1e_mesh_info *o) {
+  if (!m || !o) return fail(P1E_EINVAL, "null argument");
+  std::memset(o, 0, sizeof(*o));
+  o->nn = m->nn;
+  o->ne = m->ne;
+  o->n_free_nodes = m->nf;
+  o->n_free_dofs = m->nfd;
+  o->nnz = m->nnz;
+  o->dim = m->dim;
+  o->ncomp = m->d;
+  o->kind = m->kind;
+  o->max_valence = m->max_valence;
+  o->total_volume = m->total_vol;
+  o->min_volume = m->min_vol;
+  o->max_volume = m->max_vol;
+  o->dirichlet_bv = m->dirichlet_bv;
+  o->alignment = kAlign;
+  return P1E_OK;
+}
+
+uint64_t p1e_workspace_bytes(const p1e_mesh *m, int mask) {
+  if (!m || mask <= 0 || (mask & ~(P1E_FP64 | P1E_MIXED | P1E_FD))) return 0;
+  return make_layout(m, mask).total;
+}
+
+int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream) {
+  if (!m || !buf) return fail(P1E_EINVAL, "null argument");
+  if (mask <= 0 || (mask & ~(P1E_FP64 | P1E_MIXED | P1E_FD)))
+    return fail(P1E_EINVAL, "invalid mode mask");
+  if ((uintptr_t)buf % kAlign) return fail(P1E_EINVAL, "device buffer is not 256-byte aligned");
+  Layout L = make_layout(m, mask);
+  if (bytes < L.total)
+    return fail(P1E_ENOMEM, "device buffer too small: need " + std::to_string(L.total) +
+                                " bytes, got " + std::to_string(bytes));
+  hipStream_t s = (hipStream_t)stream;
+  char *base = (char *)buf;
+  auto up = [&](uint64_t off, const void *src, size_t n) -> bool {
+    if (n == 0) return true;
+    return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  const int dd = m->dim * m->dim + 1;
+  std::vector<float> g32;
+  if (mask & P1E_MIXED) {
+    g32.resize(m->geo64.size());
+    for (size_t i = 0; i < g32.size(); ++i) g32[i] = (float)m->geo64[i];
+  }
+  bool ok = up(L.node_info, m->node_info.data(), 4 * m->node_info.size()) &&
+            up(L.xref, m->xref.data(), 8 * m->xref.size()) &&
+            up(L.vD, m->vD.data(), 8 * m->vD.size()) &&
+            up(L.bhat, m->bhat.data(), 8 * m->bhat.size()) &&
+            up(L.conn, m->conn.data(), 4 * m->conn.size()) &&
+            ((mask & (P1E_FP64 | P1E_FD)) ? up(L.geo64, m->geo64.data(), 8ull * dd * m->ne)
+                                          : true) &&
+            ((mask & P1E_MIXED) ? up(L.geo32, g32.data(), 4ull * dd * m->ne) : true) &&
+            up(L.row_ptr, m->row_ptr.data(), 4 * m->row_ptr.size()) &&
+            up(L.ent, m->ent.data(), 4 * m->ent.size()) &&
+            up(L.row_info, m->row_info.data(), 4 * m->row_info.size());
+  hipError_t se = hipStreamSynchronize(s);
+  if (!ok || se != hipSuccess)
+    return fail(P1E_EHIP, std::string("upload failed: ") + hipGetErrorString(hipGetLastError()));
+  DevMesh &D = m->dev;
+  D.node_info = (const int32_t *)(base + L.node_info);
+  D.xref = (const double *)(base + L.xref);
+  D.vD = (const double *)(base + L.vD);
+  D.bhat = (const double *)(base + L.bhat);
+  D.conn = (const int32_t *)(base + L.conn);
+  D.geo64 = (mask & (P1E_FP64 | P1E_FD)) ? (const double *)(base + L.geo64) : nullptr;
+  D.geo32 = (mask & P1E_MIXED) ? (const float *)(base + L.geo32) : nullptr;
+  D.row_ptr = (const int32_t *)(base + L.row_ptr);
+  D.ent = (const uint32_t *)(base + L.ent);
+  D.row_info = (const int32_t *)(base + L.row_info);
+  D.u = base + L.u;
+  D.r = base + L.r;
+  D.part = (double2 *)(base + L.part);
+  D.badp = (int32_t *)(base + L.badp);
+  m->part_cap = part_slots(m);
+  m->bound_modes = mask;
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  m->device = dev;
+  g_last_error.clear();
+  return P1E_OK;
+}
+
+static int check_call(const p1e_mesh *m, const void *vhat, int need_mode) {
+  if (!m) return fail(P1E_EINVAL, "null mesh");
+  if (!vhat && m->nfd > 0) return fail(P1E_EINVAL, "vhat is null");
+  if (!(m->bound_modes & need_mode))
+    return fail(P1E_ESTATE, "mesh is not bound for the requested mode");
+  return P1E_OK;
+}
+
+int p1e_energy(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
+               void *stream) {
+  if (prec != P1E_FP64 && prec != P1E_MIXED) return fail(P1E_EINVAL, "prec must be FP64 or MIXED");
+  int rc = check_call(m, vhat, prec);
+  if (rc) return rc;
+  if (!out3 || !flag) return fail(P1E_EINVAL, "null output pointer");
+  return run_energy(m, vhat, prec, out3, flag, (hipStream_t)stream);
+}
+
+int p1e_grad_exact(p1e_mesh *m, const double *vhat, int prec, double *g, double *out3,
+                   int32_t *flag, void *stream) {
+  if (prec != P1E_FP64 && prec != P1E_MIXED) return fail(P1E_EINVAL, "prec must be FP64 or MIXED");
+  int rc = check_call(m, vhat, prec);
+  if (rc) return rc;
+  if ((!g && m->nfd > 0) || !flag) return fail(P1E_EINVAL, "null output pointer");
+  return run_grad_exact(m, vhat, prec, g, out3, flag, (hipStream_t)stream);
+}
+
+int p1e_grad_patch_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t *flag,
+                      void *stream) {
+  int rc = check_call(m, vhat, P1E_FD);
+  if (rc) return rc;
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(P1E_EINVAL, "eps must be > 0");
+  if ((!g && m->nfd > 0) || !flag) return fail(P1E_EINVAL, "null output pointer");
+  return run_grad_fd(m, vhat, eps, g, flag, (hipStream_t)stream);
+}
+
+int p1e_prof_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return P1E_OK;
+}
+
+int p1e_prof_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &r : g_prof_pending) {
+    (void)hipEventSynchronize(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_pending.clear();
+  g_prof_agg.clear();
+  return P1E_OK;
+}
+
+int p1e_prof_collect(char *names, int64_t names_cap, int64_t *counts, double *total_ms,
+                     int32_t cap, int32_t *n_out) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &r : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto it = std::find_if(g_prof_agg.begin(), g_prof_agg.end(),
+                             [&](const ProfAgg &a) { return a.name == r.name; });
+      if (it == g_prof_agg.end()) g_prof_agg.push_back({r.name, 1, (double)ms});
+      else {
+        it->count += 1;
+        it->ms += ms;
+      }
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_pending.clear();
+  std::string all;
+  int32_t n = 0;
+  for (auto &a : g_prof_agg) {
+    if (n >= cap) break;
+    if (counts) counts[n] = a.count;
+    if (total_ms) total_ms[n] = a.ms;
+    all += a.name;
+    all += '\n';
+    ++n;
+  }
+  if (names && names_cap > 0) {
+    size_t c = std::min<size_t>(all.size(), (size_t)names_cap - 1);
+    std::memcpy(names, all.data(), c);
+    names[c] = 0;
+  }
+  if (n_out) *n_out = n;
+  return P1E_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+"""GPU parity: libp1e (through its C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances (stated, not tuned):
+* FP64 mode: relative 1e-12 for J and for ||g - g_ref||_2 / ||g_ref||_2 (exact gradient).
+* Mixed mode: relative 1e-5 for J, 1e-4 for the exact gradient in the 2-norm.
+* Patch central differences (FP64): per DOF
+      |g - g_ref| <= 32 u cond_n / (2 eps) + 4 u (|v_n| + eps) / eps * gabs_n + 1e-12 |g_ref|
+  with u = 2^-53, cond_n = sum_T |T| (|W+|_abs + |W-|_abs) (rounding of the summed
+  densities) and gabs_n = sum_T |T| |W+ - W-| / (2 eps) (rounding of the perturbed value
+  v_n +- eps in the oracle); both scales come from the oracle.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import p1e_synth as S
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_01158_amd as P
+    return P
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+def _cases():
+    return {
+        # the small configuration: p = 3 on the 33x33 unit-square grid, eps = 1e-6
+        "plap_square_33": lambda: S.config_problem("plap_square_33"),
+        "plap_p1.5_45": lambda: S.plaplace_square(n=45, p=1.5, seed=3),
+        "plap_p5_37": lambda: S.plaplace_square(n=37, p=5.0, seed=4),
+        "plap_lshape_16": lambda: S.plaplace_lshape(16, p=3.0, seed=5),
+        "nh2d_beam_60x13": lambda: S.neohooke_beam_2d(60, 13, 2.0, 13 * 2.0 / 60, seed=6),
+        "nh3d_box_13x7x5": lambda: S.neohooke_box_3d(13, 7, 5, 1.0, 7 / 13, 5 / 13, seed=7),
+        "twisted_bar_L1": lambda: S.twisted_bar(1),
+        "twisted_bar_L2": lambda: S.twisted_bar(2),
+    }
+
+
+CASES = list(_cases().keys())
+
+
+def _plap3d():
+    """scalar p-Laplacian on a 3D Kuhn box (dim 3, d = 1), zero Dirichlet on the boundary"""
+    coords, conn = S.kuhn_box_mesh(9, 6, 7, 0, 1, 0, 0.7, 0, 0.8)
+    X = coords
+    on = np.any((X < 1e-9) | (X > np.array([1, 0.7, 0.8]) - 1e-9), axis=1)
+    rng = np.random.default_rng(9)
+    v = rng.uniform(-1, 1, size=(X.shape[0], 1))
+    v[on] = 0.0
+    return S.Problem(name="plap3d", dim=3, ncomp=1, kind="plaplace", coords=coords, conn=conn,
+                     dirichlet=on.astype(np.uint8)[:, None],
+                     dirichlet_values=np.zeros((X.shape[0], 1)),
+                     load=np.full((X.shape[0], 1), 2.0), v=v, p=3.0, eps=1e-6, h=1 / 9)
+
+
+def _get(name):
+    if name == "plap3d_box":
+        return _plap3d()
+    return _cases()[name]()
+
+
+ALL = CASES + ["plap3d_box"]
+
+
+def _setup(P, prob, modes):
+    mesh = P.Mesh.from_problem(prob, modes=modes)
+    vhat = torch.tensor(prob.vhat(), dtype=torch.float64, device="cuda")
+    return mesh, vhat
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def _rel2(g, gref):
+    return np.linalg.norm(g - gref) / np.linalg.norm(gref)
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_energy_and_exact_gradient_fp64(P, oracle_mod, name):
+    _note(f"[parity fp64] {name}")
+    prob = _get(name)
+    O = oracle_mod.Oracle(prob)
+    ref = O.energy(prob.v)
+    gref = O.grad_exact(prob.v)
+    mesh, vhat = _setup(P, prob, P.P1E_FP64)
+    out3, flag = mesh.energy(vhat, "fp64")
+    g, out3g, flag2 = mesh.grad_exact(vhat, "fp64")
+    torch.cuda.synchronize()
+    J, Jg, bv = out3.cpu().numpy()
+    assert int(flag.item()) == 0 and int(flag2.item()) == 0
+    assert _rel(J, ref["J"]) <= 1e-12
+    assert _rel(Jg, ref["Jgrad"]) <= 1e-12
+    assert abs(bv - ref["bv"]) <= 1e-12 * max(abs(ref["bv"]), abs(ref["Jgrad"]))
+    assert np.array_equal(out3.cpu().numpy(), out3g.cpu().numpy())
+    g = g.cpu().numpy()
+    assert _rel2(g, gref) <= 1e-12
+    # entrywise: the element forces summed per node are larger than the node's gradient
+    # (they cancel), so the max-norm deviation is bounded looser than the 2-norm one
+    assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_energy_and_exact_gradient_mixed(P, oracle_mod, name):
+    _note(f"[parity mixed] {name}")
+    prob = _get(name)
+    O = oracle_mod.Oracle(prob)
+    ref = O.energy(prob.v)
+    gref = O.grad_exact(prob.v)
+    mesh, vhat = _setup(P, prob, P.P1E_MIXED)
+    g, out3, flag = mesh.grad_exact(vhat, "mixed")
+    out3e, flage = mesh.energy(vhat, "mixed")
+    torch.cuda.synchronize()
+    assert int(flag.item()) == 0
+    J = out3.cpu().numpy()
+    assert _rel(J[0], ref["J"]) <= 1e-5
+    assert _rel(J[1], ref["Jgrad"]) <= 1e-5
+    assert np.array_equal(out3e.cpu().numpy(), J)
+    assert _rel2(g.cpu().numpy(), gref) <= 1e-4
+
+
+def _fd_tol(prob, gref, cond, gabs, eps):
+    v = prob.vhat()
+    return 32 * U * cond / (2 * eps) + 4 * U * (np.abs(v) + eps) / eps * gabs + 1e-12 * np.abs(gref)
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_patch_fd_gradient(P, oracle_mod, name):
+    _note(f"[parity fd] {name}")
+    prob = _get(name)
+    eps = prob.eps
+    O = oracle_mod.Oracle(prob)
+    gref, cond, gabs = O.grad_patch_fd(prob.v, eps, with_cond=True)
+    mesh, vhat = _setup(P, prob, P.P1E_FD)
+    g, flag = mesh.grad_patch_fd(vhat, eps)
+    torch.cuda.synchronize()
+    assert int(flag.item()) == 0
+    g = g.cpu().numpy()
+    tol = _fd_tol(prob, gref, cond, gabs, eps)
+    bad = np.flatnonzero(np.abs(g - gref) > tol)
+    assert bad.size == 0, (bad[:5], g[bad[:5]], gref[bad[:5]], tol[bad[:5]])
+    # and the patch differences approximate the exact gradient to O(eps^2)
+    gex = O.grad_exact(prob.v)
+    assert _rel2(g, gex) <= 1e-6
+
+
+def test_determinism_bitwise(P):
+    prob = S.neohooke_box_3d(11, 9, 6, seed=2)
+    mesh, vhat = _setup(P, prob, P.P1E_FP64 | P.P1E_MIXED | P.P1E_FD)
+    for prec in ("fp64", "mixed"):
+        a = [t.clone() for t in mesh.grad_exact(vhat, prec)]
+        b = [t.clone() for t in mesh.grad_exact(vhat, prec)]
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+    f1, _ = mesh.grad_patch_fd(vhat, 1e-6)
+    f1 = f1.clone()
+    f2, _ = mesh.grad_patch_fd(vhat, 1e-6)
+    assert torch.equal(f1, f2)
+
+
+def test_bad_elements_are_flagged(P, oracle_mod):
+    """det F <= 0 -> J = +Inf and the number of bad elements (oracle's count)."""
+    prob = S.neohooke_box_3d(6, 5, 4, seed=3)
+    rng = np.random.default_rng(0)
+    v = prob.v.copy()
+    free_nodes = np.flatnonzero(prob.dirichlet.max(axis=1) == 0)
+    pick = rng.choice(free_nodes, 5, replace=False)
+    v[pick] += 0.5 * rng.standard_normal((5, 3))  # large jumps invert some elements
+    ref = oracle_mod.Oracle(prob).energy(v)
+    assert ref["nbad"] > 0
+    mesh = P.Mesh.from_problem(prob, modes=P.P1E_FP64 | P.P1E_MIXED | P.P1E_FD)
+    vhat = torch.tensor(v.reshape(-1)[prob.free_mask], device="cuda")
+    for prec in ("fp64", "mixed"):
+        out3, flag = mesh.energy(vhat, prec)
+        torch.cuda.synchronize()
+        assert int(flag.item()) == ref["nbad"]
+        assert np.isinf(out3[0].item()) and out3[0].item() > 0
+    _, flag = mesh.grad_patch_fd(vhat, 1e-6)
+    assert int(flag.item()) >= ref["nbad"]
+    vnan = vhat.clone()
+    vnan[7] = float("nan")
+    out3, flag = mesh.energy(vnan, "fp64")
+    assert int(flag.item()) > 0 and np.isinf(out3[0].item())
+
+
+def test_empty_and_all_prescribed(P):
+    """No elements: J = -b.v = 0 (b = 0), g = 0. No free DOFs: J from Dirichlet data only."""
+    coords = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    conn = np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)
+    m = P.Mesh(2, "plaplace", conn[:0], coords, p=3.0, modes=P.P1E_FP64 | P.P1E_FD)
+    vh = torch.ones(4, dtype=torch.float64, device="cuda")
+    out3, flag = m.energy(vh, "fp64")
+    g, _, _ = m.grad_exact(vh, "fp64")
+    gf, _ = m.grad_patch_fd(vh, 1e-6)
+    torch.cuda.synchronize()
+    assert out3.cpu().tolist() == [0.0, 0.0, 0.0] and int(flag.item()) == 0
+    assert torch.count_nonzero(g).item() == 0 and torch.count_nonzero(gf).item() == 0
+    vals = np.array([[0.0], [1.0], [2.0], [3.0]])
+    m2 = P.Mesh(2, "plaplace", conn, coords, dirichlet=np.ones((4, 1), np.uint8),
+                dirichlet_values=vals, load=np.ones((4, 1)), p=2.0, modes=P.P1E_FP64)
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    out3, flag = m2.energy(e, "fp64")
+    g, _, _ = m2.grad_exact(e, "fp64")
+    torch.cuda.synchronize()
+    # grad v = (1, 2) on both triangles: J_grad = 1/2 * |(1,2)|^2 * 1 = 2.5;
+    # b = M 1 = row sums of M: patch areas / 3; b.v = integral of v = 1.5
+    J, Jg, bv = out3.cpu().tolist()
+    assert Jg == pytest.approx(2.5, rel=1e-14) and bv == pytest.approx(1.5, rel=1e-14)
+    assert J == pytest.approx(1.0, rel=1e-14)
+
+
+def test_abi_errors_on_device(P):
+    prob = S.plaplace_square(n=4)
+    mesh, vhat = _setup(P, prob, P.P1E_FP64)
+    with pytest.raises(P.P1EError) as ei:
+        mesh.energy(vhat, "mixed")  # not bound for mixed
+    assert ei.value.status == -7
+    m2, _ = _setup(P, prob, P.P1E_FD)
+    with pytest.raises(P.P1EError) as ei:
+        m2.grad_patch_fd(vhat, 0.0)
+    assert ei.value.status == -1
+    buf = torch.empty(64, dtype=torch.uint8, device="cuda")
+    h = P.mesh_create(2, "plaplace", prob.conn, prob.coords, prob.dirichlet, p=3.0)
+    try:
+        with pytest.raises(P.P1EError) as ei:
+            P.mesh_bind(h, buf, 64, P.P1E_FP64)
+        assert ei.value.status in (-3, -1)
+    finally:
+        P.mesh_destroy(h)
