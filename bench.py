@@ -31,6 +31,9 @@ def _args():
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP64 and FD extra timings")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run plain device-to-device copies of this many MiB (a reference "
+                         "for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -51,6 +54,7 @@ def algorithmic_bytes(info, prec):
     gather = 4 * nnz + 8 * nf + w * (dim + 1) * d * ne + 16 * nfd
     prepass = nn * (4 + 8 * dim) + 16 * nfd + nn * ns * w
     return {"k_element_force": elem, "k_gather": gather, "k_prepass": prepass}
+
 
 
 def cpu_baseline(prob, target_s=12.0):
@@ -96,11 +100,12 @@ def main():
     info = mesh.info
     vhat0 = torch.tensor(prob.vhat(), device=dev)
     vhat = vhat0.clone().requires_grad_(True)
+    seed = torch.ones((), dtype=torch.float64, device=dev)  # dJ/dJ, allocated once
 
     def step():
         vhat.grad = None
         J = P.p1_energy(vhat, mesh, a.prec)
-        J.backward()
+        torch.autograd.backward(J, seed)
         return J
 
     for _ in range(a.warmup):
@@ -150,6 +155,13 @@ def main():
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / n
             extras[name] = {"elements_per_s": info["ne"] / dt, "ms": dt * 1e3}
+
+    if a.copy_calibration > 0:
+        src = torch.empty(a.copy_calibration << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     out = {
         "metric": "elements/s for J+grad J (3D Neo-Hookean, 6M tets)",

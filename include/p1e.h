@@ -66,6 +66,14 @@ extern "C" {
                        the energy sum (compensated) and gradient accumulation in FP64 */
 #define P1E_FD 4    /* bind-only bit: arrays for the patch central-difference gradient (FP64) */
 
+/* ------------------------------------------------------------------ mesh flags */
+/* P1E_LOCALITY_ORDER: renumber nodes and elements internally along a space-filling (Morton)
+ * curve, for meshes whose input numbering has poor locality (e.g. from an unstructured
+ * generator). It changes only the order of floating-point sums, never the external DOF
+ * numbering. Without it the input order is kept (best for lexicographically numbered
+ * structured meshes). */
+#define P1E_LOCALITY_ORDER 1
+
 typedef struct p1e_mesh p1e_mesh;
 
 /* Mesh and problem description (all arrays are host memory, row-major, 0-based). */
@@ -73,7 +81,7 @@ typedef struct p1e_mesh_desc {
   int32_t dim;   /* 2 (triangles) or 3 (tetrahedra) */
   int32_t ncomp; /* d: 1 for P1E_PLAPLACE, dim for P1E_NEOHOOKE */
   int32_t kind;  /* P1E_PLAPLACE or P1E_NEOHOOKE */
-  int32_t reserved;
+  int32_t flags; /* 0 or P1E_LOCALITY_ORDER */
   int64_t nn; /* number of nodes, 1 <= nn < 2^28 */
   int64_t ne; /* number of elements, 0 <= ne < 2^29 */
   const int32_t *conn;       /* [ne][dim+1] vertex indices, distinct, in [0, nn) */
@@ -127,6 +135,19 @@ int p1e_energy(p1e_mesh *mesh, const double *vhat, int prec, double *out3, int32
  * p1e_energy; flag receives the bad-element count. */
 int p1e_grad_exact(p1e_mesh *mesh, const double *vhat, int prec, double *g, double *out3,
                    int32_t *flag, void *stream);
+
+/* The exact gradient in its two phases, for a differentiation hook whose backward pass runs
+ * later than its forward pass (Section 6.2 split at the element/patch boundary):
+ *   p1e_energy_forces  energy as p1e_energy, and the element forces |T| dW/dF grad phi_l of
+ *                      every element, kept in the mesh's scratch arrays;
+ *   p1e_grad_gather    g[n] = s * (sum over the patch of node(n) of the kept forces - b_n)
+ *                      with s = *scale (a device double; NULL means 1).
+ * p1e_grad_gather returns P1E_ESTATE unless the last force-producing call on this mesh
+ * (p1e_energy_forces or p1e_grad_exact) used the same prec; p1e_grad_patch_fd overwrites the
+ * forces. Calls must be enqueued in that order on one stream, or ordered by the caller. */
+int p1e_energy_forces(p1e_mesh *mesh, const double *vhat, int prec, double *out3,
+                      int32_t *flag, void *stream);
+int p1e_grad_gather(p1e_mesh *mesh, int prec, const double *scale, double *g, void *stream);
 
 /* Patch central differences (Section 6.1, eqs. CD, CDS, sumpatch), FP64 throughout:
  * g[n] = [sum_{T in T^(n)} |T| W(F_T(v + eps e_n)) - sum |T| W(F_T(v - eps e_n))]/(2 eps) - b_n

@@ -29,6 +29,8 @@ P1E_FP64 = 1
 P1E_MIXED = 2
 P1E_FD = 4
 
+P1E_LOCALITY_ORDER = 1
+
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EDEGEN", -3: "ENOMEM", -4: "EHIP", -5: "EDOMAIN",
                 -6: "EBUSY", -7: "ESTATE"}
 
@@ -36,7 +38,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EDEGEN", -3: "ENOMEM", -4: "EHIP", -
 class MeshDesc(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32), ("ncomp", ctypes.c_int32), ("kind", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("nn", ctypes.c_int64), ("ne", ctypes.c_int64),
+        ("flags", ctypes.c_int32), ("nn", ctypes.c_int64), ("ne", ctypes.c_int64),
         ("conn", ctypes.c_void_p), ("coords", ctypes.c_void_p), ("dirichlet", ctypes.c_void_p),
         ("dirichlet_values", ctypes.c_void_p), ("load", ctypes.c_void_p),
         ("p", ctypes.c_double), ("C1", ctypes.c_double), ("D1", ctypes.c_double),
@@ -84,6 +86,8 @@ def lib():
         "p1e_energy": ([vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "p1e_grad_exact": ([vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "p1e_grad_patch_fd": ([vp, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "p1e_energy_forces": ([vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
+        "p1e_grad_gather": ([vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "p1e_last_error": ([], ctypes.c_char_p),
         "p1e_prof_enable": ([ctypes.c_int], ctypes.c_int),
         "p1e_prof_reset": ([], ctypes.c_int),

@@ -39,9 +39,9 @@ def neohooke_constants(E, nu):
 
 # ------------------------------------------------------------------ 1:1 entry points
 def mesh_create(dim, kind, conn, coords, dirichlet=None, dirichlet_values=None, load=None,
-                p=2.0, C1=0.0, D1=0.0):
+                p=2.0, C1=0.0, D1=0.0, flags=0):
     """p1e_mesh_create. kind: "plaplace" | "neohooke". Arrays are host numpy; returns an
-    opaque handle (int)."""
+    opaque handle (int). flags: 0 or P1E_LOCALITY_ORDER."""
     k = P1E_NEOHOOKE if kind in ("neohooke", P1E_NEOHOOKE) else P1E_PLAPLACE
     ncomp = dim if k == P1E_NEOHOOKE else 1
     conn = np.ascontiguousarray(conn, dtype=np.int32)
@@ -50,7 +50,7 @@ def mesh_create(dim, kind, conn, coords, dirichlet=None, dirichlet_values=None, 
     dval = None if dirichlet_values is None else np.ascontiguousarray(dirichlet_values,
                                                                      dtype=np.float64)
     f = None if load is None else np.ascontiguousarray(load, dtype=np.float64)
-    desc = L.MeshDesc(dim, ncomp, k, 0, coords.shape[0] if coords.ndim else 0,
+    desc = L.MeshDesc(dim, ncomp, k, int(flags), coords.shape[0] if coords.ndim else 0,
                       conn.shape[0] if conn.size else 0,
                       _ptr(conn) if conn.size else None, _ptr(coords), _ptr(dmask), _ptr(dval),
                       _ptr(f), float(p), float(C1), float(D1))
@@ -93,6 +93,19 @@ def grad_exact(handle, vhat, prec, g, out3, flag, stream=None):
                                  _dptr(out3), _dptr(flag), _stream_ptr(stream, flag.device)))
 
 
+def energy_forces(handle, vhat, prec, out3, flag, stream=None):
+    """p1e_energy_forces: energy, and the element forces kept for grad_gather."""
+    check(L.lib().p1e_energy_forces(ctypes.c_void_p(handle), _dptr(vhat), PREC[prec],
+                                    _dptr(out3), _dptr(flag), _stream_ptr(stream, flag.device)))
+
+
+def grad_gather(handle, prec, scale, g, stream=None):
+    """p1e_grad_gather: g = scale * (patch sums of the kept forces - b); scale is a device
+    0-d/1-element f64 tensor or None."""
+    check(L.lib().p1e_grad_gather(ctypes.c_void_p(handle), PREC[prec], _dptr(scale), _dptr(g),
+                                  _stream_ptr(stream, g.device)))
+
+
 def grad_patch_fd(handle, vhat, eps, g, flag, stream=None):
     """p1e_grad_patch_fd on device tensors."""
     check(L.lib().p1e_grad_patch_fd(ctypes.c_void_p(handle), _dptr(vhat), float(eps), _dptr(g),
@@ -130,9 +143,9 @@ class Mesh:
 
     def __init__(self, dim, kind, conn, coords, dirichlet=None, dirichlet_values=None,
                  load=None, p=2.0, C1=0.0, D1=0.0, modes=P1E_FP64 | P1E_MIXED,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, flags=0):
         self.handle = mesh_create(dim, kind, conn, coords, dirichlet, dirichlet_values, load,
-                                  p, C1, D1)
+                                  p, C1, D1, flags)
         self.info = mesh_get_info(self.handle)
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
@@ -146,9 +159,13 @@ class Mesh:
         with torch.cuda.device(self.device):
             mesh_bind(self.handle, self.buf, self.nbytes, modes, stream)
         self.n_free_dofs = int(self.info["n_free_dofs"])
+        # bumped by every call that rewrites the element-force scratch; lets a
+        # differentiation hook know whether the forces of its forward pass are still there
+        self.forces_gen = 0
 
     @classmethod
-    def from_problem(cls, prob, modes=P1E_FP64 | P1E_MIXED, device="cuda", stream=None):
+    def from_problem(cls, prob, modes=P1E_FP64 | P1E_MIXED, device="cuda", stream=None,
+                     flags=0):
         """Build from an object with the fields of ``p1e_synth.Problem``."""
         if prob.kind == "neohooke":
             C1, D1 = neohooke_constants(prob.E, prob.nu)
@@ -158,7 +175,7 @@ class Mesh:
             p = prob.p
         return cls(prob.dim, prob.kind, prob.conn, prob.coords, prob.dirichlet,
                    prob.dirichlet_values, prob.load, p=p, C1=C1, D1=D1, modes=modes,
-                   device=device, stream=stream)
+                   device=device, stream=stream, flags=flags)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -194,7 +211,23 @@ class Mesh:
         out3 = torch.empty(3, dtype=torch.float64, device=self.device) if out3 is None else out3
         flag = torch.empty(1, dtype=torch.int32, device=self.device) if flag is None else flag
         grad_exact(self.handle, vhat, prec, g, out3, flag, stream)
+        self.forces_gen += 1
         return g, out3, flag
+
+    def energy_forces(self, vhat, prec="mixed", stream=None, out3=None, flag=None):
+        """Energy plus element forces kept for grad_gather; returns (out3, flag, generation)."""
+        self._check_vhat(vhat)
+        out3 = torch.empty(3, dtype=torch.float64, device=self.device) if out3 is None else out3
+        flag = torch.empty(1, dtype=torch.int32, device=self.device) if flag is None else flag
+        energy_forces(self.handle, vhat, prec, out3, flag, stream)
+        self.forces_gen += 1
+        return out3, flag, self.forces_gen
+
+    def grad_gather(self, prec="mixed", scale=None, stream=None, g=None):
+        """g = scale * (patch sums of the forces of the last energy_forces/grad_exact - b)."""
+        g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device) if g is None else g
+        grad_gather(self.handle, prec, scale, g, stream)
+        return g
 
     def grad_patch_fd(self, vhat, eps, stream=None):
         """Returns (g, flag): patch central-difference gradient (FP64)."""
@@ -202,4 +235,5 @@ class Mesh:
         g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device)
         flag = torch.empty(1, dtype=torch.int32, device=self.device)
         grad_patch_fd(self.handle, vhat, eps, g, flag, stream)
+        self.forces_gen += 1
         return g, flag

@@ -1,8 +1,13 @@
 """torch.autograd.Function whose backward is the library's exact gradient (Section 6.2).
 
-``P1Energy.apply(vhat, mesh, prec)`` returns the 0-d energy J(vhat) on the device. When
-``vhat`` requires grad, the forward pass runs the fused J + grad J call once and keeps the
-gradient, so backward is only ``grad_output * g`` (no second pass over the mesh).
+``P1Energy.apply(vhat, mesh, prec)`` returns the 0-d energy J(vhat) on the device.
+
+When ``vhat`` requires grad, the forward pass runs the element phase of the exact gradient
+(energy plus element forces, ``p1e_energy_forces``) and the backward pass runs its node phase
+(``p1e_grad_gather``), which applies the incoming gradient as a device-side scale: one pass
+over the mesh in total and no extra elementwise kernels. If another call rewrote the mesh's
+force scratch between the two passes, backward recomputes the gradient at the saved input.
+The bad-element count of the forward pass is kept on ``mesh.last_flag``.
 """
 
 import torch
@@ -12,20 +17,28 @@ class P1Energy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vhat, mesh, prec="mixed"):
         if vhat.requires_grad:
-            g, out3, flag = mesh.grad_exact(vhat.detach(), prec)
-            ctx.save_for_backward(g)
+            out3, flag, gen = mesh.energy_forces(vhat.detach(), prec)
+            ctx.save_for_backward(vhat)
+            ctx.gen = gen
         else:
             out3, flag = mesh.energy(vhat, prec)
-        ctx.mark_non_differentiable(flag)
-        return out3[0], flag
+        ctx.mesh, ctx.prec = mesh, prec
+        mesh.last_flag = flag
+        return out3[0]
 
     @staticmethod
-    def backward(ctx, grad_j, grad_flag):
-        (g,) = ctx.saved_tensors
-        return grad_j * g, None, None
+    def backward(ctx, grad_j):
+        (vhat,) = ctx.saved_tensors
+        mesh = ctx.mesh
+        scale = grad_j.reshape(1).to(torch.float64).contiguous()
+        if mesh.forces_gen == ctx.gen:
+            g = mesh.grad_gather(ctx.prec, scale=scale)
+        else:
+            mesh.energy_forces(vhat, ctx.prec)
+            g = mesh.grad_gather(ctx.prec, scale=scale)
+        return g, None, None
 
 
 def p1_energy(vhat, mesh, prec="mixed"):
-    """J(vhat) as a differentiable 0-d tensor (the bad-element count is dropped)."""
-    J, _ = P1Energy.apply(vhat, mesh, prec)
-    return J
+    """J(vhat) as a differentiable 0-d tensor."""
+    return P1Energy.apply(vhat, mesh, prec)

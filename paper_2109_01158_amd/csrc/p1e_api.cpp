@@ -77,9 +77,10 @@ uint64_t u_bytes(const p1e_mesh *m, int modes) {
   return (uint64_t)m->nn * node_stride(m->d) * es;
 }
 
+// whole blocks of element records: the element kernel writes full blocks without tail checks
 uint64_t r_bytes(const p1e_mesh *m, int modes) {
   uint64_t es = (modes & (P1E_FP64 | P1E_FD)) ? 8 : 4;
-  return (uint64_t)m->ne * m->k * m->d * es;
+  return (uint64_t)nblocks(m->ne) * kBlock * m->k * m->d * es;
 }
 
 int64_t part_slots(const p1e_mesh *m) {
@@ -88,8 +89,8 @@ int64_t part_slots(const p1e_mesh *m) {
 }
 
 struct Layout {
-  uint64_t node_info, xref, vD, bhat, conn, geo64, geo32, row_ptr, ent, row_info, u, r, part,
-      badp, total;
+  uint64_t node_info, node_int, xref, vD, bhat, conn, geo64, geo32, row_ptr, ent, row_info, u,
+      r, part, badp, total;
 };
 
 static Layout make_layout(const p1e_mesh *m, int modes) {
@@ -102,6 +103,7 @@ static Layout make_layout(const p1e_mesh *m, int modes) {
   };
   const int dd = m->dim * m->dim + 1;
   L.node_info = take(4ull * m->nn);
+  L.node_int = take(4ull * m->nn);
   L.xref = take(m->kind == P1E_NEOHOOKE ? 8ull * m->nn * m->dim : 0);
   L.vD = take(8ull * m->nn * m->d);
   L.bhat = take(8ull * m->nfd);
@@ -177,6 +179,82 @@ double edge_inverse(int dim, const double *X, const int32_t *T, double Binv[3][3
   return det;
 }
 
+// Bit interleaving for Morton (Z-order) keys: 21 bits per axis in 3D, 32 in 2D.
+uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+uint64_t spread2(uint64_t x) {
+  x &= 0xffffffffull;
+  x = (x | x << 16) & 0x0000ffff0000ffffull;
+  x = (x | x << 8) & 0x00ff00ff00ff00ffull;
+  x = (x | x << 4) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | x << 2) & 0x3333333333333333ull;
+  x = (x | x << 1) & 0x5555555555555555ull;
+  return x;
+}
+
+// Morton key of a point on an isotropic grid over the bounding box (same step on every axis).
+struct MortonKey {
+  int dim;
+  double lo[3], scale;
+  uint64_t operator()(const double *x) const {
+    const int bits = dim == 3 ? 21 : 32;
+    const double top = (double)((1ull << bits) - 1);
+    uint64_t q[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+      double t = (x[a] - lo[a]) * scale;
+      q[a] = (uint64_t)std::min(std::max(t, 0.0), top);
+    }
+    return dim == 3 ? spread3(q[0]) | spread3(q[1]) << 1 | spread3(q[2]) << 2
+                    : spread2(q[0]) | spread2(q[1]) << 1;
+  }
+};
+
+// Internal numbering of nodes and elements along a Morton curve, so that the elements of a
+// nodal patch, and the patches of neighbouring nodes, sit close together in memory. The
+// external DOF numbering (vhat, gradients) is not affected.
+void locality_order(const p1e_mesh_desc *D, std::vector<int32_t> &nperm,
+                    std::vector<int32_t> &eperm) {
+  const int dim = D->dim, k = dim + 1;
+  const int64_t nn = D->nn, ne = D->ne;
+  nperm.resize(nn);
+  eperm.resize(ne);
+  for (int64_t i = 0; i < nn; ++i) nperm[i] = (int32_t)i;
+  for (int64_t e = 0; e < ne; ++e) eperm[e] = (int32_t)e;
+  if (!(D->flags & P1E_LOCALITY_ORDER)) return;
+  MortonKey key{dim, {0, 0, 0}, 0.0};
+  double hi[3] = {0, 0, 0}, ext = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    key.lo[a] = INFINITY;
+    hi[a] = -INFINITY;
+  }
+  for (int64_t i = 0; i < nn; ++i)
+    for (int a = 0; a < dim; ++a) {
+      key.lo[a] = std::min(key.lo[a], D->coords[i * dim + a]);
+      hi[a] = std::max(hi[a], D->coords[i * dim + a]);
+    }
+  for (int a = 0; a < dim; ++a) ext = std::max(ext, hi[a] - key.lo[a]);
+  const int bits = dim == 3 ? 21 : 32;
+  key.scale = ext > 0.0 ? (double)((1ull << bits) - 1) / ext : 0.0;
+  std::vector<uint64_t> nk(nn), ek(ne);
+  for (int64_t i = 0; i < nn; ++i) nk[i] = key(D->coords + i * dim);
+  for (int64_t e = 0; e < ne; ++e) {
+    double c[3] = {0, 0, 0};
+    for (int l = 0; l < k; ++l)
+      for (int a = 0; a < dim; ++a) c[a] += D->coords[(int64_t)D->conn[e * k + l] * dim + a];
+    for (int a = 0; a < dim; ++a) c[a] /= k;
+    ek[e] = key(c);
+  }
+  std::stable_sort(nperm.begin(), nperm.end(), [&](int32_t a, int32_t b) { return nk[a] < nk[b]; });
+  std::stable_sort(eperm.begin(), eperm.end(), [&](int32_t a, int32_t b) { return ek[a] < ek[b]; });
+}
+
 int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   m->dim = D->dim;
   m->d = D->ncomp;
@@ -190,13 +268,7 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   const int dim = m->dim, d = m->d, k = m->k;
   const int64_t nn = m->nn, ne = m->ne;
 
-  // ---- element geometry (Section 4.1) and connectivity in structure-of-arrays form
-  const int dd = dim * dim + 1;
-  m->conn.resize((size_t)k * ne);
-  m->geo64.resize((size_t)dd * ne);
-  double vmin = INFINITY, vmax = 0.0;
-  HostAcc vsum;
-  const double fact = dim == 2 ? 2.0 : 6.0;
+  // ---- validate connectivity before using it
   for (int64_t e = 0; e < ne; ++e) {
     const int32_t *T = D->conn + e * k;
     for (int l = 0; l < k; ++l) {
@@ -205,12 +277,30 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
       for (int l2 = 0; l2 < l; ++l2)
         if (T[l2] == T[l])
           return fail(P1E_EINVAL, "element " + std::to_string(e) + ": repeated vertex");
-      m->conn[(size_t)l * ne + e] = T[l];
     }
+  }
+
+  // ---- internal numbering (internal -> external) and its inverse for nodes
+  std::vector<int32_t> nperm, eperm;
+  locality_order(D, nperm, eperm);
+  std::vector<int32_t> ninv(nn);
+  for (int64_t i = 0; i < nn; ++i) ninv[nperm[i]] = (int32_t)i;
+
+  // ---- element geometry (Section 4.1) and connectivity, structure of arrays, internal order
+  const int dd = dim * dim + 1;
+  m->conn.resize((size_t)k * ne);
+  m->geo64.resize((size_t)dd * ne);
+  double vmin = INFINITY, vmax = 0.0;
+  HostAcc vsum;
+  const double fact = dim == 2 ? 2.0 : 6.0;
+  for (int64_t e = 0; e < ne; ++e) {
+    const int64_t ex = eperm[e];
+    const int32_t *T = D->conn + ex * k;
+    for (int l = 0; l < k; ++l) m->conn[(size_t)l * ne + e] = ninv[T[l]];
     double Bi[3][3], h;
     double det = edge_inverse(dim, D->coords, T, Bi, &h);
     if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * std::pow(h, dim))
-      return fail(P1E_EDEGEN, "element " + std::to_string(e) + " is degenerate");
+      return fail(P1E_EDEGEN, "element " + std::to_string(ex) + " is degenerate");
     double vol = std::fabs(det) / fact;
     for (int l = 0; l < dim; ++l)
       for (int c = 0; c < dim; ++c) m->geo64[(size_t)(l * dim + c) * ne + e] = Bi[l][c];
@@ -223,33 +313,41 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   m->min_vol = ne ? vmin : 0.0;
   m->max_vol = vmax;
 
-  // ---- DOF maps: free DOFs in ascending n = d*i + j (Remark 1: a node is free if any of
-  // its components is free)
-  m->node_info.resize(nn);
-  m->vD.assign((size_t)nn * d, 0.0);
-  int64_t nfd = 0, nf = 0;
-  std::vector<int32_t> free_row(nn, -1);
+  // ---- DOF maps over external nodes: free DOFs in ascending n = d*i + j (Remark 1: a node
+  // is free if any of its components is free)
+  std::vector<int32_t> ext_info(nn);
+  int64_t nfd = 0;
   for (int64_t i = 0; i < nn; ++i) {
     int mask = 0;
-    for (int j = 0; j < d; ++j) {
-      bool fixed = D->dirichlet && D->dirichlet[i * d + j];
-      if (!fixed) mask |= 1 << j;
-      if (fixed && D->dirichlet_values) m->vD[i * d + j] = D->dirichlet_values[i * d + j];
-    }
+    for (int j = 0; j < d; ++j)
+      if (!(D->dirichlet && D->dirichlet[i * d + j])) mask |= 1 << j;
     if (nfd >= (int64_t(1) << 28)) return fail(P1E_EINVAL, "too many free DOFs (>= 2^28)");
-    m->node_info[i] = (int32_t)((nfd << 3) | mask);
+    ext_info[i] = (int32_t)((nfd << 3) | mask);
     nfd += __builtin_popcount(mask);
-    if (mask) free_row[i] = (int32_t)nf++;
   }
   m->nfd = nfd;
+
+  // ---- node arrays in external order (the prepass streams them and writes the nodal field
+  // at the internal position node_int[i]); free-node rows in internal node order
+  m->node_info = ext_info;
+  m->node_int = ninv;
+  m->vD.assign((size_t)nn * d, 0.0);
+  if (D->dirichlet && D->dirichlet_values)
+    for (int64_t i = 0; i < nn * d; ++i)
+      if (D->dirichlet[i]) m->vD[i] = D->dirichlet_values[i];
+  if (m->kind == P1E_NEOHOOKE) m->xref.assign(D->coords, D->coords + (size_t)nn * dim);
+  std::vector<int32_t> free_row(nn, -1);
+  int64_t nf = 0;
+  for (int64_t i = 0; i < nn; ++i)
+    if (ext_info[nperm[i]] & 7) free_row[i] = (int32_t)nf++;
   m->nf = nf;
 
-  // ---- free-node patch rows (Section 4.2) as CSR of (element << 2 | local vertex),
-  // elements ascending within each row (counting sort over the element loop)
+  // ---- free-node patch rows (Section 4.2) as CSR of (element << 2 | local vertex), internal
+  // element ids ascending within each row (counting sort over the element loop)
   m->row_ptr.assign(nf + 1, 0);
   for (int64_t e = 0; e < ne; ++e)
     for (int l = 0; l < k; ++l) {
-      int32_t r = free_row[D->conn[e * k + l]];
+      int32_t r = free_row[m->conn[(size_t)l * ne + e]];
       if (r >= 0) m->row_ptr[r + 1] += 1;
     }
   int maxv = 0;
@@ -264,21 +362,21 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
     std::vector<int32_t> fill(m->row_ptr.begin(), m->row_ptr.end() - 1);
     for (int64_t e = 0; e < ne; ++e)
       for (int l = 0; l < k; ++l) {
-        int32_t r = free_row[D->conn[e * k + l]];
+        int32_t r = free_row[m->conn[(size_t)l * ne + e]];
         if (r >= 0) m->ent[fill[r]++] = ((uint32_t)e << 2) | (uint32_t)l;
       }
   }
   m->row_info.resize(nf);
   for (int64_t i = 0; i < nn; ++i)
-    if (free_row[i] >= 0) m->row_info[free_row[i]] = m->node_info[i];
+    if (free_row[i] >= 0) m->row_info[free_row[i]] = ext_info[nperm[i]];
 
   // ---- b = M f (Section 3.2): element mass matrix |T| (1 + delta_ab) / ((dim+1)(dim+2)),
-  // so b_a += |T| (sum_c f_c + f_a) / ((dim+1)(dim+2))
+  // so b_a += |T| (sum_c f_c + f_a) / ((dim+1)(dim+2)); external numbering
   std::vector<double> b((size_t)nn * d, 0.0);
   if (D->load) {
     const double den = (double)(k * (k + 1));
     for (int64_t e = 0; e < ne; ++e) {
-      const int32_t *T = D->conn + e * k;
+      const int32_t *T = D->conn + (int64_t)eperm[e] * k;
       double vol = m->geo64[(size_t)(dim * dim) * ne + e];
       for (int j = 0; j < d; ++j) {
         double fs = 0.0;
@@ -291,16 +389,14 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   m->bhat.resize(nfd);
   HostAcc dbv;
   for (int64_t i = 0; i < nn; ++i) {
-    int mask = m->node_info[i] & 7;
-    int64_t fb = m->node_info[i] >> 3;
+    int mask = ext_info[i] & 7;
+    int64_t fb = ext_info[i] >> 3;
     for (int j = 0; j < d; ++j) {
       if (mask >> j & 1) m->bhat[fb++] = b[i * d + j];
-      else dbv.add(b[i * d + j] * m->vD[i * d + j]);
+      else if (D->dirichlet_values) dbv.add(b[i * d + j] * D->dirichlet_values[i * d + j]);
     }
   }
   m->dirichlet_bv = dbv.value();
-
-  if (m->kind == P1E_NEOHOOKE) m->xref.assign(D->coords, D->coords + (size_t)nn * dim);
   return P1E_OK;
 }
 
@@ -395,6 +491,7 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
     for (size_t i = 0; i < g32.size(); ++i) g32[i] = (float)m->geo64[i];
   }
   bool ok = up(L.node_info, m->node_info.data(), 4 * m->node_info.size()) &&
+            up(L.node_int, m->node_int.data(), 4 * m->node_int.size()) &&
             up(L.xref, m->xref.data(), 8 * m->xref.size()) &&
             up(L.vD, m->vD.data(), 8 * m->vD.size()) &&
             up(L.bhat, m->bhat.data(), 8 * m->bhat.size()) &&
@@ -410,6 +507,7 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
     return fail(P1E_EHIP, std::string("upload failed: ") + hipGetErrorString(hipGetLastError()));
   DevMesh &D = m->dev;
   D.node_info = (const int32_t *)(base + L.node_info);
+  D.node_int = (const int32_t *)(base + L.node_int);
   D.xref = (const double *)(base + L.xref);
   D.vD = (const double *)(base + L.vD);
   D.bhat = (const double *)(base + L.bhat);
@@ -425,6 +523,7 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
   D.badp = (int32_t *)(base + L.badp);
   m->part_cap = part_slots(m);
   m->bound_modes = mask;
+  m->forces_prec = 0;
   int dev = -1;
   (void)hipGetDevice(&dev);
   m->device = dev;
@@ -455,7 +554,29 @@ int p1e_grad_exact(p1e_mesh *m, const double *vhat, int prec, double *g, double 
   int rc = check_call(m, vhat, prec);
   if (rc) return rc;
   if ((!g && m->nfd > 0) || !flag) return fail(P1E_EINVAL, "null output pointer");
-  return run_grad_exact(m, vhat, prec, g, out3, flag, (hipStream_t)stream);
+  rc = run_grad_exact(m, vhat, prec, g, out3, flag, (hipStream_t)stream);
+  m->forces_prec = rc == P1E_OK ? prec : 0;
+  return rc;
+}
+
+int p1e_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
+                      void *stream) {
+  if (prec != P1E_FP64 && prec != P1E_MIXED) return fail(P1E_EINVAL, "prec must be FP64 or MIXED");
+  int rc = check_call(m, vhat, prec);
+  if (rc) return rc;
+  if (!out3 || !flag) return fail(P1E_EINVAL, "null output pointer");
+  rc = run_energy_forces(m, vhat, prec, out3, flag, (hipStream_t)stream);
+  m->forces_prec = rc == P1E_OK ? prec : 0;
+  return rc;
+}
+
+int p1e_grad_gather(p1e_mesh *m, int prec, const double *scale, double *g, void *stream) {
+  if (!m) return fail(P1E_EINVAL, "null mesh");
+  if (prec != P1E_FP64 && prec != P1E_MIXED) return fail(P1E_EINVAL, "prec must be FP64 or MIXED");
+  if (m->forces_prec != prec)
+    return fail(P1E_ESTATE, "no element forces of this precision: call p1e_energy_forces first");
+  if (!g && m->nfd > 0) return fail(P1E_EINVAL, "null output pointer");
+  return run_gather(m, prec, scale, g, (hipStream_t)stream);
 }
 
 int p1e_grad_patch_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t *flag,
@@ -464,6 +585,7 @@ int p1e_grad_patch_fd(p1e_mesh *m, const double *vhat, double eps, double *g, in
   if (rc) return rc;
   if (!(eps > 0.0) || !std::isfinite(eps)) return fail(P1E_EINVAL, "eps must be > 0");
   if ((!g && m->nfd > 0) || !flag) return fail(P1E_EINVAL, "null output pointer");
+  m->forces_prec = 0;  // the patch differences overwrite the element force records
   return run_grad_fd(m, vhat, eps, g, flag, (hipStream_t)stream);
 }
 

@@ -17,9 +17,12 @@ constexpr uint64_t kAlign = 256;   // alignment of every sub-array in the bound 
 
 // Device view of a bound mesh. All arrays live in the caller's buffer.
 struct DevMesh {
+  // node arrays in the caller's (external) node order
   const int32_t *node_info = nullptr;  // [nn]  (first free DOF << 3) | free-component mask
+  const int32_t *node_int = nullptr;   // [nn]  internal number of each node
   const double *xref = nullptr;        // [nn][dim] reference coordinates (Neo-Hookean)
   const double *vD = nullptr;          // [nn][d] prescribed values
+  // element and patch arrays in internal (locality) order
   const double *bhat = nullptr;        // [n_free_dofs] b = M f on the free DOFs
   const int32_t *conn = nullptr;       // [dim+1][ne] structure of arrays
   const double *geo64 = nullptr;       // [dim*dim+1][ne]: B^-1 entries (row l-1 = grad phi_l), |T|
@@ -27,7 +30,8 @@ struct DevMesh {
   const int32_t *row_ptr = nullptr;    // [nf+1] patch rows of free nodes
   const uint32_t *ent = nullptr;       // [nnz] (element << 2) | local vertex, ascending element
   const int32_t *row_info = nullptr;   // [nf] node_info of each free node
-  void *u = nullptr;                   // scratch: nodal field [nn][ns], ns = 4 if d == 3 else d
+  void *u = nullptr;                   // scratch: nodal field [nn][ns] in internal node order,
+                                       // ns = 4 if d == 3 else d
   void *r = nullptr;                   // scratch: per-element forces / differences [(dim+1)d][ne]
   double2 *part = nullptr;             // scratch: compensated block partials
   int32_t *badp = nullptr;             // scratch: bad-element counts per block
@@ -45,7 +49,8 @@ struct p1e_mesh {
   // host copies (kept so the mesh can be bound again)
   std::vector<int32_t> conn;       // [k][ne]
   std::vector<double> geo64;       // [dim*dim+1][ne]
-  std::vector<int32_t> node_info;  // [nn]
+  std::vector<int32_t> node_info;  // [nn] external order
+  std::vector<int32_t> node_int;   // [nn] external -> internal node number
   std::vector<double> xref;        // [nn][dim] (Neo-Hookean only)
   std::vector<double> vD;          // [nn][d]
   std::vector<double> bhat;        // [nfd]
@@ -58,6 +63,7 @@ struct p1e_mesh {
   int device = -1;
   p1e::DevMesh dev;
   int64_t part_cap = 0;  // number of double2 partial slots
+  int forces_prec = 0;   // precision of the element forces held in scratch (0 = none)
 };
 
 namespace p1e {
@@ -84,5 +90,8 @@ int run_grad_exact(p1e_mesh *m, const double *vhat, int prec, double *g, double 
                    int32_t *flag, hipStream_t s);
 int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t *flag,
                 hipStream_t s);
+int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
+                      hipStream_t s);
+int run_gather(p1e_mesh *m, int prec, const double *scale, double *g, hipStream_t s);
 
 }  // namespace p1e

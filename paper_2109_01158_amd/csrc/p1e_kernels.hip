@@ -83,8 +83,11 @@ __device__ __forceinline__ void block_reduce(double &s, double &c, int &cnt) {
 // The dispatcher hands consecutive workgroups to the 8 XCDs in turn, and each XCD has its
 // own L2. Renumber blocks so that every XCD works on one contiguous range of tiles: tiles
 // that share nodes or elements then share an L2. Bijective on [0, nb).
+#ifndef P1E_XCD_COUNT
+#define P1E_XCD_COUNT 8
+#endif
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
-  constexpr int X = 8;
+  constexpr int X = P1E_XCD_COUNT;
   const int q = nb / X, r = nb % X;
   const int x = b % X, k = b / X;
   return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
@@ -276,9 +279,12 @@ __device__ __forceinline__ double density(const T G[D][DIM], const Params &prm, 
 }
 
 // ----------------------------------------------------------------------- kernels
-// u = expanded nodal field; part[b] = compensated partial of b.vhat over the block's nodes
+// u = expanded nodal field; part[b] = compensated partial of b.vhat over the block's nodes.
+// Walks the nodes in the caller's order (coalesced reads of vhat, b, x) and writes each
+// node's field at its internal position.
 template <typename T, int D, bool SUB_X>
 __global__ __launch_bounds__(kBlock) void k_prepass(int nn, const int32_t *__restrict__ node_info,
+                                                    const int32_t *__restrict__ node_int,
                                                     const double *__restrict__ vhat,
                                                     const double *__restrict__ vD,
                                                     const double *__restrict__ xref,
@@ -309,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_prepass(int nn, const int32_t *__res
       if constexpr (SUB_X) val -= xref[(int64_t)i * D + j];
       o[j] = (T)val;
     }
-    NodeVec<T, D>::store(u, i, o);
+    NodeVec<T, D>::store(u, node_int[i], o);
   }
   block_reduce<kBlock>(s, c, cnt);
   if (threadIdx.x == 0) part[tile] = make_double2(s, c);
@@ -317,17 +323,39 @@ __global__ __launch_bounds__(kBlock) void k_prepass(int nn, const int32_t *__res
 
 enum { MODE_ENERGY = 0, MODE_FORCE = 1, MODE_FD = 2 };
 
+// one force-record entry: D words of T, loaded and stored as a single vector access
+template <typename T, int D>
+struct Entry {
+  T v[D];
+};
+
+template <typename T, int D, int K>
+__device__ __forceinline__ void store_entries(T *__restrict__ r, int nep, int e, const T *out) {
+#pragma unroll
+  for (int l = 0; l < K; ++l) {
+    Entry<T, D> q;
+#pragma unroll
+    for (int j = 0; j < D; ++j) q.v[j] = out[l * D + j];
+    *reinterpret_cast<Entry<T, D> *>(r + ((int64_t)l * nep + e) * D) = q;
+  }
+}
+
 // One element per thread. geo: [DIM*DIM][ne] entries of B^-1 followed by [ne] sizes |T|.
-// r (MODE_FORCE, MODE_FD): one record of (DIM+1)*D words per element, word l*D + j is the
-// contribution of this element to component j of its local vertex l.
+// r (MODE_FORCE, MODE_FD): vertex-major entries r[l][e] of D words (l < DIM+1, e < nep, nep =
+// ne rounded up to whole blocks): the contribution of element e to the D components of its
+// local vertex l. Vertex-major keeps a wavefront's stores contiguous, and in structured
+// meshes a node is the same local vertex of all elements of a neighbouring cell, so the
+// entries one patch gathers are contiguous as well.
 template <int DIM, int D, int KIND, typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_element(int ne, const int32_t *__restrict__ conn,
+__global__ __launch_bounds__(kBlock) void k_element(int ne, int nep,
+                                                    const int32_t *__restrict__ conn,
                                                     const T *__restrict__ geo,
                                                     const T *__restrict__ u,
                                                     T *__restrict__ r,
                                                     double2 *__restrict__ part,
                                                     int32_t *__restrict__ badp, Params prm) {
   constexpr int K = DIM + 1;
+  constexpr int KD = K * D;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int e = tile * kBlock + threadIdx.x;
   double s = 0.0, c = 0.0;
@@ -358,7 +386,6 @@ __global__ __launch_bounds__(kBlock) void k_element(int ne, const int32_t *__res
       }
     bool bad = false;
     const double W = density<DIM, D, KIND, T>(G, prm, bad);
-    T *rec = r + (int64_t)e * (K * D);
     if constexpr (MODE == MODE_FORCE) {
       T P[D][DIM];
       if constexpr (KIND == P1E_NEOHOOKE) {
@@ -380,8 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_element(int ne, const int32_t *__res
           out[l * D + j] = acc;
           out[j] -= acc;
         }
-#pragma unroll
-      for (int q = 0; q < K * D; ++q) rec[q] = out[q];
+      store_entries<T, D, K>(r, nep, e, out);
     }
     if constexpr (MODE == MODE_FD) {
       // Central differences of |T| W under v_n +- eps for every DOF n of this element: only
@@ -423,8 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_element(int ne, const int32_t *__res
           out[l * D + j] = (T)((double)vol * (Wp - Wm) * inv2e);
         }
       }
-#pragma unroll
-      for (int q = 0; q < K * D; ++q) rec[q] = out[q];
+      store_entries<T, D, K>(r, nep, e, out);
     }
     if (bad) {
       cnt = 1;
@@ -439,30 +464,61 @@ __global__ __launch_bounds__(kBlock) void k_element(int ne, const int32_t *__res
   }
 }
 
-// GL lanes per free node: the lanes of a group stride over the node's patch entries, then
-// combine their sums by a butterfly over the group (every lane ends with the same sum, as
-// FP addition is commutative), and the group's first lane writes g = sum - b in free-DOF
-// order. Fixed order of operations: deterministic. No atomics.
-template <int K, int D, typename T, int GL>
-__global__ __launch_bounds__(kBlock) void k_gather(int nf, const int32_t *__restrict__ row_ptr,
+// GL lanes per free node: the lanes of a group stride over the node's patch entries (U
+// entries per lane per round, their loads issued together), then combine their sums by a
+// butterfly over the group (every lane ends with the same sum, as FP addition is
+// commutative), and the group's first lane writes g = scale * (sum - b) in free-DOF order
+// (scale: optional device scalar, the incoming gradient of a differentiation hook). Fixed order
+// of operations: deterministic. No atomics.
+template <int K, int D, typename T, int GL, int U>
+__global__ __launch_bounds__(kBlock) void k_gather(int nf, int nep,
+                                                   const int32_t *__restrict__ row_ptr,
                                                    const uint32_t *__restrict__ ent,
                                                    const int32_t *__restrict__ row_info,
                                                    const T *__restrict__ r,
                                                    const double *__restrict__ bhat,
+                                                   const double *__restrict__ scale,
                                                    double *__restrict__ g) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int sub = threadIdx.x % GL;
   const int row = tile * (kBlock / GL) + threadIdx.x / GL;
-  double acc[D];
+  double acc[D], bv[D];
+  int fb0 = 0, mask = 0;
 #pragma unroll
-  for (int j = 0; j < D; ++j) acc[j] = 0.0;
+  for (int j = 0; j < D; ++j) acc[j] = bv[j] = 0.0;
   if (row < nf) {
     const int t0 = row_ptr[row], t1 = row_ptr[row + 1];
-    for (int t = t0 + sub; t < t1; t += GL) {
-      const uint32_t x = ent[t];
-      const T *q = r + ((int64_t)(x >> 2) * K + (x & 3)) * D;
+    // the row's DOF map and load vector do not depend on the entries: fetch them first so
+    // their latency overlaps the entry loads
+    if (sub == 0) {
+      const int info = row_info[row];
+      mask = info & 7;
+      fb0 = info >> 3;
+      int fb = fb0;
 #pragma unroll
-      for (int j = 0; j < D; ++j) acc[j] += (double)q[j];
+      for (int j = 0; j < D; ++j)
+        if ((mask >> j) & 1) bv[j] = bhat[fb++];
+    }
+    for (int base = t0 + sub; base < t1; base += GL * U) {
+      // branch-free round: out-of-row slots load the row's last entry and add zero, so
+      // all U loads of the round are in flight together
+      uint32_t x[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = base + u * GL;
+        ok[u] = t < t1;
+        x[u] = ent[ok[u] ? t : t1 - 1];
+      }
+      Entry<T, D> q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        q[u] = *reinterpret_cast<const Entry<T, D> *>(
+            r + ((int64_t)(x[u] & 3) * nep + (x[u] >> 2)) * D);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[j] += ok[u] ? (double)q[u].v[j] : 0.0;
     }
   }
 #pragma unroll
@@ -470,13 +526,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(int nf, const int32_t *__rest
 #pragma unroll
     for (int j = 0; j < D; ++j) acc[j] += __shfl_xor(acc[j], off, 64);
   if (row < nf && sub == 0) {
-    const int info = row_info[row];
-    const int mask = info & 7;
-    int fb = info >> 3;
+    const double sc = scale ? *scale : 1.0;
+    int fb = fb0;
 #pragma unroll
     for (int j = 0; j < D; ++j)
       if ((mask >> j) & 1) {
-        g[fb] = acc[j] - bhat[fb];
+        g[fb] = sc * (acc[j] - bv[j]);
         ++fb;
       }
   }
@@ -560,7 +615,7 @@ int launch_prepass(p1e_mesh *m, const double *vhat, double2 *pn, hipStream_t s) 
   const int nb = (int)nblocks(m->nn);
   prof_begin("k_prepass", s);
   hipLaunchKernelGGL((k_prepass<T, D, SUBX>), dim3(nb), dim3(kBlock), 0, s, (int)m->nn,
-                     m->dev.node_info, vhat, m->dev.vD, m->dev.xref, m->dev.bhat, (T *)m->dev.u,
+                     m->dev.node_info, m->dev.node_int, vhat, m->dev.vD, m->dev.xref, m->dev.bhat, (T *)m->dev.u,
                      pn);
   prof_end(s);
   return check_launch("k_prepass");
@@ -575,26 +630,37 @@ int launch_element(p1e_mesh *m, const T *geo, double eps, hipStream_t s) {
                                           : "k_element_fd";
   prof_begin(name, s);
   hipLaunchKernelGGL((k_element<DIM, D, KIND, T, MODE>), dim3(nb), dim3(kBlock), 0, s,
-                     (int)m->ne, m->dev.conn, geo, (const T *)m->dev.u, (T *)m->dev.r,
+                     (int)m->ne, nb * kBlock, m->dev.conn, geo, (const T *)m->dev.u, (T *)m->dev.r,
                      m->dev.part, m->dev.badp, params_of(m, eps));
   prof_end(s);
   return check_launch(name);
 }
 
-// lanes per patch row: enough to cover a typical patch in one or two rounds
+// Lanes per patch row and entries per lane per round (3D Kuhn patches hold up to 24
+// elements, 2D right-triangle patches 6); both can be set at build time.
+#ifndef P1E_GATHER_LANES_3D
+#define P1E_GATHER_LANES_3D 8
+#endif
+#ifndef P1E_GATHER_LANES_2D
+#define P1E_GATHER_LANES_2D 4
+#endif
+#ifndef P1E_GATHER_UNROLL
+#define P1E_GATHER_UNROLL 3
+#endif
 template <int DIM>
-constexpr int gather_lanes() { return DIM == 3 ? 8 : 4; }
+constexpr int gather_lanes() { return DIM == 3 ? P1E_GATHER_LANES_3D : P1E_GATHER_LANES_2D; }
 
 template <int DIM, int D, typename T>
-int launch_gather(p1e_mesh *m, double *g, hipStream_t s) {
+int launch_gather(p1e_mesh *m, const double *scale, double *g, hipStream_t s) {
   if (m->nf == 0) return P1E_OK;
   constexpr int GL = gather_lanes<DIM>();
   const int rows_per_block = kBlock / GL;
   const int nb = (int)((m->nf + rows_per_block - 1) / rows_per_block);
   prof_begin("k_gather", s);
-  hipLaunchKernelGGL((k_gather<DIM + 1, D, T, GL>), dim3(nb), dim3(kBlock), 0, s, (int)m->nf,
+  hipLaunchKernelGGL((k_gather<DIM + 1, D, T, GL, P1E_GATHER_UNROLL>), dim3(nb), dim3(kBlock), 0, s, (int)m->nf,
+                     (int)(nblocks(m->ne) * kBlock),
                      m->dev.row_ptr, m->dev.ent, m->dev.row_info, (const T *)m->dev.r,
-                     m->dev.bhat, g);
+                     m->dev.bhat, scale, g);
   prof_end(s);
   return check_launch("k_gather");
 }
@@ -613,8 +679,8 @@ int launch_finalize(p1e_mesh *m, const double2 *pn, double *out3, int32_t *flag,
 // node partials follow the element partials (the layout reserves 2 x part_cap slots)
 double2 *node_partials(p1e_mesh *m) { return m->dev.part + m->part_cap; }
 
-// The full pipeline for one (DIM, D, KIND, T): prepass, element pass (mode), optional
-// gather, finalize.
+// The pipeline for one (DIM, D, KIND, T): prepass, element pass (mode), finalize, and the
+// patch gather when g is given.
 template <int DIM, int D, int KIND, typename T, int MODE>
 int pipeline(p1e_mesh *m, const double *vhat, const T *geo, double eps, double *g,
              double *out3, int32_t *flag, hipStream_t s) {
@@ -624,11 +690,10 @@ int pipeline(p1e_mesh *m, const double *vhat, const T *geo, double eps, double *
   if (rc) return rc;
   rc = launch_element<DIM, D, KIND, T, MODE>(m, geo, eps, s);
   if (rc) return rc;
-  if constexpr (MODE != MODE_ENERGY) {
-    rc = launch_gather<DIM, D, T>(m, g, s);
-    if (rc) return rc;
-  }
-  return launch_finalize(m, pn, out3, flag, s);
+  rc = launch_finalize(m, pn, out3, flag, s);
+  if (rc) return rc;
+  if (MODE != MODE_ENERGY && g != nullptr) rc = launch_gather<DIM, D, T>(m, nullptr, g, s);
+  return rc;
 }
 
 template <typename T, int MODE>
@@ -640,6 +705,16 @@ int dispatch(p1e_mesh *m, const double *vhat, const T *geo, double eps, double *
   }
   if (m->dim == 3) return pipeline<3, 1, P1E_PLAPLACE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
   return pipeline<2, 1, P1E_PLAPLACE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
+}
+
+template <typename T>
+int dispatch_gather(p1e_mesh *m, const double *scale, double *g, hipStream_t s) {
+  if (m->kind == P1E_NEOHOOKE) {
+    if (m->dim == 3) return launch_gather<3, 3, T>(m, scale, g, s);
+    return launch_gather<2, 2, T>(m, scale, g, s);
+  }
+  if (m->dim == 3) return launch_gather<3, 1, T>(m, scale, g, s);
+  return launch_gather<2, 1, T>(m, scale, g, s);
 }
 
 }  // namespace
@@ -661,6 +736,18 @@ int run_grad_exact(p1e_mesh *m, const double *vhat, int prec, double *g, double 
 int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t *flag,
                 hipStream_t s) {
   return dispatch<double, MODE_FD>(m, vhat, m->dev.geo64, eps, g, nullptr, flag, s);
+}
+
+int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
+                      hipStream_t s) {
+  if (prec == P1E_MIXED)
+    return dispatch<float, MODE_FORCE>(m, vhat, m->dev.geo32, 0.0, nullptr, out3, flag, s);
+  return dispatch<double, MODE_FORCE>(m, vhat, m->dev.geo64, 0.0, nullptr, out3, flag, s);
+}
+
+int run_gather(p1e_mesh *m, int prec, const double *scale, double *g, hipStream_t s) {
+  if (prec == P1E_MIXED) return dispatch_gather<float>(m, scale, g, s);
+  return dispatch_gather<double>(m, scale, g, s);
 }
 
 }  // namespace p1e

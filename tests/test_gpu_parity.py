@@ -237,3 +237,19 @@ def test_abi_errors_on_device(P):
         assert ei.value.status in (-3, -1)
     finally:
         P.mesh_destroy(h)
+
+
+def test_internal_order_does_not_change_results(P, oracle_mod):
+    """The locality renumbering changes only the order of sums."""
+    prob = S.neohooke_box_3d(14, 6, 5, 1.0, 6 / 14, 5 / 14, seed=11)
+    v = torch.tensor(prob.vhat(), device="cuda")
+    outs = []
+    for flags in (0, P.P1E_LOCALITY_ORDER):
+        m = P.Mesh.from_problem(prob, modes=P.P1E_FP64 | P.P1E_FD, flags=flags)
+        g, o, _ = m.grad_exact(v, "fp64")
+        f, _ = m.grad_patch_fd(v, 1e-6)
+        outs.append((g.cpu().numpy(), o.cpu().numpy(), f.cpu().numpy()))
+    (g0, o0, f0), (g1, o1, f1) = outs
+    assert np.abs(o0 - o1).max() <= 1e-13 * np.abs(o0).max()
+    assert np.linalg.norm(g0 - g1) <= 1e-13 * np.linalg.norm(g0)
+    assert np.linalg.norm(f0 - f1) <= 1e-9 * np.linalg.norm(f0)
