@@ -80,11 +80,11 @@ uint64_t u_bytes(const p1e_mesh *m, int modes) {
 // whole blocks of element records: the element kernel writes full blocks without tail checks
 uint64_t r_bytes(const p1e_mesh *m, int modes) {
   uint64_t es = (modes & (P1E_FP64 | P1E_FD)) ? 8 : 4;
-  return (uint64_t)nblocks(m->ne) * kBlock * m->k * m->d * es;
+  return (uint64_t)padded_elements(m->ne) * m->k * m->d * es;
 }
 
 int64_t part_slots(const p1e_mesh *m) {
-  int64_t n = std::max<int64_t>(nblocks(m->ne), nblocks(m->nn));
+  int64_t n = std::max<int64_t>(element_blocks(m->ne), node_blocks(m->nn));
   return std::max<int64_t>(n, 1);
 }
 

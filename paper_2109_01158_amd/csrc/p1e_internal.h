@@ -12,7 +12,9 @@
 
 namespace p1e {
 
-constexpr int kBlock = 256;        // threads per block of every streaming kernel
+constexpr int kBlock = 256;        // threads per block of the patch gather
+constexpr int kBlockElem = 512;    // threads (= elements) per block of the element kernel
+constexpr int kBlockNode = 1024;   // threads (= nodes) per block of the node prepass
 constexpr uint64_t kAlign = 256;   // alignment of every sub-array in the bound buffer
 
 // Device view of a bound mesh. All arrays live in the caller's buffer.
@@ -76,7 +78,11 @@ void prof_begin(const char *name, hipStream_t s);
 void prof_end(hipStream_t s);
 
 // number of blocks of the streaming kernels over n items
-inline int64_t nblocks(int64_t n) { return (n + kBlock - 1) / kBlock; }
+inline int64_t nblocks(int64_t n, int per = kBlock) { return (n + per - 1) / per; }
+inline int64_t element_blocks(int64_t ne) { return nblocks(ne, kBlockElem); }
+inline int64_t node_blocks(int64_t nn) { return nblocks(nn, kBlockNode); }
+// per-element scratch is padded to whole element blocks
+inline int64_t padded_elements(int64_t ne) { return element_blocks(ne) * kBlockElem; }
 
 // device bytes of each scratch array for the given mode mask
 uint64_t u_bytes(const p1e_mesh *m, int modes);

@@ -283,7 +283,7 @@ __device__ __forceinline__ double density(const T G[D][DIM], const Params &prm, 
 // Walks the nodes in the caller's order (coalesced reads of vhat, b, x) and writes each
 // node's field at its internal position.
 template <typename T, int D, bool SUB_X>
-__global__ __launch_bounds__(kBlock) void k_prepass(int nn, const int32_t *__restrict__ node_info,
+__global__ __launch_bounds__(kBlockNode) void k_prepass(int nn, const int32_t *__restrict__ node_info,
                                                     const int32_t *__restrict__ node_int,
                                                     const double *__restrict__ vhat,
                                                     const double *__restrict__ vD,
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_prepass(int nn, const int32_t *__res
                                                     const double *__restrict__ bhat,
                                                     T *__restrict__ u, double2 *__restrict__ part) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int i = tile * kBlock + threadIdx.x;
+  const int i = tile * kBlockNode + threadIdx.x;
   double s = 0.0, c = 0.0;
   int cnt = 0;
   if (i < nn) {
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_prepass(int nn, const int32_t *__res
     }
     NodeVec<T, D>::store(u, node_int[i], o);
   }
-  block_reduce<kBlock>(s, c, cnt);
+  block_reduce<kBlockNode>(s, c, cnt);
   if (threadIdx.x == 0) part[tile] = make_double2(s, c);
 }
 
@@ -347,7 +347,7 @@ __device__ __forceinline__ void store_entries(T *__restrict__ r, int nep, int e,
 // meshes a node is the same local vertex of all elements of a neighbouring cell, so the
 // entries one patch gathers are contiguous as well.
 template <int DIM, int D, int KIND, typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_element(int ne, int nep,
+__global__ __launch_bounds__(kBlockElem) void k_element(int ne, int nep,
                                                     const int32_t *__restrict__ conn,
                                                     const T *__restrict__ geo,
                                                     const T *__restrict__ u,
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_element(int ne, int nep,
   constexpr int K = DIM + 1;
   constexpr int KD = K * D;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int e = tile * kBlock + threadIdx.x;
+  const int e = tile * kBlockElem + threadIdx.x;
   double s = 0.0, c = 0.0;
   int cnt = 0;
   if (e < ne) {
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_element(int ne, int nep,
       s = (double)vol * W;
     }
   }
-  block_reduce<kBlock>(s, c, cnt);
+  block_reduce<kBlockElem>(s, c, cnt);
   if (threadIdx.x == 0) {
     part[tile] = make_double2(s, c);
     badp[tile] = cnt;
@@ -545,7 +545,7 @@ constexpr int kFin = 1024;
 __device__ __forceinline__ void strided_pairs(int n, const double2 *__restrict__ p,
                                               const int32_t *__restrict__ cntp, double &s,
                                               double &c, int &cnt) {
-  constexpr int B = 8;
+  constexpr int B = 16;
   int i = threadIdx.x;
   for (; i + (B - 1) * kFin < n; i += B * kFin) {
     double2 q[B];
@@ -612,9 +612,9 @@ Params params_of(const p1e_mesh *m, double eps) { return Params{m->C1, m->D1, m-
 
 template <typename T, int D, bool SUBX>
 int launch_prepass(p1e_mesh *m, const double *vhat, double2 *pn, hipStream_t s) {
-  const int nb = (int)nblocks(m->nn);
+  const int nb = (int)node_blocks(m->nn);
   prof_begin("k_prepass", s);
-  hipLaunchKernelGGL((k_prepass<T, D, SUBX>), dim3(nb), dim3(kBlock), 0, s, (int)m->nn,
+  hipLaunchKernelGGL((k_prepass<T, D, SUBX>), dim3(nb), dim3(kBlockNode), 0, s, (int)m->nn,
                      m->dev.node_info, m->dev.node_int, vhat, m->dev.vD, m->dev.xref, m->dev.bhat, (T *)m->dev.u,
                      pn);
   prof_end(s);
@@ -624,13 +624,13 @@ int launch_prepass(p1e_mesh *m, const double *vhat, double2 *pn, hipStream_t s) 
 template <int DIM, int D, int KIND, typename T, int MODE>
 int launch_element(p1e_mesh *m, const T *geo, double eps, hipStream_t s) {
   if (m->ne == 0) return P1E_OK;
-  const int nb = (int)nblocks(m->ne);
+  const int nb = (int)element_blocks(m->ne);
   const char *name = MODE == MODE_ENERGY ? "k_element_energy"
                      : MODE == MODE_FORCE ? "k_element_force"
                                           : "k_element_fd";
   prof_begin(name, s);
-  hipLaunchKernelGGL((k_element<DIM, D, KIND, T, MODE>), dim3(nb), dim3(kBlock), 0, s,
-                     (int)m->ne, nb * kBlock, m->dev.conn, geo, (const T *)m->dev.u, (T *)m->dev.r,
+  hipLaunchKernelGGL((k_element<DIM, D, KIND, T, MODE>), dim3(nb), dim3(kBlockElem), 0, s,
+                     (int)m->ne, (int)padded_elements(m->ne), m->dev.conn, geo, (const T *)m->dev.u, (T *)m->dev.r,
                      m->dev.part, m->dev.badp, params_of(m, eps));
   prof_end(s);
   return check_launch(name);
@@ -658,7 +658,7 @@ int launch_gather(p1e_mesh *m, const double *scale, double *g, hipStream_t s) {
   const int nb = (int)((m->nf + rows_per_block - 1) / rows_per_block);
   prof_begin("k_gather", s);
   hipLaunchKernelGGL((k_gather<DIM + 1, D, T, GL, P1E_GATHER_UNROLL>), dim3(nb), dim3(kBlock), 0, s, (int)m->nf,
-                     (int)(nblocks(m->ne) * kBlock),
+                     (int)padded_elements(m->ne),
                      m->dev.row_ptr, m->dev.ent, m->dev.row_info, (const T *)m->dev.r,
                      m->dev.bhat, scale, g);
   prof_end(s);
@@ -667,8 +667,8 @@ int launch_gather(p1e_mesh *m, const double *scale, double *g, hipStream_t s) {
 
 int launch_finalize(p1e_mesh *m, const double2 *pn, double *out3, int32_t *flag,
                     hipStream_t s) {
-  const int nbe = m->ne ? (int)nblocks(m->ne) : 0;
-  const int nbn = (int)nblocks(m->nn);
+  const int nbe = m->ne ? (int)element_blocks(m->ne) : 0;
+  const int nbn = (int)node_blocks(m->nn);
   prof_begin("k_finalize", s);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFin), 0, s, nbe, m->dev.part, m->dev.badp, nbn,
                      pn, m->dirichlet_bv, out3, flag);
