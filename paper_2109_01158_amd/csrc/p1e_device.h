@@ -1,0 +1,508 @@
+// p1e_device.h -- device-side building blocks shared by the single-mesh kernels
+// (p1e_kernels.hip) and the batched multi-request kernels (p1e_batch.hip): compensated sums,
+// block reductions, nodal field access, the densities and their stresses, and the bodies of
+// the node, element and patch passes. Not part of the public ABI.
+//
+// Precision. P1E_FP64 runs everything in double. P1E_MIXED evaluates the element algebra in
+// float on the displacement gradient G = F - I, with the cancellation-free forms
+//   |F|^2 - dim = 2 tr G + |G|^2,  det F - 1 = tr G + s2(G) + det G  (s2: sum of principal
+//   2x2 minors, absent in 2D),  log det F = log1p(det F - 1)  (double),
+//   F - F^-T = [(s2 + det G) I + (det F) G + G^T - cof G] / det F  (2D: cof terms reduce),
+// and accumulates energies and forces in double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "p1e_internal.h"
+
+namespace p1e {
+namespace dev {
+
+struct Params {
+  double C1, D1, p, eps;
+};
+
+// ----------------------------------------------------------------------- compensated sums
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// (s, c) pairs: value = s + c
+__device__ __forceinline__ void pair_add(double &s, double &c, double s2, double c2) {
+  double t, e;
+  two_sum(s, s2, t, e);
+  s = t;
+  c = c + c2 + e;
+}
+
+// Block-wide deterministic reduction of (s, c) pairs and an integer count; thread 0 gets
+// the result. Fixed shuffle and LDS order, so the result does not depend on timing.
+template <int NT>
+__device__ __forceinline__ void block_reduce(double &s, double &c, int &cnt) {
+  __shared__ double sh_s[NT / 64], sh_c[NT / 64];
+  __shared__ int sh_n[NT / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    double s2 = __shfl_down(s, off, 64);
+    double c2 = __shfl_down(c, off, 64);
+    int n2 = __shfl_down(cnt, off, 64);
+    pair_add(s, c, s2, c2);
+    cnt += n2;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh_s[wave] = s;
+    sh_c[wave] = c;
+    sh_n[wave] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < NT / 64; ++w) {
+      pair_add(s, c, sh_s[w], sh_c[w]);
+      cnt += sh_n[w];
+    }
+  }
+}
+
+// The dispatcher hands consecutive workgroups to the 8 XCDs in turn, and each XCD has its
+// own L2. Renumber blocks so that every XCD works on one contiguous range of tiles: tiles
+// that share nodes or elements then share an L2. Bijective on [0, nb).
+#ifndef P1E_XCD_COUNT
+#define P1E_XCD_COUNT 8
+#endif
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int X = P1E_XCD_COUNT;
+  const int q = nb / X, r = nb % X;
+  const int x = b % X, k = b / X;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// explicit fused multiply-add: kernels are built without automatic contraction, so the
+// same expression rounds the same way in every kernel that uses it
+__device__ __forceinline__ float mad(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double mad(double a, double b, double c) { return fma(a, b, c); }
+
+// ----------------------------------------------------------------------- node field access
+template <typename T, int D>
+struct NodeVec;
+template <>
+struct NodeVec<float, 3> {
+  static constexpr int NS = 4;
+  __device__ static void load(const float *u, int i, float o[3]) {
+    float4 q = reinterpret_cast<const float4 *>(u)[i];
+    o[0] = q.x, o[1] = q.y, o[2] = q.z;
+  }
+  __device__ static void store(float *u, int i, const float o[3]) {
+    reinterpret_cast<float4 *>(u)[i] = make_float4(o[0], o[1], o[2], 0.f);
+  }
+};
+template <>
+struct NodeVec<double, 3> {
+  static constexpr int NS = 4;
+  __device__ static void load(const double *u, int i, double o[3]) {
+    const double2 *q = reinterpret_cast<const double2 *>(u) + 2 * (int64_t)i;
+    double2 a = q[0], b = q[1];
+    o[0] = a.x, o[1] = a.y, o[2] = b.x;
+  }
+  __device__ static void store(double *u, int i, const double o[3]) {
+    double2 *q = reinterpret_cast<double2 *>(u) + 2 * (int64_t)i;
+    q[0] = make_double2(o[0], o[1]);
+    q[1] = make_double2(o[2], 0.0);
+  }
+};
+template <>
+struct NodeVec<float, 2> {
+  static constexpr int NS = 2;
+  __device__ static void load(const float *u, int i, float o[2]) {
+    float2 q = reinterpret_cast<const float2 *>(u)[i];
+    o[0] = q.x, o[1] = q.y;
+  }
+  __device__ static void store(float *u, int i, const float o[2]) {
+    reinterpret_cast<float2 *>(u)[i] = make_float2(o[0], o[1]);
+  }
+};
+template <>
+struct NodeVec<double, 2> {
+  static constexpr int NS = 2;
+  __device__ static void load(const double *u, int i, double o[2]) {
+    double2 q = reinterpret_cast<const double2 *>(u)[i];
+    o[0] = q.x, o[1] = q.y;
+  }
+  __device__ static void store(double *u, int i, const double o[2]) {
+    reinterpret_cast<double2 *>(u)[i] = make_double2(o[0], o[1]);
+  }
+};
+template <typename T>
+struct NodeVec<T, 1> {
+  static constexpr int NS = 1;
+  __device__ static void load(const T *u, int i, T o[1]) { o[0] = u[i]; }
+  __device__ static void store(T *u, int i, const T o[1]) { u[i] = o[0]; }
+};
+
+// ----------------------------------------------------------------------- densities
+template <typename T>
+__device__ __forceinline__ T fpow(T x, T y);
+template <>
+__device__ __forceinline__ float fpow<float>(float x, float y) { return powf(x, y); }
+template <>
+__device__ __forceinline__ double fpow<double>(double x, double y) { return pow(x, y); }
+
+// Neo-Hookean density at F = I + G (eq. neoHook), returned in double.
+template <int DIM, typename T>
+__device__ __forceinline__ double nh_energy(const T G[DIM][DIM], double C1, double D1,
+                                            bool &bad) {
+  T tr, s2, dG, n2 = T(0);
+  if constexpr (DIM == 3) {
+    tr = G[0][0] + G[1][1] + G[2][2];
+    s2 = G[0][0] * G[1][1] + G[0][0] * G[2][2] + G[1][1] * G[2][2] - G[0][1] * G[1][0] -
+         G[0][2] * G[2][0] - G[1][2] * G[2][1];
+    dG = G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) -
+         G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +
+         G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+  } else {
+    tr = G[0][0] + G[1][1];
+    s2 = T(0);
+    dG = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+  }
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) n2 += G[j][m] * G[j][m];
+  const double delta = (double)tr + (double)s2 + (double)dG;  // det F - 1
+  if (!(delta > -1.0)) {
+    bad = true;
+    return 0.0;
+  }
+  const double q = delta - log1p(delta);  // (det F - 1) - log det F >= 0
+  // |F|^2 - dim - 2 log det F = |G|^2 - 2 (s2 + det G) + 2 q
+  const double W = C1 * ((double)n2 - 2.0 * ((double)s2 + (double)dG) + 2.0 * q) +
+                   D1 * delta * delta;
+  if (!isfinite(W)) bad = true;
+  return W;
+}
+
+// First Piola stress P = dW/dF at F = I + G, in T:
+//   P = 2 C1 (J F - cof F) / J + 2 D1 (J - 1) cof F,  J = det F.
+template <int DIM, typename T>
+__device__ __forceinline__ void nh_stress(const T G[DIM][DIM], T C1, T D1, T P[DIM][DIM]) {
+  if constexpr (DIM == 3) {
+    T cg[3][3];  // cof G
+    cg[0][0] = G[1][1] * G[2][2] - G[1][2] * G[2][1];
+    cg[0][1] = G[1][2] * G[2][0] - G[1][0] * G[2][2];
+    cg[0][2] = G[1][0] * G[2][1] - G[1][1] * G[2][0];
+    cg[1][0] = G[0][2] * G[2][1] - G[0][1] * G[2][2];
+    cg[1][1] = G[0][0] * G[2][2] - G[0][2] * G[2][0];
+    cg[1][2] = G[0][1] * G[2][0] - G[0][0] * G[2][1];
+    cg[2][0] = G[0][1] * G[1][2] - G[0][2] * G[1][1];
+    cg[2][1] = G[0][2] * G[1][0] - G[0][0] * G[1][2];
+    cg[2][2] = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+    const T tr = G[0][0] + G[1][1] + G[2][2];
+    const T s2 = cg[0][0] + cg[1][1] + cg[2][2];
+    const T dG = G[0][0] * cg[0][0] + G[0][1] * cg[0][1] + G[0][2] * cg[0][2];
+    const T delta = tr + s2 + dG;
+    const T J = T(1) + delta;
+    const T a = T(2) * C1 / J, bcoef = T(2) * D1 * delta;
+    const T diagA = s2 + dG;    // (J F - cof F) = diagA I + J G + G^T - cof G
+    const T diagC = T(1) + tr;  // cof F = diagC I - G^T + cof G
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        T A = J * G[j][m] + G[m][j] - cg[j][m] + (j == m ? diagA : T(0));
+        T C = cg[j][m] - G[m][j] + (j == m ? diagC : T(0));
+        P[j][m] = a * A + bcoef * C;
+      }
+  } else {
+    const T dG = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+    const T delta = G[0][0] + G[1][1] + dG;
+    const T J = T(1) + delta;
+    const T a = T(2) * C1 / J, bcoef = T(2) * D1 * delta;
+    const T cg[2][2] = {{G[1][1], -G[1][0]}, {-G[0][1], G[0][0]}};
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        // J F - cof F = det G I + J G + G^T ;  cof F = I + cof G
+        T A = J * G[j][m] + G[m][j] + (j == m ? dG : T(0));
+        T C = cg[j][m] + (j == m ? T(1) : T(0));
+        P[j][m] = a * A + bcoef * C;
+      }
+  }
+}
+
+// p-Laplacian density |g|^p / p (eq. pLaplacian), in double
+template <int DIM, typename T>
+__device__ __forceinline__ double pl_energy(const T g[DIM], double p, bool &bad) {
+  T s = T(0);
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) s += g[m] * g[m];
+  const double W = pow((double)s, 0.5 * p) / p;
+  if (!isfinite(W)) bad = true;
+  return W;
+}
+
+// its gradient |g|^(p-2) g, defined as 0 at g = 0
+template <int DIM, typename T>
+__device__ __forceinline__ void pl_stress(const T g[DIM], T p, T P[DIM]) {
+  T s = T(0);
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) s += g[m] * g[m];
+  const T sc = s > T(0) ? fpow<T>(s, T(0.5) * (p - T(2))) : T(0);
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) P[m] = sc * g[m];
+}
+
+// density dispatch on a D x DIM gradient
+template <int DIM, int D, int KIND, typename T>
+__device__ __forceinline__ double density(const T G[D][DIM], const Params &prm, bool &bad) {
+  if constexpr (KIND == P1E_NEOHOOKE) {
+    return nh_energy<DIM, T>(G, prm.C1, prm.D1, bad);
+  } else {
+    return pl_energy<DIM, T>(G[0], prm.p, bad);
+  }
+}
+
+
+enum { MODE_ENERGY = 0, MODE_FORCE = 1, MODE_FD = 2 };
+
+// one force-record entry: D words of T, loaded and stored as a single vector access
+template <typename T, int D>
+struct Entry {
+  T v[D];
+};
+
+template <typename T, int D, int K>
+__device__ __forceinline__ void store_entries(T *__restrict__ r, int nep, int e, const T *out) {
+#pragma unroll
+  for (int l = 0; l < K; ++l) {
+    Entry<T, D> q;
+#pragma unroll
+    for (int j = 0; j < D; ++j) q.v[j] = out[l * D + j];
+    *reinterpret_cast<Entry<T, D> *>(r + ((int64_t)l * nep + e) * D) = q;
+  }
+}
+
+// The element pass for element e < ne: gather u at the vertices, G = grad u (eq. Dv), the
+// density (energy of the element added to (s, c), bad elements counted in cnt) and, by
+// MODE, the element forces |T| dW/dF grad phi_l (Section 6.2) or the per-element central
+// differences of |T| W under a perturbation of one row of F (Section 6.1), written as
+// vertex-major entries r[l][e] (nep = padded element count).
+// geo: [DIM*DIM][ne] entries of B^-1 followed by [ne] sizes |T|.
+template <int DIM, int D, int KIND, typename T, int MODE>
+__device__ __forceinline__ void element_pass(int e, int ne, int nep,
+                                             const int32_t *__restrict__ conn,
+                                             const T *__restrict__ geo,
+                                             const T *__restrict__ u, T *__restrict__ r,
+                                             const Params &prm, double &s, double &c,
+                                             int &cnt) {
+  constexpr int K = DIM + 1;
+  int nd[K];
+#pragma unroll
+  for (int l = 0; l < K; ++l) nd[l] = conn[(int64_t)l * ne + e];
+  T uu[K][D];
+#pragma unroll
+  for (int l = 0; l < K; ++l) NodeVec<T, D>::load(u, nd[l], uu[l]);
+  T Bi[DIM][DIM];
+#pragma unroll
+  for (int l = 0; l < DIM; ++l)
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) Bi[l][m] = geo[(int64_t)(l * DIM + m) * ne + e];
+  const T vol = geo[(int64_t)(DIM * DIM) * ne + e];
+  // G = D Binv with D[j][l] = u_{l+1}[j] - u_0[j]   (eq. Dv, grad phi_0 = -sum of others)
+  T G[D][DIM];
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < DIM; ++l) acc = mad(uu[l + 1][j] - uu[0][j], Bi[l][m], acc);
+      G[j][m] = acc;
+    }
+  bool bad = false;
+  const double W = density<DIM, D, KIND, T>(G, prm, bad);
+  if constexpr (MODE == MODE_FORCE) {
+    T P[D][DIM];
+    if constexpr (KIND == P1E_NEOHOOKE) {
+      nh_stress<DIM, T>(G, (T)prm.C1, (T)prm.D1, P);
+    } else {
+      pl_stress<DIM, T>(G[0], (T)prm.p, P[0]);
+    }
+    T out[K * D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) out[j] = T(0);
+#pragma unroll
+    for (int l = 1; l < K; ++l)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) acc = mad(P[j][m], Bi[l - 1][m], acc);
+        acc *= vol;
+        out[l * D + j] = acc;
+        out[j] -= acc;
+      }
+    store_entries<T, D, K>(r, nep, e, out);
+  }
+  if constexpr (MODE == MODE_FD) {
+    // Central differences of |T| W under v_n +- eps for every DOF n of this element: only
+    // row j of F changes, by +-eps grad phi_l (Section 6.1). Differenced per element; the
+    // patch sum happens in k_gather.
+    const double inv2e = 1.0 / (2.0 * prm.eps);
+    T out[K * D];
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      T a[DIM];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        if (l == 0) {
+          T t = T(0);
+#pragma unroll
+          for (int q = 0; q < DIM; ++q) t -= Bi[q][m];
+          a[m] = t;
+        } else {
+          a[m] = Bi[l - 1][m];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        T Gp[D][DIM], Gm[D][DIM];
+#pragma unroll
+        for (int jj = 0; jj < D; ++jj)
+#pragma unroll
+          for (int m = 0; m < DIM; ++m) {
+            Gp[jj][m] = G[jj][m];
+            Gm[jj][m] = G[jj][m];
+          }
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+          Gp[j][m] = mad((T)prm.eps, a[m], G[j][m]);
+          Gm[j][m] = mad(-(T)prm.eps, a[m], G[j][m]);
+        }
+        const double Wp = density<DIM, D, KIND, T>(Gp, prm, bad);
+        const double Wm = density<DIM, D, KIND, T>(Gm, prm, bad);
+        out[l * D + j] = (T)((double)vol * (Wp - Wm) * inv2e);
+      }
+    }
+    store_entries<T, D, K>(r, nep, e, out);
+  }
+  if (bad) {
+    cnt += 1;
+  } else {
+    double t, err;
+    two_sum(s, (double)vol * W, t, err);
+    s = t;
+    c += err;
+  }
+}
+
+// The node prepass for node i (caller's order): the nodal field of v (u = v - x when
+// SUB_X) stored at the node's internal position, and b.v of its free DOFs added to (s, c).
+template <typename T, int D, bool SUB_X>
+__device__ __forceinline__ void prepass_node(int i, const int32_t *__restrict__ node_info,
+                                             const int32_t *__restrict__ node_int,
+                                             const double *__restrict__ vhat,
+                                             const double *__restrict__ vD,
+                                             const double *__restrict__ xref,
+                                             const double *__restrict__ bhat,
+                                             T *__restrict__ u, double &s, double &c) {
+  const int info = node_info[i];
+  const int mask = info & 7;
+  int fb = info >> 3;
+  T o[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double val;
+    if ((mask >> j) & 1) {
+      val = vhat[fb];
+      double prod = bhat[fb] * val, t, e;
+      two_sum(s, prod, t, e);
+      s = t;
+      c += e;
+      ++fb;
+    } else {
+      val = vD[(int64_t)i * D + j];
+    }
+    if constexpr (SUB_X) val -= xref[(int64_t)i * D + j];
+    o[j] = (T)val;
+  }
+  NodeVec<T, D>::store(u, node_int[i], o);
+}
+
+// GL lanes per free node: the lanes of a group stride over the node's patch entries (U
+// entries per lane per round, their loads issued together), then combine their sums by a
+// butterfly over the group (every lane ends with the same sum, as FP addition is
+// commutative), and the group's first lane writes g = scale * (sum - b) in free-DOF order
+// (scale: optional device scalar, the incoming gradient of a differentiation hook). Fixed
+// order of operations: deterministic. No atomics. Every lane of the wave must call this
+// (row >= nf for idle lanes).
+template <int K, int D, typename T, int GL, int U>
+__device__ __forceinline__ void gather_row(int row, int sub, int nf, int nep,
+                                           const int32_t *__restrict__ row_ptr,
+                                           const uint32_t *__restrict__ ent,
+                                           const int32_t *__restrict__ row_info,
+                                           const T *__restrict__ r,
+                                           const double *__restrict__ bhat,
+                                           const double *__restrict__ scale,
+                                           double *__restrict__ g) {
+  double acc[D], bv[D];
+  int fb0 = 0, mask = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) acc[j] = bv[j] = 0.0;
+  if (row < nf) {
+    const int t0 = row_ptr[row], t1 = row_ptr[row + 1];
+    // the row's DOF map and load vector do not depend on the entries: fetch them first so
+    // their latency overlaps the entry loads
+    if (sub == 0) {
+      const int info = row_info[row];
+      mask = info & 7;
+      fb0 = info >> 3;
+      int fb = fb0;
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if ((mask >> j) & 1) bv[j] = bhat[fb++];
+    }
+    for (int base = t0 + sub; base < t1; base += GL * U) {
+      // branch-free round: out-of-row slots load the row's last entry and add zero, so
+      // all U loads of the round are in flight together
+      uint32_t x[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = base + u * GL;
+        ok[u] = t < t1;
+        x[u] = ent[ok[u] ? t : t1 - 1];
+      }
+      Entry<T, D> q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        q[u] = *reinterpret_cast<const Entry<T, D> *>(
+            r + ((int64_t)(x[u] & 3) * nep + (x[u] >> 2)) * D);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[j] += ok[u] ? (double)q[u].v[j] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int off = GL / 2; off > 0; off >>= 1)
+#pragma unroll
+    for (int j = 0; j < D; ++j) acc[j] += __shfl_xor(acc[j], off, 64);
+  if (row < nf && sub == 0) {
+    const double sc = scale ? *scale : 1.0;
+    int fb = fb0;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if ((mask >> j) & 1) {
+        g[fb] = sc * (acc[j] - bv[j]);
+        ++fb;
+      }
+  }
+}
+
+}  // namespace dev
+}  // namespace p1e
