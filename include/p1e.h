@@ -156,6 +156,94 @@ int p1e_grad_gather(p1e_mesh *mesh, int prec, const double *scale, double *g, vo
 int p1e_grad_patch_fd(p1e_mesh *mesh, const double *vhat, double eps, double *g,
                       int32_t *flag, void *stream);
 
+/* ------------------------------------------------------------------ minimization
+ * A first-order minimization of J over vhat with the exact gradient, as the paper feeds J and
+ * grad J to an optimizer (Section 7; the paper uses a trust-region method, this library
+ * L-BFGS): memory m, initial inverse Hessian (s.y / y.y) I, a new pair kept only if
+ * s.y > 1e-12 |s||y|, Armijo backtracking (c1 = 1e-4, halving, at most 40 trials), the first
+ * step (and any step after a restart) scaled so that the largest nodal update is 0.1 h with h
+ * the edge of the smallest element's reference cell, and a restart from steepest descent when
+ * the two-loop direction is not a descent direction. Exactly max_iters accepted iterations
+ * unless the gradient vanishes or the line search stalls. */
+typedef struct p1e_lbfgs_opts {
+  int32_t history;   /* m, 1..8 */
+  int32_t max_iters; /* accepted iterations */
+  int32_t prec;      /* P1E_FP64 or P1E_MIXED (the mesh must be bound for it) */
+  int32_t reserved;
+} p1e_lbfgs_opts;
+
+/* status values of a finished minimization */
+#define P1E_MIN_OK 0         /* max_iters iterations done */
+#define P1E_MIN_STALLED 1    /* 40 halvings without sufficient decrease */
+#define P1E_MIN_CONVERGED 2  /* zero gradient */
+#define P1E_MIN_BAD_START (-5) /* the start point has bad elements */
+
+typedef struct p1e_min_report {
+  int32_t status, iterations, evaluations, reserved;
+  double J;      /* final energy */
+  double J_grad; /* J_grad of the last evaluated point */
+} p1e_min_report;
+
+/* Device workspace bytes of p1e_minimize for this mesh and options. */
+uint64_t p1e_minimize_workspace_bytes(const p1e_mesh *mesh, const p1e_lbfgs_opts *opts);
+
+/* Minimize from vhat (device, in/out) on a mesh bound for opts->prec. ws: caller-owned device
+ * buffer (256-byte aligned, p1e_minimize_workspace_bytes). Synchronous on stream. Overwrites
+ * the mesh's force scratch (a following p1e_grad_gather returns P1E_ESTATE). P1E_EDOMAIN if
+ * the start point has bad elements. */
+int p1e_minimize(p1e_mesh *mesh, double *vhat, const p1e_lbfgs_opts *opts, void *ws,
+                 uint64_t ws_bytes, p1e_min_report *report, void *stream);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of many minimizations (as p1e_minimize) of different meshes on one GPU.
+ * Requests are submitted with their mesh description; worker threads build the meshes; a
+ * request is admitted into a slot, in arrival order, once a slot and enough bytes of the
+ * caller's device pool are free; every p1e_server_step advances all admitted requests by one
+ * line-search trial with one fixed sequence of batched launches (replayed from a hipGraph when
+ * use_graph is set), and retires finished ones, freeing their slot and pool bytes. Each
+ * request's result is bitwise the same as when it runs alone. The server is driven by one
+ * thread (submit/step/poll); submission may come from any thread. */
+typedef struct p1e_server p1e_server;
+
+typedef struct p1e_server_opts {
+  int32_t max_slots;     /* requests on the device at once, 1..4096 */
+  int32_t history;       /* L-BFGS memory, 1..8 */
+  int32_t max_iters;     /* accepted iterations per request */
+  int32_t prec;          /* P1E_FP64 or P1E_MIXED */
+  int32_t use_graph;     /* replay the step from a captured hipGraph (needs a non-NULL stream) */
+  int32_t setup_threads; /* host threads building meshes */
+  uint64_t pool_bytes;   /* size of pool */
+  void *pool;            /* caller-owned device buffer, 256-byte aligned, kept alive until destroy */
+  void *stream;          /* hipStream_t for all device work */
+} p1e_server_opts;
+
+typedef struct p1e_request_info {
+  int64_t id;
+  int32_t status;      /* P1E_MIN_* or a negative P1E_E* setup/admission error */
+  int32_t iterations, evaluations, n_free_dofs;
+  double J, J_grad;
+  double t_submit, t_admit, t_done; /* seconds on the server clock (p1e_server_clock) */
+  uint64_t device_bytes;            /* pool bytes the request held */
+} p1e_request_info;
+
+/* Bytes at the head of the pool used for the engine tables. */
+uint64_t p1e_server_table_bytes(int32_t max_slots, uint64_t pool_bytes);
+int p1e_server_create(const p1e_server_opts *opts, p1e_server **out);
+void p1e_server_destroy(p1e_server *server);
+double p1e_server_clock(const p1e_server *server);
+/* Copies the description (and the optional start point vhat0[n0] on the host; NULL: the
+ * prescribed values, v = x for Neo-Hookean and 0 for the p-Laplacian); returns its id. */
+int p1e_server_submit(p1e_server *server, const p1e_mesh_desc *desc, const double *vhat0,
+                      int64_t n0, int64_t *id);
+/* Retire finished requests, admit waiting ones, enqueue one step; reports the numbers of
+ * admitted and of submitted-but-not-admitted requests. */
+int p1e_server_step(p1e_server *server, int32_t *n_active, int32_t *n_waiting);
+/* Finished requests not reported before (up to cap). */
+int p1e_server_poll(p1e_server *server, p1e_request_info *out, int32_t cap, int32_t *n);
+/* Final vhat of a finished request (host copy of n doubles), until p1e_server_release. */
+int p1e_server_result_vhat(p1e_server *server, int64_t id, double *dst, int64_t n);
+int p1e_server_release(p1e_server *server, int64_t id);
+
 /* Thread-local message of the last failure ("" if none). */
 const char *p1e_last_error(void);
 

@@ -8,8 +8,8 @@ from ._lib import (  # noqa: F401
     P1E_FD, P1E_FP64, P1E_LOCALITY_ORDER, P1E_MIXED, P1E_NEOHOOKE, P1E_PLAPLACE, P1EError, lib,
 )
 from .api import (  # noqa: F401
-    Mesh, energy, energy_forces, grad_exact, grad_gather, grad_patch_fd, mesh_bind, mesh_create,
-    mesh_destroy,
+    Mesh, Server, energy, energy_forces, grad_exact, grad_gather, grad_patch_fd, mesh_bind,
+    mesh_create, mesh_destroy, mesh_minimize, minimize, minimize_workspace_bytes,
     mesh_get_info, neohooke_constants, prof_collect, prof_enable, prof_reset, workspace_bytes,
 )
 from .autograd import P1Energy, p1_energy  # noqa: F401

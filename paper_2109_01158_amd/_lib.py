@@ -57,6 +57,37 @@ class MeshInfo(ctypes.Structure):
     ]
 
 
+class LbfgsOpts(ctypes.Structure):
+    _fields_ = [("history", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class MinReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("evaluations", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("J", ctypes.c_double), ("J_grad", ctypes.c_double)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("history", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("setup_threads", ctypes.c_int32),
+                ("pool_bytes", ctypes.c_uint64), ("pool", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("evaluations", ctypes.c_int32),
+                ("n_free_dofs", ctypes.c_int32), ("J", ctypes.c_double),
+                ("J_grad", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+P1E_MIN_OK, P1E_MIN_STALLED, P1E_MIN_CONVERGED, P1E_MIN_BAD_START = 0, 1, 2, -5
+
+
 class P1EError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"p1e status {STATUS_NAMES.get(status, status)}: {msg}")
@@ -89,6 +120,20 @@ def lib():
         "p1e_energy_forces": ([vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "p1e_grad_gather": ([vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "p1e_last_error": ([], ctypes.c_char_p),
+        "p1e_minimize_workspace_bytes": ([vp, ctypes.POINTER(LbfgsOpts)], u64),
+        "p1e_minimize": ([vp, vp, ctypes.POINTER(LbfgsOpts), vp, u64, ctypes.POINTER(MinReport),
+                          vp], ctypes.c_int),
+        "p1e_server_table_bytes": ([i32, u64], u64),
+        "p1e_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)], ctypes.c_int),
+        "p1e_server_destroy": ([vp], None),
+        "p1e_server_clock": ([vp], dbl),
+        "p1e_server_submit": ([vp, ctypes.POINTER(MeshDesc), vp, i64, ctypes.POINTER(i64)],
+                              ctypes.c_int),
+        "p1e_server_step": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
+        "p1e_server_poll": ([vp, ctypes.POINTER(RequestInfo), i32, ctypes.POINTER(i32)],
+                            ctypes.c_int),
+        "p1e_server_result_vhat": ([vp, i64, vp, i64], ctypes.c_int),
+        "p1e_server_release": ([vp, i64], ctypes.c_int),
         "p1e_prof_enable": ([ctypes.c_int], ctypes.c_int),
         "p1e_prof_reset": ([], ctypes.c_int),
         "p1e_prof_collect": ([vp, i64, vp, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),

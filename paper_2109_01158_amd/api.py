@@ -237,3 +237,130 @@ class Mesh:
         grad_patch_fd(self.handle, vhat, eps, g, flag, stream)
         self.forces_gen += 1
         return g, flag
+
+
+# ------------------------------------------------------------------ minimization
+def minimize_workspace_bytes(handle, history=5, max_iters=200, prec="fp64"):
+    o = L.LbfgsOpts(int(history), int(max_iters), PREC[prec], 0)
+    return int(L.lib().p1e_minimize_workspace_bytes(ctypes.c_void_p(handle), ctypes.byref(o)))
+
+
+def minimize(handle, vhat, history, max_iters, prec, ws, stream=None):
+    """p1e_minimize: vhat (device f64, in/out), ws a device uint8 tensor (256-byte aligned).
+    Returns the report as a dict."""
+    o = L.LbfgsOpts(int(history), int(max_iters), PREC[prec], 0)
+    rep = L.MinReport()
+    check(L.lib().p1e_minimize(ctypes.c_void_p(handle), _dptr(vhat), ctypes.byref(o),
+                               ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.byref(rep),
+                               _stream_ptr(stream, ws.device)))
+    return {name: getattr(rep, name) for name, _ in L.MinReport._fields_ if name != "reserved"}
+
+
+def _aligned_buffer(nbytes, device, align=256):
+    raw = torch.empty(nbytes + align, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % align
+    return raw, raw[off: off + nbytes]
+
+
+def mesh_minimize(mesh, vhat, history=5, max_iters=200, prec="fp64", stream=None):
+    """Minimize in place from vhat on a bound Mesh (allocates the workspace with torch)."""
+    nb = minimize_workspace_bytes(mesh.handle, history, max_iters, prec)
+    raw, ws = _aligned_buffer(nb, mesh.device)
+    rep = minimize(mesh.handle, vhat, history, max_iters, prec, ws, stream)
+    mesh.forces_gen += 1
+    del raw
+    return rep
+
+
+# ------------------------------------------------------------------ serving
+def _desc_of(prob, flags=0):
+    """A MeshDesc for a p1e_synth.Problem-like object; returns (desc, arrays kept alive)."""
+    if prob.kind == "neohooke":
+        C1, D1 = neohooke_constants(prob.E, prob.nu)
+        k, p = P1E_NEOHOOKE, 2.0
+    else:
+        C1 = D1 = 0.0
+        k, p = P1E_PLAPLACE, prob.p
+    conn = np.ascontiguousarray(prob.conn, dtype=np.int32)
+    coords = np.ascontiguousarray(prob.coords, dtype=np.float64)
+    dm = np.ascontiguousarray(prob.dirichlet, dtype=np.uint8)
+    dv = np.ascontiguousarray(prob.dirichlet_values, dtype=np.float64)
+    f = np.ascontiguousarray(prob.load, dtype=np.float64)
+    desc = L.MeshDesc(prob.dim, prob.ncomp, k, int(flags), coords.shape[0], conn.shape[0],
+                      _ptr(conn), _ptr(coords), _ptr(dm), _ptr(dv), _ptr(f), float(p), float(C1),
+                      float(D1))
+    return desc, (conn, coords, dm, dv, f)
+
+
+class Server:
+    """Continuous-batching minimization server on one GPU (p1e_server_*).
+
+    The pool is a torch-owned device buffer; all work runs on a dedicated torch stream (default
+    priority). Drive it from one thread: submit(), step() until idle, poll()."""
+
+    def __init__(self, pool_bytes, max_slots=256, history=5, max_iters=200, prec="fp64",
+                 use_graph=True, setup_threads=8, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self._raw, self.pool = _aligned_buffer(int(pool_bytes), self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        o = L.ServerOpts(int(max_slots), int(history), int(max_iters), PREC[prec],
+                         1 if use_graph else 0, int(setup_threads), int(pool_bytes),
+                         ctypes.c_void_p(self.pool.data_ptr()),
+                         ctypes.c_void_p(self.stream.cuda_stream))
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            check(L.lib().p1e_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            with torch.cuda.device(self.device):
+                L.lib().p1e_server_destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+            torch.cuda.synchronize(self.device)
+            self._raw = self.pool = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clock(self):
+        return float(L.lib().p1e_server_clock(ctypes.c_void_p(self.handle)))
+
+    def submit(self, prob, vhat0=None, flags=0):
+        desc, keep = _desc_of(prob, flags)
+        rid = ctypes.c_int64()
+        v0 = None if vhat0 is None else np.ascontiguousarray(vhat0, dtype=np.float64)
+        check(L.lib().p1e_server_submit(ctypes.c_void_p(self.handle), ctypes.byref(desc),
+                                        _ptr(v0), 0 if v0 is None else v0.size,
+                                        ctypes.byref(rid)))
+        del keep
+        return rid.value
+
+    def step(self):
+        a, w = ctypes.c_int32(), ctypes.c_int32()
+        with torch.cuda.device(self.device):
+            check(L.lib().p1e_server_step(ctypes.c_void_p(self.handle), ctypes.byref(a),
+                                          ctypes.byref(w)))
+        return a.value, w.value
+
+    def poll(self, cap=1024):
+        buf = (L.RequestInfo * cap)()
+        n = ctypes.c_int32()
+        check(L.lib().p1e_server_poll(ctypes.c_void_p(self.handle), buf, cap, ctypes.byref(n)))
+        return [{name: getattr(buf[i], name) for name, _ in L.RequestInfo._fields_}
+                for i in range(n.value)]
+
+    def result_vhat(self, rid, n):
+        out = np.zeros(int(n))
+        check(L.lib().p1e_server_result_vhat(ctypes.c_void_p(self.handle), int(rid),
+                                             _ptr(out), int(n)))
+        return out
+
+    def release(self, rid):
+        check(L.lib().p1e_server_release(ctypes.c_void_p(self.handle), int(rid)))

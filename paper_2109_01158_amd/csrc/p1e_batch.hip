@@ -1,0 +1,567 @@
+// p1e_batch.hip -- batched kernels of the multi-request engine: every kernel walks a device
+// table of (slot, tile) pairs with a fixed grid (grid-stride), so one launch covers all active
+// requests of an element class and the launch parameters never change while requests come
+// and go. Each slot's work is split into the same tiles and reduced in the same order whether
+// it runs alone or among others, so its results are bitwise identical either way.
+//
+// One engine step advances every active slot by one L-BFGS line-search trial (memory m,
+// two-loop recursion with H0 = (s.y / y.y) I, Armijo backtracking by halving, first step
+// scaled so that the largest nodal update is 0.1 h):
+//   evaluate   J and grad J at the trial point vt (prepass, element forces, finalize, patch
+//              gather; the same bodies as the single-mesh path, Sections 5 and 6.2)
+//   decide     accept (Armijo) or halve the step
+//   update     v, g and the newest (s, y) pair of accepted slots; trial point of rejected ones
+//   direction  two-loop recursion for slots that accepted, then the next trial point
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "p1e_device.h"
+#include "p1e_internal.h"
+
+namespace p1e {
+namespace {
+
+using namespace dev;
+
+constexpr double kArmijo = 1e-4;
+constexpr int kVB = 256;  // threads of the vector and per-slot kernels
+
+__device__ __forceinline__ int slot_mode(const EngineDev &E, int slot) {
+  return E.st[slot * kNSt + ST_MODE];
+}
+__device__ __forceinline__ bool evaluating(const EngineDev &E, int slot) {
+  const int m = slot_mode(E, slot);
+  return m == MODE_INIT || m == MODE_TRIAL;
+}
+
+// the tiles of kind K and class C: [map + off, map + off + count)
+template <int K, int C>
+__device__ __forceinline__ const int2 *tiles(const EngineDev &E, int &count) {
+  const int off = E.counts[2 * (K * kNumClasses + C)];
+  count = E.counts[2 * (K * kNumClasses + C) + 1];
+  return E.map[K] + off;
+}
+
+// ----------------------------------------------------------------------- evaluation
+template <typename T, int D, bool SUBX, int CLS>
+__global__ __launch_bounds__(kBlockNode) void kb_prepass(EngineDev E) {
+  int count;
+  const int2 *tl = tiles<TK_NODE, CLS>(E, count);
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const int2 st = tl[t];
+    if (!evaluating(E, st.x)) continue;
+    const SlotDev &S = E.slots[st.x];
+    const int i = st.y * kBlockNode + threadIdx.x;
+    double s = 0.0, c = 0.0;
+    int cnt = 0;
+    if (i < S.nn)
+      prepass_node<T, D, SUBX>(i, S.node_info, S.node_int, S.vt, S.vD, S.xref, S.bhat, (T *)S.u,
+                               s, c);
+    block_reduce<kBlockNode>(s, c, cnt);
+    if (threadIdx.x == 0) S.part[S.ntile_e + st.y] = make_double2(s, c);
+    __syncthreads();
+  }
+}
+
+template <int DIM, int D, int KIND, typename T, int CLS>
+__global__ __launch_bounds__(kBlockElem) void kb_element(EngineDev E) {
+  int count;
+  const int2 *tl = tiles<TK_ELEM, CLS>(E, count);
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const int2 st = tl[t];
+    if (!evaluating(E, st.x)) continue;
+    const SlotDev &S = E.slots[st.x];
+    const int e = st.y * kBlockElem + threadIdx.x;
+    double s = 0.0, c = 0.0;
+    int cnt = 0;
+    if (e < S.ne) {
+      const Params prm{S.C1, S.D1, S.p, 0.0};
+      element_pass<DIM, D, KIND, T, MODE_FORCE>(e, S.ne, S.nep, S.conn, (const T *)S.geo,
+                                                (const T *)S.u, (T *)S.r, prm, s, c, cnt);
+    }
+    block_reduce<kBlockElem>(s, c, cnt);
+    if (threadIdx.x == 0) {
+      S.part[st.y] = make_double2(s, c);
+      S.badp[st.y] = cnt;
+    }
+    __syncthreads();
+  }
+}
+
+template <int K, int D, typename T, int GL, int CLS>
+__global__ __launch_bounds__(kBlock) void kb_gather(EngineDev E) {
+  int count;
+  const int2 *tl = tiles<TK_ROW, CLS>(E, count);
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const int2 st = tl[t];
+    if (!evaluating(E, st.x)) continue;
+    const SlotDev &S = E.slots[st.x];
+    const int row = st.y * (kBlock / GL) + threadIdx.x / GL;
+    gather_row<K, D, T, GL, P1E_GATHER_UNROLL>(row, threadIdx.x % GL, S.nf, S.nep, S.row_ptr,
+                                               S.ent, S.row_info, (const T *)S.r, S.bhat,
+                                               nullptr, S.gt);
+  }
+}
+
+// (s, c) sum of n pairs p[stride * i + off] in a fixed order; every thread of the block
+// calls it, thread 0 gets the result
+__device__ __forceinline__ void slot_sum(const double2 *p, int n, int stride, int off,
+                                         const int32_t *cntp, double &s, double &c, int &cnt) {
+  s = 0.0, c = 0.0;
+  cnt = 0;
+  for (int i = threadIdx.x; i < n; i += kVB) {
+    const double2 q = p[(int64_t)stride * i + off];
+    pair_add(s, c, q.x, q.y);
+    if (cntp) cnt += cntp[i];
+  }
+  block_reduce<kVB>(s, c, cnt);
+}
+
+// max over n values p[stride * i + off].x, thread 0 gets it
+__device__ __forceinline__ double slot_max(const double2 *p, int n, int stride, int off) {
+  __shared__ double sh[kVB / 64];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += kVB) m = fmax(m, p[(int64_t)stride * i + off].x);
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < kVB / 64; ++w) m = fmax(m, sh[w]);
+  __syncthreads();
+  return m;
+}
+
+// one block per slot: J_t = J_grad - b.v of the trial point, and its bad-element count
+__global__ __launch_bounds__(kVB) void kb_finalize(EngineDev E) {
+  const int slot = blockIdx.x;
+  if (!evaluating(E, slot)) return;
+  const SlotDev &S = E.slots[slot];
+  double s, c, s2, c2;
+  int cnt, dummy;
+  slot_sum(S.part, S.ntile_e, 1, 0, S.badp, s, c, cnt);
+  slot_sum(S.part + S.ntile_e, S.ntile_n, 1, 0, nullptr, s2, c2, dummy);
+  if (threadIdx.x == 0) {
+    double *sc = E.sc + slot * kNSc;
+    int *st = E.st + slot * kNSt;
+    pair_add(s2, c2, S.dirichlet_bv, 0.0);
+    const double jg = s + c, bv = s2 + c2;
+    sc[SC_JG] = jg;
+    sc[SC_BV] = bv;
+    sc[SC_JT] = cnt ? INFINITY : jg - bv;
+    st[ST_BAD] = cnt;
+    st[ST_EVALS] += 1;
+  }
+}
+
+// ----------------------------------------------------------------------- line search
+// one thread per slot: accept the trial point (Armijo) or halve the step
+__global__ __launch_bounds__(kVB) void kb_decide(EngineDev E) {
+  const int slot = blockIdx.x * kVB + threadIdx.x;
+  if (slot >= E.max_slots) return;
+  double *sc = E.sc + slot * kNSc;
+  int *st = E.st + slot * kNSt;
+  const int mode = st[ST_MODE];
+  int acc = 0, needdir = 0;
+  if (mode == MODE_INIT) {
+    if (st[ST_BAD] != 0 || !isfinite(sc[SC_JT])) {
+      st[ST_MODE] = MODE_DONE;
+      st[ST_STATUS] = SLOT_BAD_START;
+    } else {
+      sc[SC_J] = sc[SC_JT];
+      acc = 1;
+      needdir = st[ST_MAXIT] > 0;
+      if (!needdir) st[ST_MODE] = MODE_DONE;
+    }
+  } else if (mode == MODE_TRIAL) {
+    const double Jt = sc[SC_JT];
+    const bool ok = st[ST_BAD] == 0 && isfinite(Jt) &&
+                    Jt <= sc[SC_J] + kArmijo * sc[SC_ALPHA] * sc[SC_GTD];
+    if (ok) {
+      acc = 2;
+      sc[SC_J] = Jt;
+      st[ST_ITER] += 1;
+      st[ST_NEXT] = (st[ST_HEAD] + 1) % E.history;
+      needdir = st[ST_ITER] < st[ST_MAXIT];
+      if (!needdir) {
+        st[ST_MODE] = MODE_DONE;
+        st[ST_STATUS] = SLOT_OK;
+      }
+    } else if (++st[ST_TRIALS] >= kMaxLineTrials) {
+      st[ST_MODE] = MODE_DONE;
+      st[ST_STATUS] = SLOT_STALLED;
+    } else {
+      sc[SC_ALPHA] *= 0.5;
+    }
+  }
+  st[ST_ACC] = acc;
+  st[ST_NEEDDIR] = needdir;
+}
+
+// per-tile view of a slot's vectors for the vector kernels
+struct VTile {
+  int slot, n, i0;
+};
+__device__ __forceinline__ VTile vtile(const EngineDev &E, int t) {
+  const int2 st = E.vmap[t];
+  VTile v;
+  v.slot = st.x;
+  v.n = E.slots[st.x].nfd;
+  v.i0 = st.y * kVecTile;
+  return v;
+}
+
+// accepted slots: newest (s, y) pair and v, g <- vt, gt, with the partial dots y.s, y.y, s.s;
+// rejected slots: the next trial point v + alpha d
+__global__ __launch_bounds__(kVB) void kb_vupdate(EngineDev E) {
+  const int count = E.counts[kCountVec];
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const VTile V = vtile(E, t);
+    const SlotDev &S = E.slots[V.slot];
+    const int *st = E.st + V.slot * kNSt;
+    const int acc = st[ST_ACC], mode = st[ST_MODE];
+    if (acc == 0) {
+      if (mode == MODE_TRIAL) {
+        const double alpha = E.sc[V.slot * kNSc + SC_ALPHA];
+        for (int k = 0; k < kVecTile; k += kVB) {
+          const int i = V.i0 + k + threadIdx.x;
+          if (i < V.n) S.vt[i] = S.v[i] + alpha * S.d[i];
+        }
+      }
+      continue;
+    }
+    double q[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    const int64_t off = (int64_t)st[ST_NEXT] * V.n;
+    for (int k = 0; k < kVecTile; k += kVB) {
+      const int i = V.i0 + k + threadIdx.x;
+      if (i < V.n) {
+        const double vt = S.vt[i], gt = S.gt[i];
+        if (acc == 2) {
+          const double sv = vt - S.v[i], yv = gt - S.g[i];
+          S.S[off + i] = sv;
+          S.Y[off + i] = yv;
+          double tt, e;
+          two_sum(q[0][0], yv * sv, tt, e), q[0][0] = tt, q[0][1] += e;
+          two_sum(q[1][0], yv * yv, tt, e), q[1][0] = tt, q[1][1] += e;
+          two_sum(q[2][0], sv * sv, tt, e), q[2][0] = tt, q[2][1] += e;
+        }
+        S.v[i] = vt;
+        S.g[i] = gt;
+      }
+    }
+    if (acc == 2) {
+      int cnt = 0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        block_reduce<kVB>(q[j][0], q[j][1], cnt);
+        if (threadIdx.x == 0) S.vpart[4 * (V.i0 / kVecTile) + j] = make_double2(q[j][0], q[j][1]);
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// one block per accepted slot: keep the new pair if s.y > 1e-12 |s||y| (then rho, gamma)
+__global__ __launch_bounds__(kVB) void kb_hist(EngineDev E) {
+  const int slot = blockIdx.x;
+  int *st = E.st + slot * kNSt;
+  if (st[ST_ACC] != 2) return;
+  const SlotDev &S = E.slots[slot];
+  double r[3];
+  for (int j = 0; j < 3; ++j) {
+    double s, c;
+    int cnt;
+    slot_sum(S.vpart, S.ntile_v, 4, j, nullptr, s, c, cnt);
+    r[j] = s + c;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double *sc = E.sc + slot * kNSc;
+    const double ys = r[0], yy = r[1], ss = r[2];
+    const int m = E.history;
+    if (ys > 1e-12 * sqrt(yy * ss) && isfinite(ys) && yy > 0.0) {
+      const int next = st[ST_NEXT];
+      st[ST_HEAD] = next;
+      st[ST_NH] = min(st[ST_NH] + 1, m);
+      sc[SC_RHO0 + next] = 1.0 / ys;
+      sc[SC_GAMMA] = ys / yy;
+    } else if (st[ST_NH] == m) {
+      st[ST_NH] = m - 1;  // the oldest pair was overwritten by the rejected one
+    }
+  }
+}
+
+// ----------------------------------------------------------------------- direction
+__device__ __forceinline__ bool needs_dir(const EngineDev &E, int slot) {
+  return E.st[slot * kNSt + ST_NEEDDIR] != 0;
+}
+
+// history index of loop position i (0 = newest) or -1 if beyond the stored pairs
+__device__ __forceinline__ int hist_index(const EngineDev &E, int slot, int i) {
+  const int *st = E.st + slot * kNSt;
+  if (i >= st[ST_NH]) return -1;
+  return (st[ST_HEAD] - i + E.history) % E.history;
+}
+
+// d = g for slots that need a new direction
+__global__ __launch_bounds__(kVB) void kb_vcopy(EngineDev E) {
+  const int count = E.counts[kCountVec];
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const VTile V = vtile(E, t);
+    if (!needs_dir(E, V.slot)) continue;
+    const SlotDev &S = E.slots[V.slot];
+    for (int k = 0; k < kVecTile; k += kVB) {
+      const int i = V.i0 + k + threadIdx.x;
+      if (i < V.n) S.d[i] = S.g[i];
+    }
+  }
+}
+
+// partial of (S or Y)[hist i] . d
+__global__ __launch_bounds__(kVB) void kb_vdot(EngineDev E, int i, int use_y) {
+  const int count = E.counts[kCountVec];
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const VTile V = vtile(E, t);
+    if (!needs_dir(E, V.slot)) continue;
+    const int h = hist_index(E, V.slot, i);
+    if (h < 0) continue;
+    const SlotDev &S = E.slots[V.slot];
+    const double *w = (use_y ? S.Y : S.S) + (int64_t)h * V.n;
+    double s = 0.0, c = 0.0;
+    int cnt = 0;
+    for (int k = 0; k < kVecTile; k += kVB) {
+      const int j = V.i0 + k + threadIdx.x;
+      if (j < V.n) {
+        double tt, e;
+        two_sum(s, w[j] * S.d[j], tt, e);
+        s = tt;
+        c += e;
+      }
+    }
+    block_reduce<kVB>(s, c, cnt);
+    if (threadIdx.x == 0) S.vpart[4 * (V.i0 / kVecTile)] = make_double2(s, c);
+    __syncthreads();
+  }
+}
+
+// one block per slot: first loop (phase 0) a_i = rho s_i.q, coef = -a_i;
+// second loop (phase 1) b = rho y_i.r, coef = a_i - b
+__global__ __launch_bounds__(kVB) void kb_coef(EngineDev E, int i, int phase) {
+  const int slot = blockIdx.x;
+  if (!needs_dir(E, slot)) return;
+  const int h = hist_index(E, slot, i);
+  if (h < 0) return;
+  const SlotDev &S = E.slots[slot];
+  double s, c;
+  int cnt;
+  slot_sum(S.vpart, S.ntile_v, 4, 0, nullptr, s, c, cnt);
+  if (threadIdx.x == 0) {
+    double *sc = E.sc + slot * kNSc;
+    const double dot = (s + c) * sc[SC_RHO0 + h];
+    if (phase == 0) {
+      sc[SC_A0 + i] = dot;
+      sc[SC_COEF] = -dot;
+    } else {
+      sc[SC_COEF] = sc[SC_A0 + i] - dot;
+    }
+  }
+}
+
+// d += coef * (S or Y)[hist i]
+__global__ __launch_bounds__(kVB) void kb_vaxpy(EngineDev E, int i, int use_y) {
+  const int count = E.counts[kCountVec];
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const VTile V = vtile(E, t);
+    if (!needs_dir(E, V.slot)) continue;
+    const int h = hist_index(E, V.slot, i);
+    if (h < 0) continue;
+    const SlotDev &S = E.slots[V.slot];
+    const double coef = E.sc[V.slot * kNSc + SC_COEF];
+    const double *w = (use_y ? S.Y : S.S) + (int64_t)h * V.n;
+    for (int k = 0; k < kVecTile; k += kVB) {
+      const int j = V.i0 + k + threadIdx.x;
+      if (j < V.n) S.d[j] = fma(coef, w[j], S.d[j]);
+    }
+  }
+}
+
+// d *= gamma (H0 = gamma I) when pairs are stored
+__global__ __launch_bounds__(kVB) void kb_vscale(EngineDev E) {
+  const int count = E.counts[kCountVec];
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const VTile V = vtile(E, t);
+    if (!needs_dir(E, V.slot) || E.st[V.slot * kNSt + ST_NH] == 0) continue;
+    const SlotDev &S = E.slots[V.slot];
+    const double gamma = E.sc[V.slot * kNSc + SC_GAMMA];
+    for (int k = 0; k < kVecTile; k += kVB) {
+      const int j = V.i0 + k + threadIdx.x;
+      if (j < V.n) S.d[j] *= gamma;
+    }
+  }
+}
+
+// d = -d, partials g.d, max|d|, g.g, max|g|
+__global__ __launch_bounds__(kVB) void kb_vneg(EngineDev E) {
+  __shared__ double sh[2][kVB / 64];
+  const int count = E.counts[kCountVec];
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const VTile V = vtile(E, t);
+    if (!needs_dir(E, V.slot)) continue;
+    const SlotDev &S = E.slots[V.slot];
+    double gd = 0, gdc = 0, gg = 0, ggc = 0, md = 0, mg = 0;
+    for (int k = 0; k < kVecTile; k += kVB) {
+      const int j = V.i0 + k + threadIdx.x;
+      if (j < V.n) {
+        const double dj = -S.d[j], gj = S.g[j];
+        S.d[j] = dj;
+        double tt, e;
+        two_sum(gd, gj * dj, tt, e), gd = tt, gdc += e;
+        two_sum(gg, gj * gj, tt, e), gg = tt, ggc += e;
+        md = fmax(md, fabs(dj));
+        mg = fmax(mg, fabs(gj));
+      }
+    }
+    int cnt = 0;
+    block_reduce<kVB>(gd, gdc, cnt);
+    __syncthreads();
+    block_reduce<kVB>(gg, ggc, cnt);
+    for (int o = 32; o > 0; o >>= 1) {
+      md = fmax(md, __shfl_down(md, o, 64));
+      mg = fmax(mg, __shfl_down(mg, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      sh[0][threadIdx.x >> 6] = md;
+      sh[1][threadIdx.x >> 6] = mg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < kVB / 64; ++w) {
+        md = fmax(md, sh[0][w]);
+        mg = fmax(mg, sh[1][w]);
+      }
+      double2 *p = S.vpart + 4 * (V.i0 / kVecTile);
+      p[0] = make_double2(gd, gdc);
+      p[1] = make_double2(md, 0.0);
+      p[2] = make_double2(gg, ggc);
+      p[3] = make_double2(mg, 0.0);
+    }
+    __syncthreads();
+  }
+}
+
+// one block per slot: directional derivative, fallback to steepest descent, first step size
+__global__ __launch_bounds__(kVB) void kb_dirfin(EngineDev E) {
+  const int slot = blockIdx.x;
+  if (!needs_dir(E, slot)) return;
+  const SlotDev &S = E.slots[slot];
+  double s, c, s2, c2;
+  int cnt;
+  slot_sum(S.vpart, S.ntile_v, 4, 0, nullptr, s, c, cnt);
+  __syncthreads();
+  slot_sum(S.vpart, S.ntile_v, 4, 2, nullptr, s2, c2, cnt);
+  const double md = slot_max(S.vpart, S.ntile_v, 4, 1);
+  const double mg = slot_max(S.vpart, S.ntile_v, 4, 3);
+  if (threadIdx.x == 0) {
+    double *sc = E.sc + slot * kNSc;
+    int *st = E.st + slot * kNSt;
+    double gtd = s + c, maxd = md;
+    int reset = 0;
+    if (!(gtd < 0.0) || !isfinite(gtd) || !(maxd > 0.0) || !isfinite(maxd)) {
+      reset = 1;  // not a descent direction: restart from steepest descent
+      st[ST_NH] = 0;
+      gtd = -(s2 + c2);
+      maxd = mg;
+    }
+    st[ST_RESET] = reset;
+    if (!(maxd > 0.0)) {  // zero gradient: stationary point reached
+      st[ST_MODE] = MODE_DONE;
+      st[ST_STATUS] = SLOT_CONVERGED;
+      st[ST_NEEDDIR] = 0;
+      return;
+    }
+    sc[SC_GTD] = gtd;
+    sc[SC_MAXD] = maxd;
+    sc[SC_ALPHA] = st[ST_NH] == 0 ? fmin(1.0, 0.1 * sc[SC_H] / maxd) : 1.0;
+    st[ST_MODE] = MODE_TRIAL;
+    st[ST_TRIALS] = 0;
+  }
+}
+
+// trial point vt = v + alpha d (d = -g after a restart)
+__global__ __launch_bounds__(kVB) void kb_vtrial(EngineDev E) {
+  const int count = E.counts[kCountVec];
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const VTile V = vtile(E, t);
+    if (!needs_dir(E, V.slot)) continue;
+    const SlotDev &S = E.slots[V.slot];
+    const double alpha = E.sc[V.slot * kNSc + SC_ALPHA];
+    const bool reset = E.st[V.slot * kNSt + ST_RESET] != 0;
+    for (int k = 0; k < kVecTile; k += kVB) {
+      const int j = V.i0 + k + threadIdx.x;
+      if (j < V.n) {
+        double dj = S.d[j];
+        if (reset) S.d[j] = dj = -S.g[j];
+        S.vt[j] = S.v[j] + alpha * dj;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------- launch sequence
+constexpr int kGridElem = 2048, kGridNode = 512, kGridRow = 4096, kGridVec = 2048;
+
+template <typename T>
+int eval_launches(const EngineDev &E, hipStream_t s) {
+  hipLaunchKernelGGL((kb_prepass<T, 1, false, CLS_PLAP2>), dim3(kGridNode), dim3(kBlockNode), 0, s, E);
+  hipLaunchKernelGGL((kb_prepass<T, 1, false, CLS_PLAP3>), dim3(kGridNode), dim3(kBlockNode), 0, s, E);
+  hipLaunchKernelGGL((kb_prepass<T, 2, true, CLS_NH2>), dim3(kGridNode), dim3(kBlockNode), 0, s, E);
+  hipLaunchKernelGGL((kb_prepass<T, 3, true, CLS_NH3>), dim3(kGridNode), dim3(kBlockNode), 0, s, E);
+  hipLaunchKernelGGL((kb_element<2, 1, P1E_PLAPLACE, T, CLS_PLAP2>), dim3(kGridElem), dim3(kBlockElem), 0, s, E);
+  hipLaunchKernelGGL((kb_element<3, 1, P1E_PLAPLACE, T, CLS_PLAP3>), dim3(kGridElem), dim3(kBlockElem), 0, s, E);
+  hipLaunchKernelGGL((kb_element<2, 2, P1E_NEOHOOKE, T, CLS_NH2>), dim3(kGridElem), dim3(kBlockElem), 0, s, E);
+  hipLaunchKernelGGL((kb_element<3, 3, P1E_NEOHOOKE, T, CLS_NH3>), dim3(kGridElem), dim3(kBlockElem), 0, s, E);
+  hipLaunchKernelGGL(kb_finalize, dim3(E.max_slots), dim3(kVB), 0, s, E);
+  hipLaunchKernelGGL((kb_gather<3, 1, T, P1E_GATHER_LANES_2D, CLS_PLAP2>), dim3(kGridRow), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_gather<4, 1, T, P1E_GATHER_LANES_3D, CLS_PLAP3>), dim3(kGridRow), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_gather<3, 2, T, P1E_GATHER_LANES_2D, CLS_NH2>), dim3(kGridRow), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_gather<4, 3, T, P1E_GATHER_LANES_3D, CLS_NH3>), dim3(kGridRow), dim3(kBlock), 0, s, E);
+  return P1E_OK;
+}
+
+}  // namespace
+
+int rows_per_tile(int cls) {
+  const int gl = (cls == CLS_PLAP3 || cls == CLS_NH3) ? P1E_GATHER_LANES_3D : P1E_GATHER_LANES_2D;
+  return kBlock / gl;
+}
+
+int batch_step(const EngineDev &E, hipStream_t s) {
+  if (E.prec == P1E_MIXED) eval_launches<float>(E, s);
+  else eval_launches<double>(E, s);
+  const int sb = (E.max_slots + kVB - 1) / kVB;
+  hipLaunchKernelGGL(kb_decide, dim3(sb), dim3(kVB), 0, s, E);
+  hipLaunchKernelGGL(kb_vupdate, dim3(kGridVec), dim3(kVB), 0, s, E);
+  hipLaunchKernelGGL(kb_hist, dim3(E.max_slots), dim3(kVB), 0, s, E);
+  hipLaunchKernelGGL(kb_vcopy, dim3(kGridVec), dim3(kVB), 0, s, E);
+  for (int i = 0; i < E.history; ++i) {
+    hipLaunchKernelGGL(kb_vdot, dim3(kGridVec), dim3(kVB), 0, s, E, i, 0);
+    hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, i, 0);
+    hipLaunchKernelGGL(kb_vaxpy, dim3(kGridVec), dim3(kVB), 0, s, E, i, 1);
+  }
+  hipLaunchKernelGGL(kb_vscale, dim3(kGridVec), dim3(kVB), 0, s, E);
+  for (int i = E.history - 1; i >= 0; --i) {
+    hipLaunchKernelGGL(kb_vdot, dim3(kGridVec), dim3(kVB), 0, s, E, i, 1);
+    hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, i, 1);
+    hipLaunchKernelGGL(kb_vaxpy, dim3(kGridVec), dim3(kVB), 0, s, E, i, 0);
+  }
+  hipLaunchKernelGGL(kb_vneg, dim3(kGridVec), dim3(kVB), 0, s, E);
+  hipLaunchKernelGGL(kb_dirfin, dim3(E.max_slots), dim3(kVB), 0, s, E);
+  hipLaunchKernelGGL(kb_vtrial, dim3(kGridVec), dim3(kVB), 0, s, E);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(P1E_EHIP, std::string("engine step: ") + hipGetErrorString(e));
+  return P1E_OK;
+}
+
+}  // namespace p1e

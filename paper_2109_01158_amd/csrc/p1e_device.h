@@ -18,6 +18,15 @@
 
 #include "p1e_internal.h"
 
+#ifndef P1E_GATHER_LANES_3D
+#define P1E_GATHER_LANES_3D 8
+#endif
+#ifndef P1E_GATHER_LANES_2D
+#define P1E_GATHER_LANES_2D 4
+#endif
+#ifndef P1E_GATHER_UNROLL
+#define P1E_GATHER_UNROLL 3
+#endif
 namespace p1e {
 namespace dev {
 

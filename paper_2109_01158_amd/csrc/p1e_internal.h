@@ -101,3 +101,76 @@ int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, i
 int run_gather(p1e_mesh *m, int prec, const double *scale, double *g, hipStream_t s);
 
 }  // namespace p1e
+
+// ============================================================================ batched engine
+// Many minimizations (requests) share the device: each occupies a slot whose mesh and
+// L-BFGS state live in one sub-allocation of a pool. One engine step advances every active
+// slot by one line-search trial with a fixed sequence of launches that read the set of
+// active slots from device tables, so the sequence can be captured once in a hipGraph.
+namespace p1e {
+
+constexpr int kMaxHistory = 8;     // L-BFGS memory m <= kMaxHistory
+constexpr int kVecTile = 1024;     // DOFs per tile of the vector kernels
+constexpr int kMaxLineTrials = 40; // backtracking halvings per iteration
+
+// per-slot scalars (double) and integers (int32), one row of kNSc / kNSt per slot
+enum SlotScalar {
+  SC_J = 0, SC_JT, SC_ALPHA, SC_GTD, SC_GAMMA, SC_H, SC_BV, SC_JG, SC_COEF, SC_MAXD,
+  SC_A0 = 12, SC_RHO0 = SC_A0 + kMaxHistory, kNSc = SC_RHO0 + kMaxHistory
+};
+enum SlotInt {
+  ST_MODE = 0, ST_ITER, ST_NH, ST_HEAD, ST_NEXT, ST_TRIALS, ST_BAD, ST_ACC, ST_NEEDDIR,
+  ST_MAXIT, ST_STATUS, ST_EVALS, ST_RESET, ST_CLASS, kNSt = 16
+};
+enum SlotMode { MODE_FREE = 0, MODE_INIT = 1, MODE_TRIAL = 2, MODE_DONE = 3 };
+// ST_STATUS on completion
+enum { SLOT_OK = 0, SLOT_STALLED = 1, SLOT_CONVERGED = 2, SLOT_BAD_START = -5 };
+
+// element classes with their own kernel instantiations
+enum ElemClass { CLS_PLAP2 = 0, CLS_PLAP3, CLS_NH2, CLS_NH3, kNumClasses };
+
+// one slot as the batched kernels see it
+struct SlotDev {
+  // mesh (layout of p1e_mesh_bind inside the slot's allocation)
+  const int32_t *node_info, *node_int;
+  const double *xref, *vD, *bhat;
+  const int32_t *conn;
+  const void *geo;  // double or float by engine precision
+  const int32_t *row_ptr;
+  const uint32_t *ent;
+  const int32_t *row_info;
+  void *u, *r;
+  double2 *part;   // [ntile_e] element partials, then [ntile_n] node partials
+  int32_t *badp;   // [ntile_e]
+  double2 *vpart;  // [ntile_v][4] vector-reduction partials
+  int32_t nn, ne, nep, nf, nfd, ntile_e, ntile_n, ntile_v;
+  double C1, D1, p, dirichlet_bv;
+  // L-BFGS vectors, nfd doubles each; S and Y hold kMaxHistory vectors each
+  double *v, *g, *d, *vt, *gt, *S, *Y;
+};
+
+// tile tables: (slot, tile) pairs; element, node and row tiles grouped by class
+enum TileKind { TK_ELEM = 0, TK_NODE = 1, TK_ROW = 2 };
+// counts[] layout: for kind k and class c, offset at 2*(k*kNumClasses + c), count next to it;
+// the number of vector tiles at kCountVec
+constexpr int kCountVec = 2 * 3 * kNumClasses;
+constexpr int kNumCounts = kCountVec + 1;
+
+// device tables of an engine (all in the table area of its workspace)
+struct EngineDev {
+  SlotDev *slots;   // [max_slots]
+  double *sc;       // [max_slots][kNSc]
+  int32_t *st;      // [max_slots][kNSt]
+  int2 *map[3];     // element, node, row tiles
+  int2 *vmap;       // vector tiles over all slots
+  int32_t *counts;  // [kNumCounts]
+  int32_t max_slots, history;
+  int32_t prec;     // P1E_FP64 or P1E_MIXED
+};
+
+// enqueue one engine step on stream s (p1e_batch.hip)
+int batch_step(const EngineDev &E, hipStream_t s);
+// rows per patch-row tile for a class (matches the gather's lanes per row)
+int rows_per_tile(int cls);
+
+}  // namespace p1e

@@ -185,15 +185,6 @@ int launch_element(p1e_mesh *m, const T *geo, double eps, hipStream_t s) {
 
 // Lanes per patch row and entries per lane per round (3D Kuhn patches hold up to 24
 // elements, 2D right-triangle patches 6); both can be set at build time.
-#ifndef P1E_GATHER_LANES_3D
-#define P1E_GATHER_LANES_3D 8
-#endif
-#ifndef P1E_GATHER_LANES_2D
-#define P1E_GATHER_LANES_2D 4
-#endif
-#ifndef P1E_GATHER_UNROLL
-#define P1E_GATHER_UNROLL 3
-#endif
 template <int DIM>
 constexpr int gather_lanes() { return DIM == 3 ? P1E_GATHER_LANES_3D : P1E_GATHER_LANES_2D; }
 

@@ -1,0 +1,144 @@
+"""Minimization (p1e_minimize) and the continuous-batching server (p1e_server_*).
+
+Pins: for p = 2 the minimizer solves K u = b with K the five-point stencil (a direct sparse
+solve, independent of the oracle); for p = 3 the minimum energy agrees with scipy's L-BFGS
+driven by the oracle's energy and gradient. The server: every request's final energy and
+final vhat are bitwise equal to its solo run, with and without hipGraph replay, and under a
+pool too small to hold all requests at once (memory admission).
+"""
+
+import numpy as np
+import pytest
+import scipy.optimize as so
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+import torch
+
+import p1e_synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_01158_amd as P
+    return P
+
+
+def _five_point(n):
+    m = n - 1
+    T = sp.diags([-np.ones(m - 1), 2 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1])
+    I = sp.identity(m)
+    return (sp.kron(I, T) + sp.kron(T, I)).tocsc()
+
+
+def _minimize(P, prob, iters, prec="fp64", history=5):
+    mesh = P.Mesh.from_problem(prob, modes=P.P1E_FP64 | P.P1E_MIXED)
+    v = torch.tensor(prob.vhat(), device="cuda")
+    rep = P.mesh_minimize(mesh, v, history=history, max_iters=iters, prec=prec)
+    return rep, v.cpu().numpy(), mesh
+
+
+def test_p2_minimum_is_the_five_point_solution(P):
+    n = 16
+    prob = S.plaplace_square(n=n, p=2.0, f=-10.0, seed=3)
+    rep, v, _ = _minimize(P, prob, 300)
+    K = _five_point(n)
+    b = np.full(K.shape[0], -10.0 / n**2)
+    u = spl.spsolve(K, b)
+    Jmin = 0.5 * u @ (K @ u) - b @ u
+    assert rep["status"] in (0, 1, 2)
+    assert abs(rep["J"] - Jmin) <= 1e-10 * abs(Jmin)
+    assert np.abs(v - u).max() <= 1e-5 * np.abs(u).max()
+
+
+def test_p3_minimum_matches_scipy_lbfgs_on_the_oracle(P, oracle_mod):
+    prob = S.plaplace_square(n=12, p=3.0, f=-10.0, seed=4)
+    O = oracle_mod.Oracle(prob)
+    fun = lambda x: (O.energy(x)["J"], O.grad_exact(x))
+    res = so.minimize(fun, prob.vhat(), jac=True, method="L-BFGS-B",
+                      options=dict(maxiter=5000, ftol=1e-15, gtol=1e-12, maxcor=10))
+    rep, v, _ = _minimize(P, prob, 400)
+    assert abs(rep["J"] - res.fun) <= 1e-10 * abs(res.fun)
+    assert abs(O.energy(v)["J"] - rep["J"]) <= 1e-12 * abs(rep["J"])
+
+
+def test_neohooke_minimization_decreases_energy(P, oracle_mod):
+    prob = S.neohooke_beam_2d(40, 8, 2.0, 0.4, seed=0, amp=0.0)
+    O = oracle_mod.Oracle(prob)
+    J0 = O.energy(prob.v)["J"]
+    for prec in ("fp64", "mixed"):
+        rep, v, _ = _minimize(P, prob, 60, prec=prec)
+        assert rep["iterations"] >= 1 and rep["J"] < J0
+        ref = O.energy(v)
+        assert ref["nbad"] == 0
+        tol = 1e-12 if prec == "fp64" else 1e-5
+        assert abs(ref["J"] - rep["J"]) <= tol * abs(ref["J"])
+
+
+def _mix():
+    return [
+        S.plaplace_square(n=20, p=1.5, seed=1),
+        S.neohooke_box_3d(8, 3, 3, 1.0, 3 / 8, 3 / 8, seed=2, amp=0.0),
+        S.plaplace_square(n=33, p=3.0, seed=3),
+        S.neohooke_beam_2d(30, 6, 2.0, 0.4, seed=4, amp=0.0),
+        S.plaplace_square(n=17, p=5.0, seed=5),
+        S.neohooke_box_3d(12, 4, 4, 1.0, 1 / 3, 1 / 3, seed=6, amp=0.0),
+        S.plaplace_lshape(8, p=3.0, seed=7),
+        S.neohooke_beam_2d(50, 5, 2.0, 0.2, seed=8, amp=0.0),
+    ]
+
+
+def _serve(P, probs, iters, max_slots, pool_mb=256, use_graph=True):
+    srv = P.Server(pool_mb << 20, max_slots=max_slots, history=5, max_iters=iters, prec="fp64",
+                   use_graph=use_graph, setup_threads=4)
+    ids = [srv.submit(p, vhat0=p.vhat()) for p in probs]
+    out, peak = {}, 0
+    for _ in range(100000):
+        a, w = srv.step()
+        peak = max(peak, a)
+        for r in srv.poll():
+            out[r["id"]] = r
+        if len(out) == len(ids):
+            break
+    res = []
+    for rid, p in zip(ids, probs):
+        r = out[rid]
+        v = srv.result_vhat(rid, r["n_free_dofs"])
+        srv.release(rid)
+        res.append((r, v))
+    srv.close()
+    return res, peak
+
+
+def test_server_mix_equals_solo_bitwise(P):
+    probs = _mix()
+    iters = 25
+    mixed, peak = _serve(P, probs, iters, max_slots=8)
+    assert peak >= 4  # requests really overlapped on the device
+    for (r, v), prob in zip(mixed, probs):
+        assert r["status"] in (0, 1, 2), r
+        solo, _ = _serve(P, [prob], iters, max_slots=1, use_graph=False)
+        (rs, vs), = solo
+        assert rs["J"] == r["J"] and rs["iterations"] == r["iterations"]
+        assert np.array_equal(vs, v)
+        # the single-request minimizer runs the same kernels
+        rep, vm, _ = _minimize(P, prob, iters)
+        assert rep["J"] == r["J"] and np.array_equal(vm, v)
+
+
+def test_server_memory_admission(P):
+    probs = _mix()
+    iters = 10
+    full, _ = _serve(P, probs, iters, max_slots=8)
+    biggest = max(r["device_bytes"] for r, _ in full)
+    total = sum(r["device_bytes"] for r, _ in full)
+    # a pool that holds the largest request but only about half of all of them at once
+    pool_mb = int(max(1.05 * biggest, 0.5 * total) * 1.02) // (1 << 20) + 1
+    tight, peak = _serve(P, probs, iters, max_slots=8, pool_mb=pool_mb)
+    assert peak < len(probs)
+    for (a, va), (b, vb) in zip(full, tight):
+        assert a["J"] == b["J"] and np.array_equal(va, vb)
+        assert b["t_admit"] >= b["t_submit"] and b["t_done"] >= b["t_admit"]
