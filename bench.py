@@ -4,10 +4,11 @@ One step = one energy-and-gradient evaluation through the autograd hook
 (``p1_energy(vhat).backward()``: prepass, element energy + forces, patch gather, compensated
 finalize) on the 460x46x46-cube Kuhn box (5,840,160 tets), mixed precision, inputs resident in
 HBM. Prints ONE JSON line. Extra fields report the FP64 path, the patch central-difference
-gradient on the same mesh, the dominant kernel against the HBM roofline (HIP events around
+gradient on the same mesh, the serving benchmark (256 minimization requests, Poisson arrivals,
+continuous batching vs one-at-a-time FP64 solves: req/s, p50/p99 latency), the dominant kernel against the HBM roofline (HIP events around
 each kernel over a second pass of the same K steps) and the FP64 oracle timed on the host CPU.
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline] [--no-serve]
 """
 
 import argparse
@@ -31,6 +32,9 @@ def _args():
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP64 and FD extra timings")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving benchmark")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-iters", type=int, default=200)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run plain device-to-device copies of this many MiB (a reference "
                          "for hardware byte counters)")
@@ -55,6 +59,28 @@ def algorithmic_bytes(info, prec):
     prepass = nn * (4 + 8 * dim) + 16 * nfd + nn * ns * w
     return {"k_element_force": elem, "k_gather": gather, "k_prepass": prepass}
 
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("p1e_device.h", "p1e_kernels.hip", "p1e_internal.h"):
+        with open(os.path.join(ROOT, "paper_2109_01158_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config, prec, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary of this workload,
+    or None if there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_jgrad_{prec}_{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t["traffic_bytes_per_launch"].get(kernel)
 
 
 def cpu_baseline(prob, target_s=12.0):
@@ -171,7 +197,7 @@ def main():
         torch.cuda.synchronize()
 
     out = {
-        "metric": "elements/s for J+grad J (3D Neo-Hookean, 6M tets)",
+        "metric": "elements/s for J+\u2207J (3D Neo-Hookean, 6M tets); serve req/s + p50/p99",
         "value": value,
         "unit": "elements/s",
         "n_gpus": 1,
@@ -192,7 +218,8 @@ def main():
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": None, "alg_bytes_per_launch": dom_bytes,
+                     "traffic": measured_traffic(a.config, a.prec, dom),
+                     "alg_bytes_per_launch": dom_bytes,
                      "alg_bytes_per_element": dom_bytes / info["ne"] if dom_bytes else None},
         "ms_per_step_with_kernel_events": ms_events,
         "step_alg_bytes_per_element": step_bytes / info["ne"],
@@ -204,6 +231,13 @@ def main():
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
+    if not a.no_serve:
+        from paper_2109_01158_amd import serving
+        del mesh, vhat, vhat0
+        torch.cuda.empty_cache()
+        out["serve"] = serving.benchmark(
+            n_requests=a.serve_requests, iters=a.serve_iters,
+            log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(out), flush=True)
 
 

@@ -235,9 +235,17 @@ double p1e_server_clock(const p1e_server *server);
  * prescribed values, v = x for Neo-Hookean and 0 for the p-Laplacian); returns its id. */
 int p1e_server_submit(p1e_server *server, const p1e_mesh_desc *desc, const double *vhat0,
                       int64_t n0, int64_t *id);
+/* As p1e_server_submit for a request that arrives at t_arrival on the server clock (in the
+ * future or now): it is neither built nor admitted before then. For replaying arrival traces. */
+int p1e_server_submit_at(p1e_server *server, const p1e_mesh_desc *desc, const double *vhat0,
+                         int64_t n0, double t_arrival, int64_t *id);
 /* Retire finished requests, admit waiting ones, enqueue one step; reports the numbers of
  * admitted and of submitted-but-not-admitted requests. */
 int p1e_server_step(p1e_server *server, int32_t *n_active, int32_t *n_waiting);
+/* p1e_server_step in a loop until nothing is active or waiting, or max_steps (<= 0: no limit)
+ * steps or max_seconds (<= 0: no limit) have passed. */
+int p1e_server_run(p1e_server *server, int64_t max_steps, double max_seconds, int32_t *n_active,
+                   int32_t *n_waiting);
 /* Finished requests not reported before (up to cap). */
 int p1e_server_poll(p1e_server *server, p1e_request_info *out, int32_t cap, int32_t *n);
 /* Final vhat of a finished request (host copy of n doubles), until p1e_server_release. */

@@ -130,6 +130,10 @@ def lib():
         "p1e_server_submit": ([vp, ctypes.POINTER(MeshDesc), vp, i64, ctypes.POINTER(i64)],
                               ctypes.c_int),
         "p1e_server_step": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
+        "p1e_server_submit_at": ([vp, ctypes.POINTER(MeshDesc), vp, i64, dbl,
+                                  ctypes.POINTER(i64)], ctypes.c_int),
+        "p1e_server_run": ([vp, i64, dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+                           ctypes.c_int),
         "p1e_server_poll": ([vp, ctypes.POINTER(RequestInfo), i32, ctypes.POINTER(i32)],
                             ctypes.c_int),
         "p1e_server_result_vhat": ([vp, i64, vp, i64], ctypes.c_int),

@@ -342,6 +342,25 @@ class Server:
         del keep
         return rid.value
 
+    def submit_at(self, prob, t_arrival, vhat0=None, flags=0):
+        """Submit a request that arrives at t_arrival (server clock seconds)."""
+        desc, keep = _desc_of(prob, flags)
+        rid = ctypes.c_int64()
+        v0 = None if vhat0 is None else np.ascontiguousarray(vhat0, dtype=np.float64)
+        check(L.lib().p1e_server_submit_at(ctypes.c_void_p(self.handle), ctypes.byref(desc),
+                                           _ptr(v0), 0 if v0 is None else v0.size,
+                                           float(t_arrival), ctypes.byref(rid)))
+        del keep
+        return rid.value
+
+    def run(self, max_steps=0, max_seconds=0.0):
+        """Step until idle (or a limit); returns (active, waiting)."""
+        a, w = ctypes.c_int32(), ctypes.c_int32()
+        with torch.cuda.device(self.device):
+            check(L.lib().p1e_server_run(ctypes.c_void_p(self.handle), int(max_steps),
+                                         float(max_seconds), ctypes.byref(a), ctypes.byref(w)))
+        return a.value, w.value
+
     def step(self):
         a, w = ctypes.c_int32(), ctypes.c_int32()
         with torch.cuda.device(self.device):

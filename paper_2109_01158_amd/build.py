@@ -1,7 +1,7 @@
 """Build libp1e.so (host setup + gfx950 kernels) in-tree with hipcc.
 
-Usage: ``python -m paper_2109_01158_amd.build`` or ``build()`` from Python. Always
-recompiles; the result is written next to this file.
+Usage: ``python paper_2109_01158_amd/build.py`` (by path: importing the package itself
+needs the library). Always recompiles; the result is written next to this file.
 """
 
 import os

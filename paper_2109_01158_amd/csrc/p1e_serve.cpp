@@ -338,6 +338,7 @@ struct p1e_server {
 
   struct Req {
     int64_t id = 0;
+    double t_arrival = 0.0;  // server clock; not built or admitted before
     p1e_mesh_desc desc{};
     std::vector<int32_t> conn;
     std::vector<double> coords, dvals, load, vhat0;
@@ -390,8 +391,16 @@ struct p1e_server {
       Req *r;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv.wait(lk, [&] { return stopping || !to_build.empty(); });
-        if (stopping) return;
+        for (;;) {
+          if (stopping) return;
+          if (!to_build.empty()) {
+            const double wait = to_build.front()->t_arrival - (now_s() - t0);
+            if (wait <= 0.0) break;
+            cv.wait_for(lk, std::chrono::duration<double>(std::min(wait, 0.01)));
+          } else {
+            cv.wait(lk);
+          }
+        }
         r = to_build.front();
         to_build.pop_front();
       }
@@ -491,8 +500,8 @@ void p1e_server_destroy(p1e_server *s) { delete s; }
 
 double p1e_server_clock(const p1e_server *s) { return s ? now_s() - s->t0 : 0.0; }
 
-int p1e_server_submit(p1e_server *s, const p1e_mesh_desc *d, const double *vhat0, int64_t n0,
-                      int64_t *id) {
+int p1e_server_submit_at(p1e_server *s, const p1e_mesh_desc *d, const double *vhat0,
+                         int64_t n0, double t_arrival, int64_t *id) {
   if (!s || !d || !id) return fail(P1E_EINVAL, "null argument");
   if (d->dim != 2 && d->dim != 3) return fail(P1E_EINVAL, "dim must be 2 or 3");
   if (d->nn < 1 || d->ne < 0 || !d->coords || (d->ne > 0 && !d->conn))
@@ -517,13 +526,24 @@ int p1e_server_submit(p1e_server *s, const p1e_mesh_desc *d, const double *vhat0
     std::lock_guard<std::mutex> lk(s->mu);
     r->id = s->next_id++;
     r->info.id = r->id;
-    r->info.t_submit = now_s() - s->t0;
-    s->to_build.push_back(r);
-    ++s->building;
+    r->t_arrival = std::max(t_arrival, now_s() - s->t0);
+    r->info.t_submit = r->t_arrival;
+    // building order = arrival order
+    auto pos = std::upper_bound(s->to_build.begin(), s->to_build.end(), r,
+                                [](const p1e_server::Req *a, const p1e_server::Req *b) {
+                                  return a->t_arrival < b->t_arrival;
+                                });
+    s->to_build.insert(pos, r);
+    ++s->building;  // submitted and not yet built (includes requests still to arrive)
     *id = r->id;
   }
   s->cv.notify_one();
   return P1E_OK;
+}
+
+int p1e_server_submit(p1e_server *s, const p1e_mesh_desc *d, const double *vhat0, int64_t n0,
+                      int64_t *id) {
+  return p1e_server_submit_at(s, d, vhat0, n0, 0.0, id);
 }
 
 int p1e_server_step(p1e_server *s, int32_t *n_active, int32_t *n_waiting) {
@@ -632,6 +652,23 @@ int p1e_server_step(p1e_server *s, int32_t *n_active, int32_t *n_waiting) {
     std::lock_guard<std::mutex> lk(s->mu);
     *n_waiting = (int32_t)(s->ready.size() + s->building);
   }
+  return P1E_OK;
+}
+
+int p1e_server_run(p1e_server *s, int64_t max_steps, double max_seconds, int32_t *n_active,
+                   int32_t *n_waiting) {
+  if (!s) return fail(P1E_EINVAL, "null server");
+  const double t_end = now_s() + (max_seconds > 0.0 ? max_seconds : 1e300);
+  int32_t a = 0, w = 0;
+  for (int64_t k = 0; max_steps <= 0 || k < max_steps; ++k) {
+    int rc = p1e_server_step(s, &a, &w);
+    if (rc) return rc;
+    if (a == 0 && w == 0 && !s->inflight) break;
+    if (now_s() > t_end) break;
+    if (a == 0) std::this_thread::sleep_for(std::chrono::microseconds(100));
+  }
+  if (n_active) *n_active = a;
+  if (n_waiting) *n_waiting = w;
   return P1E_OK;
 }
 
