@@ -73,6 +73,15 @@ extern "C" {
  * numbering. Without it the input order is kept (best for lexicographically numbered
  * structured meshes). */
 #define P1E_LOCALITY_ORDER 1
+/* P1E_LOCALITY_ROWS: renumber only the nodes (and so the patch rows) along the Morton curve,
+ * keeping the element order. */
+#define P1E_LOCALITY_ROWS 2
+/* P1E_FULL_GEOMETRY: always store B^-1 and |T| per element. By default, element records
+ * (B^-1, |T|) that agree to 2^-40 of each component's largest magnitude share one class, and
+ * a mesh with at most 256 classes (uniformly refined structured meshes have a few) stores one
+ * record per class and a one-byte class per element; the elements of a class then use its
+ * first record, which differs from their own only by the rounding of node coordinates. */
+#define P1E_FULL_GEOMETRY 4
 
 typedef struct p1e_mesh p1e_mesh;
 
@@ -81,7 +90,7 @@ typedef struct p1e_mesh_desc {
   int32_t dim;   /* 2 (triangles) or 3 (tetrahedra) */
   int32_t ncomp; /* d: 1 for P1E_PLAPLACE, dim for P1E_NEOHOOKE */
   int32_t kind;  /* P1E_PLAPLACE or P1E_NEOHOOKE */
-  int32_t flags; /* 0 or P1E_LOCALITY_ORDER */
+  int32_t flags; /* 0 or P1E_LOCALITY_ORDER | P1E_LOCALITY_ROWS | P1E_FULL_GEOMETRY */
   int64_t nn; /* number of nodes, 1 <= nn < 2^28 */
   int64_t ne; /* number of elements, 0 <= ne < 2^29 */
   const int32_t *conn;       /* [ne][dim+1] vertex indices, distinct, in [0, nn) */
@@ -102,6 +111,8 @@ typedef struct p1e_mesh_info {
   double total_volume, min_volume, max_volume;
   double dirichlet_bv; /* sum over prescribed DOFs of b_n v_n (constant part of b.v) */
   uint64_t alignment;  /* required alignment of the bound device buffer (bytes) */
+  int32_t geometry_classes; /* distinct element records kept as a table (0: per element) */
+  int32_t reserved;
 } p1e_mesh_info;
 
 /* Build a mesh handle: validates the description, computes element geometry (|T| and basis

@@ -30,6 +30,8 @@ P1E_MIXED = 2
 P1E_FD = 4
 
 P1E_LOCALITY_ORDER = 1
+P1E_LOCALITY_ROWS = 2
+P1E_FULL_GEOMETRY = 4
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EDEGEN", -3: "ENOMEM", -4: "EHIP", -5: "EDOMAIN",
                 -6: "EBUSY", -7: "ESTATE"}
@@ -53,7 +55,8 @@ class MeshInfo(ctypes.Structure):
         ("max_valence", ctypes.c_int32),
         ("total_volume", ctypes.c_double), ("min_volume", ctypes.c_double),
         ("max_volume", ctypes.c_double), ("dirichlet_bv", ctypes.c_double),
-        ("alignment", ctypes.c_uint64),
+        ("alignment", ctypes.c_uint64), ("geometry_classes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

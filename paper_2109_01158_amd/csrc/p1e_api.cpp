@@ -15,6 +15,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "p1e_internal.h"
@@ -89,7 +90,7 @@ int64_t part_slots(const p1e_mesh *m) {
 }
 
 struct Layout {
-  uint64_t node_info, node_int, xref, vD, bhat, conn, geo64, geo32, row_ptr, ent, row_info, u,
+  uint64_t node_info, node_int, xref, vD, bhat, conn, geo64, geo32, geo_cls, row_ptr, ent, row_info, u,
       r, part, badp, total;
 };
 
@@ -108,8 +109,10 @@ static Layout make_layout(const p1e_mesh *m, int modes) {
   L.vD = take(8ull * m->nn * m->d);
   L.bhat = take(8ull * m->nfd);
   L.conn = take(4ull * m->ne * m->k);
-  L.geo64 = take((modes & (P1E_FP64 | P1E_FD)) ? 8ull * dd * m->ne : 0);
-  L.geo32 = take((modes & P1E_MIXED) ? 4ull * dd * m->ne : 0);
+  const uint64_t grec = m->nclass ? (uint64_t)m->nclass : (uint64_t)m->ne;  // geometry records
+  L.geo64 = take((modes & (P1E_FP64 | P1E_FD)) ? 8ull * dd * grec : 0);
+  L.geo32 = take((modes & P1E_MIXED) ? 4ull * dd * grec : 0);
+  L.geo_cls = take(m->nclass ? (uint64_t)m->ne : 0);
   L.row_ptr = take(4ull * (m->nf + 1));
   L.ent = take(4ull * m->nnz);
   L.row_info = take(4ull * m->nf);
@@ -227,7 +230,7 @@ void locality_order(const p1e_mesh_desc *D, std::vector<int32_t> &nperm,
   eperm.resize(ne);
   for (int64_t i = 0; i < nn; ++i) nperm[i] = (int32_t)i;
   for (int64_t e = 0; e < ne; ++e) eperm[e] = (int32_t)e;
-  if (!(D->flags & P1E_LOCALITY_ORDER)) return;
+  if (!(D->flags & (P1E_LOCALITY_ORDER | P1E_LOCALITY_ROWS))) return;
   MortonKey key{dim, {0, 0, 0}, 0.0};
   double hi[3] = {0, 0, 0}, ext = 0.0;
   for (int a = 0; a < dim; ++a) {
@@ -252,7 +255,51 @@ void locality_order(const p1e_mesh_desc *D, std::vector<int32_t> &nperm,
     ek[e] = key(c);
   }
   std::stable_sort(nperm.begin(), nperm.end(), [&](int32_t a, int32_t b) { return nk[a] < nk[b]; });
-  std::stable_sort(eperm.begin(), eperm.end(), [&](int32_t a, int32_t b) { return ek[a] < ek[b]; });
+  if (D->flags & P1E_LOCALITY_ORDER)
+    std::stable_sort(eperm.begin(), eperm.end(), [&](int32_t a, int32_t b) { return ek[a] < ek[b]; });
+}
+
+// Geometry classes: meshes made by uniform refinement of structured grids have only a few
+// distinct element shapes (6 for a Kuhn box, 2 for a right-triangle grid); their records
+// [B^-1, |T|] differ only by the rounding of the node coordinates. Each record component is
+// quantized to 2^-40 of that component's largest magnitude over the mesh; records with equal
+// quantized keys share one class, represented by the first such record (element order).
+// When there are at most kMaxGeoClasses classes, the mesh keeps one table entry per class
+// and a one-byte class per element instead of the per-element arrays.
+void classify_geometry(p1e_mesh *m) {
+  const int dd = m->dim * m->dim + 1;
+  const int64_t ne = m->ne;
+  if (ne == 0) return;
+  std::vector<double> scale(dd, 0.0);
+  for (int q = 0; q < dd; ++q)
+    for (int64_t e = 0; e < ne; ++e)
+      scale[q] = std::max(scale[q], std::fabs(m->geo64[(size_t)q * ne + e]));
+  std::unordered_map<std::string, int> ids;
+  std::vector<double> tab;
+  std::vector<uint8_t> cls((size_t)ne);
+  std::string key(sizeof(int64_t) * dd, '\0');
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int q = 0; q < dd; ++q) {
+      const double v = m->geo64[(size_t)q * ne + e];
+      const int64_t k = scale[q] > 0.0 ? (int64_t)std::llround(std::ldexp(v / scale[q], 40)) : 0;
+      std::memcpy(&key[sizeof(int64_t) * q], &k, sizeof(int64_t));
+    }
+    auto it = ids.find(key);
+    int id;
+    if (it == ids.end()) {
+      id = (int)ids.size();
+      if (id >= kMaxGeoClasses) return;  // not a few-shape mesh: keep per-element arrays
+      ids.emplace(key, id);
+      for (int q = 0; q < dd; ++q) tab.push_back(m->geo64[(size_t)q * ne + e]);
+    } else {
+      id = it->second;
+    }
+    cls[e] = (uint8_t)id;
+  }
+  m->nclass = (int)ids.size();
+  m->geo_tab = std::move(tab);
+  m->geo_cls = std::move(cls);
+  std::vector<double>().swap(m->geo64);
 }
 
 int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
@@ -397,6 +444,7 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
     }
   }
   m->dirichlet_bv = dbv.value();
+  if (!(D->flags & P1E_FULL_GEOMETRY)) classify_geometry(m);
   return P1E_OK;
 }
 
@@ -461,6 +509,7 @@ int p1e_mesh_get_info(const p1e_mesh *m, p1e_mesh_info *o) {
   o->max_volume = m->max_vol;
   o->dirichlet_bv = m->dirichlet_bv;
   o->alignment = kAlign;
+  o->geometry_classes = m->nclass;
   return P1E_OK;
 }
 
@@ -485,10 +534,12 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
     return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s) == hipSuccess;
   };
   const int dd = m->dim * m->dim + 1;
+  const std::vector<double> &g64 = m->nclass ? m->geo_tab : m->geo64;
+  const uint64_t grec = m->nclass ? (uint64_t)m->nclass : (uint64_t)m->ne;
   std::vector<float> g32;
   if (mask & P1E_MIXED) {
-    g32.resize(m->geo64.size());
-    for (size_t i = 0; i < g32.size(); ++i) g32[i] = (float)m->geo64[i];
+    g32.resize(g64.size());
+    for (size_t i = 0; i < g32.size(); ++i) g32[i] = (float)g64[i];
   }
   bool ok = up(L.node_info, m->node_info.data(), 4 * m->node_info.size()) &&
             up(L.node_int, m->node_int.data(), 4 * m->node_int.size()) &&
@@ -496,9 +547,9 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
             up(L.vD, m->vD.data(), 8 * m->vD.size()) &&
             up(L.bhat, m->bhat.data(), 8 * m->bhat.size()) &&
             up(L.conn, m->conn.data(), 4 * m->conn.size()) &&
-            ((mask & (P1E_FP64 | P1E_FD)) ? up(L.geo64, m->geo64.data(), 8ull * dd * m->ne)
-                                          : true) &&
-            ((mask & P1E_MIXED) ? up(L.geo32, g32.data(), 4ull * dd * m->ne) : true) &&
+            ((mask & (P1E_FP64 | P1E_FD)) ? up(L.geo64, g64.data(), 8ull * dd * grec) : true) &&
+            ((mask & P1E_MIXED) ? up(L.geo32, g32.data(), 4ull * dd * grec) : true) &&
+            up(L.geo_cls, m->geo_cls.data(), m->geo_cls.size()) &&
             up(L.row_ptr, m->row_ptr.data(), 4 * m->row_ptr.size()) &&
             up(L.ent, m->ent.data(), 4 * m->ent.size()) &&
             up(L.row_info, m->row_info.data(), 4 * m->row_info.size());
@@ -514,6 +565,8 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
   D.conn = (const int32_t *)(base + L.conn);
   D.geo64 = (mask & (P1E_FP64 | P1E_FD)) ? (const double *)(base + L.geo64) : nullptr;
   D.geo32 = (mask & P1E_MIXED) ? (const float *)(base + L.geo32) : nullptr;
+  D.geo_cls = m->nclass ? (const uint8_t *)(base + L.geo_cls) : nullptr;
+  D.nclass = m->nclass;
   D.row_ptr = (const int32_t *)(base + L.row_ptr);
   D.ent = (const uint32_t *)(base + L.ent);
   D.row_info = (const int32_t *)(base + L.row_info);

@@ -74,14 +74,17 @@ __global__ __launch_bounds__(kBlockElem) void kb_element(EngineDev E) {
     const int2 st = tl[t];
     if (!evaluating(E, st.x)) continue;
     const SlotDev &S = E.slots[st.x];
-    const int e = st.y * kBlockElem + threadIdx.x;
     double s = 0.0, c = 0.0;
     int cnt = 0;
-    if (e < S.ne) {
-      const Params prm{S.C1, S.D1, S.p, 0.0};
-      element_pass<DIM, D, KIND, T, MODE_FORCE>(e, S.ne, S.nep, S.conn, (const T *)S.geo,
-                                                (const T *)S.u, (T *)S.r, prm, s, c, cnt);
-    }
+    const Params prm{S.C1, S.D1, S.p, 0.0};
+    if (S.gcls != nullptr)  // class table read through the caches (it differs per slot)
+      element_tile<DIM, D, KIND, T, MODE_FORCE, true>(st.y, S.ne, S.nep, S.conn,
+                                                      (const T *)S.geo, S.gcls, (const T *)S.u,
+                                                      (T *)S.r, prm, s, c, cnt);
+    else
+      element_tile<DIM, D, KIND, T, MODE_FORCE, false>(st.y, S.ne, S.nep, S.conn,
+                                                       (const T *)S.geo, nullptr,
+                                                       (const T *)S.u, (T *)S.r, prm, s, c, cnt);
     block_reduce<kBlockElem>(s, c, cnt);
     if (threadIdx.x == 0) {
       S.part[st.y] = make_double2(s, c);

@@ -6,7 +6,7 @@
 // Precision. P1E_FP64 runs everything in double. P1E_MIXED evaluates the element algebra in
 // float on the displacement gradient G = F - I, with the cancellation-free forms
 //   |F|^2 - dim = 2 tr G + |G|^2,  det F - 1 = tr G + s2(G) + det G  (s2: sum of principal
-//   2x2 minors, absent in 2D),  log det F = log1p(det F - 1)  (double),
+//   2x2 minors, absent in 2D),  (det F - 1) - log det F  by log_excess (double),
 //   F - F^-T = [(s2 + det G) I + (det F) G + G^T - cof G] / det F  (2D: cof terms reduce),
 // and accumulates energies and forces in double.
 #pragma once
@@ -18,6 +18,9 @@
 
 #include "p1e_internal.h"
 
+#ifndef P1E_STREAM_NT
+#define P1E_STREAM_NT 0
+#endif
 #ifndef P1E_GATHER_LANES_3D
 #define P1E_GATHER_LANES_3D 8
 #endif
@@ -29,6 +32,18 @@
 #endif
 namespace p1e {
 namespace dev {
+
+// Loads of arrays that one pass reads exactly once (connectivity, geometry, patch entries).
+// With P1E_STREAM_NT they are marked non-temporal, leaving cache capacity to the data that
+// is re-read (nodal fields, element force records).
+template <typename T>
+__device__ __forceinline__ T stream_load(const T *p) {
+#if P1E_STREAM_NT
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
 
 struct Params {
   double C1, D1, p, eps;
@@ -58,10 +73,10 @@ __device__ __forceinline__ void block_reduce(double &s, double &c, int &cnt) {
   for (int off = 32; off > 0; off >>= 1) {
     double s2 = __shfl_down(s, off, 64);
     double c2 = __shfl_down(c, off, 64);
-    int n2 = __shfl_down(cnt, off, 64);
     pair_add(s, c, s2, c2);
-    cnt += n2;
   }
+  if (__any(cnt != 0))  // counts are rare (bad elements): wave-uniform test
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     sh_s[wave] = s;
@@ -160,6 +175,47 @@ __device__ __forceinline__ float fpow<float>(float x, float y) { return powf(x, 
 template <>
 __device__ __forceinline__ double fpow<double>(double x, double y) { return pow(x, y); }
 
+// q(d) = d - log(1 + d) >= 0 for d > -1, in double, without the cancellation of the plain
+// difference near d = 0 (where q ~ d^2 / 2). Binary exponent reduction 1 + d = 2^k m with
+// m in [1/sqrt 2, sqrt 2), then log m = 2 atanh s = 2 s + 2 s^3 S(s^2), s = (m - 1)/(m + 1),
+// |s| <= 0.1716, S(w) = sum_{i>=0} w^i / (2i + 3); ten terms leave a truncation error below
+// 1e-16 of S.
+//  k = 0: s = d / (2 + d) from d itself (1 + d is never rounded), and d - 2 s = s d exactly
+//         in real arithmetic, so q = s d - 2 s^3 S: both terms positive for d < 0, the second
+//         at most a twentieth of the first for d > 0.
+//  k != 0: q = d - k log 2 - 2 s - 2 s^3 S - (1 + d - t)/t with t = fl(1 + d); the last term
+//         undoes the rounding of t (d - (t - 1) is exact here), q >= 0.06 so no cancellation.
+// About 40 double instructions, against over 100 for a general-purpose log1p.
+__device__ __forceinline__ double log_excess(double d) {
+  const double t = 1.0 + d;
+  int k;
+  double m = frexp(t, &k);  // t = m 2^k, m in [1/2, 1)
+  const bool lo = m < 0.70710678118654752440;
+  m = lo ? 2.0 * m : m;
+  k = lo ? k - 1 : k;
+  const bool k0 = k == 0;
+  const double s = (k0 ? d : m - 1.0) / (k0 ? 2.0 + d : m + 1.0);
+  const double w = s * s;
+  double S = 1.0 / 21.0;
+  S = fma(S, w, 1.0 / 19.0);
+  S = fma(S, w, 1.0 / 17.0);
+  S = fma(S, w, 1.0 / 15.0);
+  S = fma(S, w, 1.0 / 13.0);
+  S = fma(S, w, 1.0 / 11.0);
+  S = fma(S, w, 1.0 / 9.0);
+  S = fma(S, w, 1.0 / 7.0);
+  S = fma(S, w, 1.0 / 5.0);
+  S = fma(S, w, 1.0 / 3.0);
+  const double tail = 2.0 * (s * w) * S;
+  const double q0 = fma(s, d, -tail);
+  constexpr double kLn2Hi = 6.93147180369123816490e-01;  // high 32 bits of log 2
+  constexpr double kLn2Lo = 1.90821492927058770002e-10;  // log 2 - kLn2Hi
+  const double kd = (double)k;
+  const double corr = (d - (t - 1.0)) * __builtin_amdgcn_rcp(t);
+  const double qk = ((((d - kd * kLn2Hi) - kd * kLn2Lo) - 2.0 * s) - tail) - corr;
+  return k0 ? q0 : qk;
+}
+
 // Neo-Hookean density at F = I + G (eq. neoHook), returned in double.
 template <int DIM, typename T>
 __device__ __forceinline__ double nh_energy(const T G[DIM][DIM], double C1, double D1,
@@ -186,7 +242,7 @@ __device__ __forceinline__ double nh_energy(const T G[DIM][DIM], double C1, doub
     bad = true;
     return 0.0;
   }
-  const double q = delta - log1p(delta);  // (det F - 1) - log det F >= 0
+  const double q = log_excess(delta);  // (det F - 1) - log det F >= 0
   // |F|^2 - dim - 2 log det F = |G|^2 - 2 (s2 + det G) + 2 q
   const double W = C1 * ((double)n2 - 2.0 * ((double)s2 + (double)dG) + 2.0 * q) +
                    D1 * delta * delta;
@@ -295,32 +351,35 @@ __device__ __forceinline__ void store_entries(T *__restrict__ r, int nep, int e,
   }
 }
 
-// The element pass for element e < ne: gather u at the vertices, G = grad u (eq. Dv), the
-// density (energy of the element added to (s, c), bad elements counted in cnt) and, by
+// The element pass for element e < ne, given u at its vertices (uu): G = grad u (eq. Dv),
+// the density (energy of the element added to (s, c), bad elements counted in cnt) and, by
 // MODE, the element forces |T| dW/dF grad phi_l (Section 6.2) or the per-element central
 // differences of |T| W under a perturbation of one row of F (Section 6.1), written as
 // vertex-major entries r[l][e] (nep = padded element count).
-// geo: [DIM*DIM][ne] entries of B^-1 followed by [ne] sizes |T|.
-template <int DIM, int D, int KIND, typename T, int MODE>
-__device__ __forceinline__ void element_pass(int e, int ne, int nep,
-                                             const int32_t *__restrict__ conn,
-                                             const T *__restrict__ geo,
-                                             const T *__restrict__ u, T *__restrict__ r,
-                                             const Params &prm, double &s, double &c,
-                                             int &cnt) {
+// geo: [DIM*DIM][ne] entries of B^-1 followed by [ne] sizes |T|; or, with CLS, a table of
+// records [DIM*DIM entries of B^-1, |T|] and cls = the element's class.
+template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
+__device__ __forceinline__ void element_pass(int e, int ne, int nep, const T (&uu)[DIM + 1][D],
+                                             const T *__restrict__ geo, int cls,
+                                             T *__restrict__ r, const Params &prm, double &s,
+                                             double &c, int &cnt) {
   constexpr int K = DIM + 1;
-  int nd[K];
-#pragma unroll
-  for (int l = 0; l < K; ++l) nd[l] = conn[(int64_t)l * ne + e];
-  T uu[K][D];
-#pragma unroll
-  for (int l = 0; l < K; ++l) NodeVec<T, D>::load(u, nd[l], uu[l]);
   T Bi[DIM][DIM];
+  T vol;
+  if constexpr (CLS) {
+    const T *rec = geo + cls * (DIM * DIM + 1);
 #pragma unroll
-  for (int l = 0; l < DIM; ++l)
+    for (int l = 0; l < DIM; ++l)
 #pragma unroll
-    for (int m = 0; m < DIM; ++m) Bi[l][m] = geo[(int64_t)(l * DIM + m) * ne + e];
-  const T vol = geo[(int64_t)(DIM * DIM) * ne + e];
+      for (int m = 0; m < DIM; ++m) Bi[l][m] = rec[l * DIM + m];
+    vol = rec[DIM * DIM];
+  } else {
+#pragma unroll
+    for (int l = 0; l < DIM; ++l)
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) Bi[l][m] = stream_load(geo + (int64_t)(l * DIM + m) * ne + e);
+    vol = stream_load(geo + (int64_t)(DIM * DIM) * ne + e);
+  }
   // G = D Binv with D[j][l] = u_{l+1}[j] - u_0[j]   (eq. Dv, grad phi_0 = -sum of others)
   T G[D][DIM];
 #pragma unroll
@@ -409,6 +468,50 @@ __device__ __forceinline__ void element_pass(int e, int ne, int nep,
   }
 }
 
+// One tile of the element pass: elements tile * kElemTile + k * kBlockElem + threadIdx.x,
+// k < kElemPerThread (each k a coalesced sweep of the block), summed into (s, c, cnt).
+// Latency hiding: the connectivity (and classes) of all of the thread's elements are loaded
+// up front, and the vertex values of element k + 1 are gathered while element k is
+// computed. Lanes past ne load the last element's indices and compute nothing.
+template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
+__device__ __forceinline__ void element_tile(int tile, int ne, int nep,
+                                             const int32_t *__restrict__ conn,
+                                             const T *__restrict__ geo,
+                                             const uint8_t *__restrict__ gcls,
+                                             const T *__restrict__ u, T *__restrict__ r,
+                                             const Params &prm, double &s, double &c,
+                                             int &cnt) {
+  constexpr int K = DIM + 1, E = kElemPerThread;
+  const int e0 = tile * kElemTile + threadIdx.x;
+  int nd[E][K], cl[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = min(e0 + k * kBlockElem, ne - 1);
+#pragma unroll
+    for (int l = 0; l < K; ++l) nd[k][l] = stream_load(conn + (int64_t)l * ne + e);
+    cl[k] = CLS ? (int)stream_load(gcls + e) : 0;
+  }
+  T ua[K][D], ub[K][D];
+#pragma unroll
+  for (int l = 0; l < K; ++l) NodeVec<T, D>::load(u, nd[0][l], ua[l]);
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    if (k + 1 < E) {
+#pragma unroll
+      for (int l = 0; l < K; ++l) NodeVec<T, D>::load(u, nd[k + 1][l], ub[l]);
+    }
+    const int e = e0 + k * kBlockElem;
+    if (e < ne)
+      element_pass<DIM, D, KIND, T, MODE, CLS>(e, ne, nep, ua, geo, cl[k], r, prm, s, c, cnt);
+    if (k + 1 < E) {
+#pragma unroll
+      for (int l = 0; l < K; ++l)
+#pragma unroll
+        for (int j = 0; j < D; ++j) ua[l][j] = ub[l][j];
+    }
+  }
+}
+
 // The node prepass for node i (caller's order): the nodal field of v (u = v - x when
 // SUB_X) stored at the node's internal position, and b.v of its free DOFs added to (s, c).
 template <typename T, int D, bool SUB_X>
@@ -484,7 +587,7 @@ __device__ __forceinline__ void gather_row(int row, int sub, int nf, int nep,
       for (int u = 0; u < U; ++u) {
         const int t = base + u * GL;
         ok[u] = t < t1;
-        x[u] = ent[ok[u] ? t : t1 - 1];
+        x[u] = stream_load(ent + (ok[u] ? t : t1 - 1));
       }
       Entry<T, D> q[U];
 #pragma unroll

@@ -13,9 +13,15 @@
 namespace p1e {
 
 constexpr int kBlock = 256;        // threads per block of the patch gather
-constexpr int kBlockElem = 512;    // threads (= elements) per block of the element kernel
+constexpr int kBlockElem = 512;    // threads per block of the element kernel
+#ifndef P1E_ELEM_PER_THREAD
+#define P1E_ELEM_PER_THREAD 4
+#endif
+constexpr int kElemPerThread = P1E_ELEM_PER_THREAD;    // elements per thread (one tile)
+constexpr int kElemTile = kBlockElem * kElemPerThread;  // elements per element-kernel tile
 constexpr int kBlockNode = 1024;   // threads (= nodes) per block of the node prepass
 constexpr uint64_t kAlign = 256;   // alignment of every sub-array in the bound buffer
+constexpr int kMaxGeoClasses = 256; // geometry classes kept as one-byte indices
 
 // Device view of a bound mesh. All arrays live in the caller's buffer.
 struct DevMesh {
@@ -27,8 +33,12 @@ struct DevMesh {
   // element and patch arrays in internal (locality) order
   const double *bhat = nullptr;        // [n_free_dofs] b = M f on the free DOFs
   const int32_t *conn = nullptr;       // [dim+1][ne] structure of arrays
-  const double *geo64 = nullptr;       // [dim*dim+1][ne]: B^-1 entries (row l-1 = grad phi_l), |T|
-  const float *geo32 = nullptr;        // same in FP32 (mixed mode)
+  // element geometry: B^-1 entries (row l-1 = grad phi_l) and |T|, either per element as
+  // [dim*dim+1][ne], or (geometry classes) as a table [nclass][dim*dim+1] indexed by geo_cls
+  const double *geo64 = nullptr;       // FP64
+  const float *geo32 = nullptr;        // FP32 (mixed mode)
+  const uint8_t *geo_cls = nullptr;    // [ne] class of each element, or nullptr
+  int nclass = 0;
   const int32_t *row_ptr = nullptr;    // [nf+1] patch rows of free nodes
   const uint32_t *ent = nullptr;       // [nnz] (element << 2) | local vertex, ascending element
   const int32_t *row_info = nullptr;   // [nf] node_info of each free node
@@ -50,7 +60,10 @@ struct p1e_mesh {
 
   // host copies (kept so the mesh can be bound again)
   std::vector<int32_t> conn;       // [k][ne]
-  std::vector<double> geo64;       // [dim*dim+1][ne]
+  std::vector<double> geo64;       // [dim*dim+1][ne] (empty when classed)
+  int nclass = 0;                  // distinct element geometries when <= kMaxGeoClasses, else 0
+  std::vector<uint8_t> geo_cls;    // [ne] class of each element
+  std::vector<double> geo_tab;     // [nclass][dim*dim+1]
   std::vector<int32_t> node_info;  // [nn] external order
   std::vector<int32_t> node_int;   // [nn] external -> internal node number
   std::vector<double> xref;        // [nn][dim] (Neo-Hookean only)
@@ -79,10 +92,10 @@ void prof_end(hipStream_t s);
 
 // number of blocks of the streaming kernels over n items
 inline int64_t nblocks(int64_t n, int per = kBlock) { return (n + per - 1) / per; }
-inline int64_t element_blocks(int64_t ne) { return nblocks(ne, kBlockElem); }
+inline int64_t element_blocks(int64_t ne) { return nblocks(ne, kElemTile); }
 inline int64_t node_blocks(int64_t nn) { return nblocks(nn, kBlockNode); }
 // per-element scratch is padded to whole element blocks
-inline int64_t padded_elements(int64_t ne) { return element_blocks(ne) * kBlockElem; }
+inline int64_t padded_elements(int64_t ne) { return element_blocks(ne) * kElemTile; }
 
 // device bytes of each scratch array for the given mode mask
 uint64_t u_bytes(const p1e_mesh *m, int modes);
@@ -135,7 +148,8 @@ struct SlotDev {
   const int32_t *node_info, *node_int;
   const double *xref, *vD, *bhat;
   const int32_t *conn;
-  const void *geo;  // double or float by engine precision
+  const void *geo;  // double or float by engine precision (class table when gcls is set)
+  const uint8_t *gcls;
   const int32_t *row_ptr;
   const uint32_t *ent;
   const int32_t *row_info;

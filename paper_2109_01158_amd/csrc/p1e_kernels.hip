@@ -49,20 +49,32 @@ __global__ __launch_bounds__(kBlockNode) void k_prepass(int nn, const int32_t *_
   if (threadIdx.x == 0) part[tile] = make_double2(s, c);
 }
 
-// One element per thread.
-template <int DIM, int D, int KIND, typename T, int MODE>
+// One tile of kElemTile elements per block. With CLS the (small) table of element records
+// is staged in LDS first.
+template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
 __global__ __launch_bounds__(kBlockElem) void k_element(int ne, int nep,
                                                         const int32_t *__restrict__ conn,
                                                         const T *__restrict__ geo,
+                                                        const uint8_t *__restrict__ gcls,
+                                                        int nclass,
                                                         const T *__restrict__ u,
                                                         T *__restrict__ r,
                                                         double2 *__restrict__ part,
                                                         int32_t *__restrict__ badp, Params prm) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int e = tile * kBlockElem + threadIdx.x;
   double s = 0.0, c = 0.0;
   int cnt = 0;
-  if (e < ne) element_pass<DIM, D, KIND, T, MODE>(e, ne, nep, conn, geo, u, r, prm, s, c, cnt);
+  if constexpr (CLS) {
+    constexpr int REC = DIM * DIM + 1;
+    __shared__ T tab[kMaxGeoClasses * REC];
+    for (int q = threadIdx.x; q < nclass * REC; q += kBlockElem) tab[q] = geo[q];
+    __syncthreads();
+    element_tile<DIM, D, KIND, T, MODE, true>(tile, ne, nep, conn, tab, gcls, u, r, prm, s, c,
+                                              cnt);
+  } else {
+    element_tile<DIM, D, KIND, T, MODE, false>(tile, ne, nep, conn, geo, nullptr, u, r, prm, s,
+                                               c, cnt);
+  }
   block_reduce<kBlockElem>(s, c, cnt);
   if (threadIdx.x == 0) {
     part[tile] = make_double2(s, c);
@@ -93,26 +105,23 @@ constexpr int kFin = 1024;
 __device__ __forceinline__ void strided_pairs(int n, const double2 *__restrict__ p,
                                               const int32_t *__restrict__ cntp, double &s,
                                               double &c, int &cnt) {
+  // rounds of B predicated loads, all in flight together; absent slots add (0, 0), which
+  // leaves the compensated pair unchanged
   constexpr int B = 16;
-  int i = threadIdx.x;
-  for (; i + (B - 1) * kFin < n; i += B * kFin) {
+  for (int i = threadIdx.x; i < n; i += B * kFin) {
     double2 q[B];
     int k[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      q[b] = p[i + b * kFin];
-      k[b] = cntp ? cntp[i + b * kFin] : 0;
+      const int j = i + b * kFin;
+      q[b] = j < n ? p[j] : make_double2(0.0, 0.0);
+      k[b] = (cntp && j < n) ? cntp[j] : 0;
     }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       pair_add(s, c, q[b].x, q[b].y);
       cnt += k[b];
     }
-  }
-  for (; i < n; i += kFin) {
-    double2 q = p[i];
-    pair_add(s, c, q.x, q.y);
-    cnt += cntp ? cntp[i] : 0;
   }
 }
 
@@ -176,9 +185,16 @@ int launch_element(p1e_mesh *m, const T *geo, double eps, hipStream_t s) {
                      : MODE == MODE_FORCE ? "k_element_force"
                                           : "k_element_fd";
   prof_begin(name, s);
-  hipLaunchKernelGGL((k_element<DIM, D, KIND, T, MODE>), dim3(nb), dim3(kBlockElem), 0, s,
-                     (int)m->ne, (int)padded_elements(m->ne), m->dev.conn, geo, (const T *)m->dev.u, (T *)m->dev.r,
-                     m->dev.part, m->dev.badp, params_of(m, eps));
+  if (m->dev.geo_cls != nullptr)
+    hipLaunchKernelGGL((k_element<DIM, D, KIND, T, MODE, true>), dim3(nb), dim3(kBlockElem), 0,
+                       s, (int)m->ne, (int)padded_elements(m->ne), m->dev.conn, geo,
+                       m->dev.geo_cls, m->dev.nclass, (const T *)m->dev.u, (T *)m->dev.r,
+                       m->dev.part, m->dev.badp, params_of(m, eps));
+  else
+    hipLaunchKernelGGL((k_element<DIM, D, KIND, T, MODE, false>), dim3(nb), dim3(kBlockElem), 0,
+                       s, (int)m->ne, (int)padded_elements(m->ne), m->dev.conn, geo, nullptr, 0,
+                       (const T *)m->dev.u, (T *)m->dev.r, m->dev.part, m->dev.badp,
+                       params_of(m, eps));
   prof_end(s);
   return check_launch(name);
 }

@@ -64,7 +64,7 @@ struct TableCaps {
 TableCaps table_caps(int max_slots, uint64_t pool_bytes) {
   TableCaps c;
   c.slots = max_slots;
-  c.elem = (int64_t)(pool_bytes / (kBlockElem * 40)) + 2 * max_slots;
+  c.elem = (int64_t)(pool_bytes / (kElemTile * 40)) + 2 * max_slots;
   c.node = (int64_t)(pool_bytes / (kBlockNode * 16)) + 2 * max_slots;
   c.row = (int64_t)(pool_bytes / (32 * 64)) + 2 * max_slots;
   c.vec = (int64_t)(pool_bytes / (kVecTile * 64)) + 2 * max_slots;
@@ -169,6 +169,7 @@ struct Engine {
     S.bhat = D.bhat;
     S.conn = D.conn;
     S.geo = E.prec == P1E_MIXED ? (const void *)D.geo32 : (const void *)D.geo64;
+    S.gcls = D.geo_cls;
     S.row_ptr = D.row_ptr;
     S.ent = D.ent;
     S.row_info = D.row_info;

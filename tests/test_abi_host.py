@@ -143,3 +143,26 @@ def test_partially_prescribed_nodes_are_free_nodes(p1e):
         assert info["n_free_nodes"] == int((dm.min(axis=1) == 0).sum())
     finally:
         p1e.mesh_destroy(h)
+
+
+def test_geometry_classes(p1e):
+    """Uniform structured meshes have a few classes of element records (equal up to the
+    rounding of node coordinates); jittered ones have one per element and keep full arrays."""
+    P = S.neohooke_box_3d(5, 4, 3)
+    h = p1e.mesh_create(3, "neohooke", P.conn, P.coords, P.dirichlet, P.dirichlet_values,
+                        P.load, C1=1.0, D1=1.0)
+    assert p1e.mesh_get_info(h)["geometry_classes"] == 6
+    p1e.mesh_destroy(h)
+    P2 = S.plaplace_square(n=9)
+    h = p1e.mesh_create(2, "plaplace", P2.conn, P2.coords, P2.dirichlet, p=3.0)
+    assert p1e.mesh_get_info(h)["geometry_classes"] == 2
+    p1e.mesh_destroy(h)
+    h = p1e.mesh_create(2, "plaplace", P2.conn, P2.coords, P2.dirichlet, p=3.0,
+                        flags=p1e.P1E_FULL_GEOMETRY)
+    assert p1e.mesh_get_info(h)["geometry_classes"] == 0
+    p1e.mesh_destroy(h)
+    P3 = S.plaplace_square(n=17)  # 578 elements, more than 256 possible classes
+    X = P3.coords + 1e-3 * np.random.default_rng(0).standard_normal(P3.coords.shape)
+    h = p1e.mesh_create(2, "plaplace", P3.conn, X, P3.dirichlet, p=3.0)
+    assert p1e.mesh_get_info(h)["geometry_classes"] == 0
+    p1e.mesh_destroy(h)

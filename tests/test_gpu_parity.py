@@ -253,3 +253,77 @@ def test_internal_order_does_not_change_results(P, oracle_mod):
     assert np.abs(o0 - o1).max() <= 1e-13 * np.abs(o0).max()
     assert np.linalg.norm(g0 - g1) <= 1e-13 * np.linalg.norm(g0)
     assert np.linalg.norm(f0 - f1) <= 1e-9 * np.linalg.norm(f0)
+
+
+@pytest.mark.parametrize("name", ["nh3d_box_13x7x5", "plap_square_33", "nh2d_beam_60x13"])
+def test_geometry_classes_match_per_element_geometry(P, name):
+    """Classed geometry (one record per class of elements whose records agree to 2^-40)
+    changes results only at the level of coordinate rounding."""
+    prob = _get(name)
+    v = torch.tensor(prob.vhat(), device="cuda")
+    outs = []
+    for flags in (0, P.P1E_FULL_GEOMETRY):
+        m = P.Mesh.from_problem(prob, modes=P.P1E_FP64 | P.P1E_MIXED | P.P1E_FD, flags=flags)
+        assert (m.info["geometry_classes"] > 0) == (flags == 0)
+        res = []
+        for prec in ("fp64", "mixed"):
+            g, o, _ = m.grad_exact(v, prec)
+            e, _ = m.energy(v, prec)
+            res += [g.cpu().numpy(), o.cpu().numpy(), e.cpu().numpy()]
+        f, _ = m.grad_patch_fd(v, prob.eps)
+        res.append(f.cpu().numpy())
+        outs.append(res)
+    tols = [1e-13, 1e-14, 1e-14, 1e-6, 1e-6, 1e-6, 1e-9]
+    for a, b, t in zip(*outs, tols):
+        assert np.linalg.norm(a - b) <= t * np.linalg.norm(b)
+
+
+DELTAS = [-0.999, -0.9, -0.5, -0.3, -0.2929, -0.2928, -0.1, -1e-3, -1e-7, -1e-12, 0.0, 1e-12,
+          1e-7, 1e-3, 0.2, 0.4142, 0.4143, 0.9, 1.5, 3.0, 20.0, 1e3]
+
+
+def _w_exact(G, C1, D1):
+    """W of eq. (neoHook) at F = I + G in 80-digit arithmetic (G's binary values taken exactly)."""
+    import mpmath
+    with mpmath.workdps(80):
+        dim = G.shape[0]
+        F = mpmath.matrix([[mpmath.mpf(float(G[i, j])) + (1 if i == j else 0) for j in range(dim)]
+                           for i in range(dim)])
+        detF = mpmath.det(F)
+        I1 = sum(F[i, j] ** 2 for i in range(dim) for j in range(dim))
+        return float(C1 * (I1 - dim - 2 * mpmath.log(detF)) + D1 * (detF - 1) ** 2)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_neohooke_log_term_over_wide_det_range(P, dim):
+    """One reference simplex (B^-1 = I, |T| = 1/dim!) under F = I + G with det F - 1 from
+    -0.999 to 1e3 and down to 1e-12: J = |T| W against W evaluated in 80-digit arithmetic at
+    the G the kernels see. Covers both branches of the log term (1 + d inside and outside
+    [1/sqrt 2, sqrt 2)) and the cancellation near det F = 1."""
+    C1, D1 = 0.7, 1.9
+    x = np.vstack([np.zeros(dim), np.eye(dim)])
+    conn = np.arange(dim + 1, dtype=np.int32)[None, :]
+    mesh = P.Mesh(dim, "neohooke", conn, x, C1=C1, D1=D1, modes=P.P1E_FP64 | P.P1E_MIXED)
+    vol = 1.0 / (2.0 if dim == 2 else 6.0)
+    worst = {"fp64": 0.0, "mixed": 0.0}
+    for d in DELTAS:
+        for shear in (0.0, 0.3):
+            G = np.zeros((dim, dim))
+            G[0, 0] = d
+            G[0, 1] = shear
+            v = x + x @ G.T  # v_l = x_l + G x_l
+            Geff = (v - x)[1:].T  # the displacement gradient the kernels form (B^-1 = I)
+            vhat = torch.tensor(v.ravel(), device="cuda")
+            for prec in ("fp64", "mixed"):
+                Gk = Geff if prec == "fp64" else Geff.astype(np.float32).astype(np.float64)
+                want = vol * _w_exact(Gk, C1, D1)
+                out3, flag = mesh.energy(vhat, prec)
+                J = float(out3[0].item())
+                assert int(flag.item()) == 0
+                if want == 0.0:
+                    assert abs(J) <= 1e-300
+                    continue
+                worst[prec] = max(worst[prec], abs(J - want) / want)
+    _note(f"[log term dim {dim}] worst relative error {worst}")
+    assert worst["fp64"] <= 1e-13
+    assert worst["mixed"] <= 1e-5
