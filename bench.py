@@ -1,8 +1,8 @@
 """Benchmark: elements/s of J + exact grad J for 3D Neo-Hookean on ~6M tetrahedra (one GPU).
 
 One step = one energy-and-gradient evaluation through the autograd hook
-(``p1_energy(vhat).backward()``: prepass, element energy + forces, patch gather, compensated
-finalize) on the 460x46x46-cube Kuhn box (5,840,160 tets), mixed precision, inputs resident in
+(``p1_energy(vhat).backward()``: element tiles with energy, forces and in-tile patch sums,
+halo rows, compensated finalize, scaled gradient) on the 460x46x46-cube Kuhn box (5,840,160 tets), mixed precision, inputs resident in
 HBM. Prints ONE JSON line. Extra fields report the FP64 path, the patch central-difference
 gradient on the same mesh, the serving benchmark (256 minimization requests, Poisson arrivals,
 continuous batching vs one-at-a-time FP64 solves: req/s, p50/p99 latency), the dominant kernel against the HBM roofline (HIP events around
@@ -41,24 +41,29 @@ def _args():
     return ap.parse_args()
 
 
-def algorithmic_bytes(info, prec):
+def algorithmic_bytes(info, prec, classed):
     """Compulsory HBM bytes of one J + exact grad J call, per kernel (each array touched once).
 
-    Element pass: connectivity 4(dim+1) B, B^-1 and |T| (dim^2 + 1) words, the nodal field
-    once per node, element forces (dim+1) d words written. Gather: patch entries 4 B each,
-    row pointer and row info 8 B per free node, forces read once, b read and g written per
-    free DOF. Prepass: per node the DOF map 4 B, vhat, x, b read once and the nodal field
-    written."""
+    k_tile_force: local connectivity 2(dim+1) B and the geometry class 1 B (or B^-1 and |T|,
+    dim^2 + 1 words) per element; local patch entries 2 B per free-node incidence; the tile
+    node records (node, record, slot: 12 B; row pointer: 2 B) per tile node; per node the
+    DOF map 4 B and the subtrahend/prescribed values 8d B; per free DOF vhat and b read and
+    g written (rows complete in one tile); per free row its row info 4 B; the halo partial
+    sums 8d B per slot written. k_halo: per halo row 8 B of row index and pointer, its row
+    info 4 B, b read and g written (8d B each); per slot its index 4 B and partial 8d B
+    read. k_scale: the kept gradient read and g written."""
     ne, nn, nf, nfd, nnz = (info["ne"], info["nn"], info["n_free_nodes"], info["n_free_dofs"],
                             info["nnz"])
     dim, d = info["dim"], info["ncomp"]
     w = 4 if prec == "mixed" else 8
-    ns = 4 if d == 3 else d
-    elem = ne * (4 * (dim + 1) + w * (dim * dim + 1) + w * (dim + 1) * d) + nn * ns * w
-    gather = 4 * nnz + 8 * nf + w * (dim + 1) * d * ne + 16 * nfd
-    prepass = nn * (4 + 8 * dim) + 16 * nfd + nn * ns * w
-    return {"k_element_force": elem, "k_gather": gather, "k_prepass": prepass}
-
+    tn, nh, ns = info["n_tile_nodes"], info["n_halo_rows"], info["n_halo_slots"]
+    geo = ne if classed else ne * w * (dim * dim + 1)
+    complete_dofs = d * (nf - nh)
+    tile = (ne * 2 * (dim + 1) + geo + 2 * nnz + 14 * tn + nn * (4 + 8 * d) + 16 * nfd
+            + 4 * nf + 8 * complete_dofs + 8 * d * ns)
+    halo = nh * (12 + 16 * d) + ns * (4 + 8 * d)
+    scale = 16 * nfd
+    return {"k_tile_force": tile, "k_halo": halo, "k_scale": scale}
 
 
 def kernel_source_hash():
@@ -159,7 +164,7 @@ def main():
     P.prof_enable(False)
     kern = P.prof_collect()
 
-    abytes = algorithmic_bytes(info, a.prec)
+    abytes = algorithmic_bytes(info, a.prec, info["geometry_classes"] > 0)
     kstats = {k: {"launches": c, "avg_us": 1e3 * t / c} for k, (c, t) in kern.items()}
     dom = max(kstats, key=lambda k: kstats[k]["avg_us"])
     dom_bytes = abytes.get(dom)

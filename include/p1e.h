@@ -67,15 +67,14 @@ extern "C" {
 #define P1E_FD 4    /* bind-only bit: arrays for the patch central-difference gradient (FP64) */
 
 /* ------------------------------------------------------------------ mesh flags */
-/* P1E_LOCALITY_ORDER: renumber nodes and elements internally along a space-filling (Morton)
- * curve, for meshes whose input numbering has poor locality (e.g. from an unstructured
- * generator). It changes only the order of floating-point sums, never the external DOF
- * numbering. Without it the input order is kept (best for lexicographically numbered
- * structured meshes). */
-#define P1E_LOCALITY_ORDER 1
-/* P1E_LOCALITY_ROWS: renumber only the nodes (and so the patch rows) along the Morton curve,
- * keeping the element order. */
-#define P1E_LOCALITY_ROWS 2
+/* Internal numbering (never visible in vhat or gradients): the elements are grouped into
+ * tiles of consecutive elements, each evaluated by one workgroup with its nodal values and
+ * element results in on-chip memory, and the nodes are numbered in order of first use. By
+ * default the elements are first sorted along a Morton curve of their centroids, which makes
+ * tiles compact. P1E_INPUT_ORDER keeps the caller's element order instead (for callers that
+ * already number elements in compact clusters). Either choice changes only the order of
+ * floating-point sums. */
+#define P1E_INPUT_ORDER 1
 /* P1E_FULL_GEOMETRY: always store B^-1 and |T| per element. By default, element records
  * (B^-1, |T|) that agree to 2^-40 of each component's largest magnitude share one class, and
  * a mesh with at most 256 classes (uniformly refined structured meshes have a few) stores one
@@ -90,7 +89,7 @@ typedef struct p1e_mesh_desc {
   int32_t dim;   /* 2 (triangles) or 3 (tetrahedra) */
   int32_t ncomp; /* d: 1 for P1E_PLAPLACE, dim for P1E_NEOHOOKE */
   int32_t kind;  /* P1E_PLAPLACE or P1E_NEOHOOKE */
-  int32_t flags; /* 0 or P1E_LOCALITY_ORDER | P1E_LOCALITY_ROWS | P1E_FULL_GEOMETRY */
+  int32_t flags; /* 0 or P1E_INPUT_ORDER | P1E_FULL_GEOMETRY */
   int64_t nn; /* number of nodes, 1 <= nn < 2^28 */
   int64_t ne; /* number of elements, 0 <= ne < 2^29 */
   const int32_t *conn;       /* [ne][dim+1] vertex indices, distinct, in [0, nn) */
@@ -113,11 +112,15 @@ typedef struct p1e_mesh_info {
   uint64_t alignment;  /* required alignment of the bound device buffer (bytes) */
   int32_t geometry_classes; /* distinct element records kept as a table (0: per element) */
   int32_t reserved;
+  int64_t n_tiles;      /* element tiles */
+  int64_t n_tile_nodes; /* sum over tiles of the distinct nodes of the tile */
+  int64_t n_halo_rows;  /* free nodes whose patch spans several tiles (or no element) */
+  int64_t n_halo_slots; /* partial patch sums of halo rows (one per tile and halo row) */
 } p1e_mesh_info;
 
 /* Build a mesh handle: validates the description, computes element geometry (|T| and basis
- * gradients, Section 4.1), the free-node patch lists (Section 4.2, stored as one row of
- * (element, local vertex) pairs per free node), the DOF maps and b = M f (Section 3.2).
+ * gradients, Section 4.1), the free-node patch lists (Section 4.2, split by element tiles
+ * into rows of (element, local vertex) pairs), the DOF maps and b = M f (Section 3.2).
  * Host-only; needs no GPU. Returns P1E_EINVAL or P1E_EDEGEN on bad input. */
 int p1e_mesh_create(const p1e_mesh_desc *desc, p1e_mesh **out);
 
@@ -141,21 +144,22 @@ int p1e_energy(p1e_mesh *mesh, const double *vhat, int prec, double *out3, int32
                void *stream);
 
 /* Exact gradient (Section 6.2): g[n] = dJ/dv_n for the free DOFs, FP64, in vhat order.
- * Element forces |T| dW/dF grad phi are formed per element and gathered per free node over
- * its patch (no atomics). out3 (nullable) receives the energy of the same call, as in
- * p1e_energy; flag receives the bad-element count. */
+ * Element forces |T| dW/dF grad phi are formed per element and summed per free node over
+ * its patch in a fixed order (no atomics): within an element tile from on-chip memory, then
+ * over the tiles the patch spans. out3 (nullable) receives the energy of the same call, as
+ * in p1e_energy; flag receives the bad-element count. */
 int p1e_grad_exact(p1e_mesh *mesh, const double *vhat, int prec, double *g, double *out3,
                    int32_t *flag, void *stream);
 
-/* The exact gradient in its two phases, for a differentiation hook whose backward pass runs
- * later than its forward pass (Section 6.2 split at the element/patch boundary):
- *   p1e_energy_forces  energy as p1e_energy, and the element forces |T| dW/dF grad phi_l of
- *                      every element, kept in the mesh's scratch arrays;
- *   p1e_grad_gather    g[n] = s * (sum over the patch of node(n) of the kept forces - b_n)
- *                      with s = *scale (a device double; NULL means 1).
- * p1e_grad_gather returns P1E_ESTATE unless the last force-producing call on this mesh
- * (p1e_energy_forces or p1e_grad_exact) used the same prec; p1e_grad_patch_fd overwrites the
- * forces. Calls must be enqueued in that order on one stream, or ordered by the caller. */
+/* The exact gradient in two calls, for a differentiation hook whose backward pass runs later
+ * than its forward pass:
+ *   p1e_energy_forces  energy as p1e_energy, and the exact gradient (as p1e_grad_exact)
+ *                      kept in the mesh's scratch arrays;
+ *   p1e_grad_gather    g[n] = s * (kept gradient)[n] with s = *scale (a device double; NULL
+ *                      means 1), which is s * (patch sum of the element forces - b_n).
+ * p1e_grad_gather returns P1E_ESTATE unless a p1e_energy_forces call with the same prec came
+ * before it (p1e_minimize clears the kept gradient). Calls must be enqueued in that order on
+ * one stream, or ordered by the caller. */
 int p1e_energy_forces(p1e_mesh *mesh, const double *vhat, int prec, double *out3,
                       int32_t *flag, void *stream);
 int p1e_grad_gather(p1e_mesh *mesh, int prec, const double *scale, double *g, void *stream);
@@ -200,7 +204,7 @@ uint64_t p1e_minimize_workspace_bytes(const p1e_mesh *mesh, const p1e_lbfgs_opts
 
 /* Minimize from vhat (device, in/out) on a mesh bound for opts->prec. ws: caller-owned device
  * buffer (256-byte aligned, p1e_minimize_workspace_bytes). Synchronous on stream. Overwrites
- * the mesh's force scratch (a following p1e_grad_gather returns P1E_ESTATE). P1E_EDOMAIN if
+ * the mesh's scratch arrays (a following p1e_grad_gather returns P1E_ESTATE). P1E_EDOMAIN if
  * the start point has bad elements. */
 int p1e_minimize(p1e_mesh *mesh, double *vhat, const p1e_lbfgs_opts *opts, void *ws,
                  uint64_t ws_bytes, p1e_min_report *report, void *stream);

@@ -5,7 +5,7 @@ package is its thin Python binding. Importing it fails if the library is not bui
 """
 
 from ._lib import (  # noqa: F401
-    P1E_FD, P1E_FP64, P1E_FULL_GEOMETRY, P1E_LOCALITY_ORDER, P1E_LOCALITY_ROWS, P1E_MIXED,
+    P1E_FD, P1E_FP64, P1E_FULL_GEOMETRY, P1E_INPUT_ORDER, P1E_MIXED,
     P1E_NEOHOOKE, P1E_PLAPLACE, P1EError, lib,
 )
 from .api import (  # noqa: F401

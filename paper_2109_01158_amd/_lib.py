@@ -29,8 +29,7 @@ P1E_FP64 = 1
 P1E_MIXED = 2
 P1E_FD = 4
 
-P1E_LOCALITY_ORDER = 1
-P1E_LOCALITY_ROWS = 2
+P1E_INPUT_ORDER = 1
 P1E_FULL_GEOMETRY = 4
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EDEGEN", -3: "ENOMEM", -4: "EHIP", -5: "EDOMAIN",
@@ -56,7 +55,9 @@ class MeshInfo(ctypes.Structure):
         ("total_volume", ctypes.c_double), ("min_volume", ctypes.c_double),
         ("max_volume", ctypes.c_double), ("dirichlet_bv", ctypes.c_double),
         ("alignment", ctypes.c_uint64), ("geometry_classes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("n_tiles", ctypes.c_int64),
+        ("n_tile_nodes", ctypes.c_int64), ("n_halo_rows", ctypes.c_int64),
+        ("n_halo_slots", ctypes.c_int64),
     ]
 
 

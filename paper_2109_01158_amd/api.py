@@ -41,7 +41,7 @@ def neohooke_constants(E, nu):
 def mesh_create(dim, kind, conn, coords, dirichlet=None, dirichlet_values=None, load=None,
                 p=2.0, C1=0.0, D1=0.0, flags=0):
     """p1e_mesh_create. kind: "plaplace" | "neohooke". Arrays are host numpy; returns an
-    opaque handle (int). flags: 0 or P1E_LOCALITY_ORDER."""
+    opaque handle (int). flags: 0 or P1E_INPUT_ORDER | P1E_FULL_GEOMETRY."""
     k = P1E_NEOHOOKE if kind in ("neohooke", P1E_NEOHOOKE) else P1E_PLAPLACE
     ncomp = dim if k == P1E_NEOHOOKE else 1
     conn = np.ascontiguousarray(conn, dtype=np.int32)
@@ -94,14 +94,14 @@ def grad_exact(handle, vhat, prec, g, out3, flag, stream=None):
 
 
 def energy_forces(handle, vhat, prec, out3, flag, stream=None):
-    """p1e_energy_forces: energy, and the element forces kept for grad_gather."""
+    """p1e_energy_forces: energy, and the exact gradient kept for grad_gather."""
     check(L.lib().p1e_energy_forces(ctypes.c_void_p(handle), _dptr(vhat), PREC[prec],
                                     _dptr(out3), _dptr(flag), _stream_ptr(stream, flag.device)))
 
 
 def grad_gather(handle, prec, scale, g, stream=None):
-    """p1e_grad_gather: g = scale * (patch sums of the kept forces - b); scale is a device
-    0-d/1-element f64 tensor or None."""
+    """p1e_grad_gather: g = scale * (kept gradient); scale is a device 0-d/1-element f64
+    tensor or None."""
     check(L.lib().p1e_grad_gather(ctypes.c_void_p(handle), PREC[prec], _dptr(scale), _dptr(g),
                                   _stream_ptr(stream, g.device)))
 
@@ -159,8 +159,8 @@ class Mesh:
         with torch.cuda.device(self.device):
             mesh_bind(self.handle, self.buf, self.nbytes, modes, stream)
         self.n_free_dofs = int(self.info["n_free_dofs"])
-        # bumped by every call that rewrites the element-force scratch; lets a
-        # differentiation hook know whether the forces of its forward pass are still there
+        # bumped by every call that rewrites the kept gradient (energy_forces, minimize); lets
+        # a differentiation hook know whether the gradient of its forward pass is still there
         self.forces_gen = 0
 
     @classmethod
@@ -211,11 +211,11 @@ class Mesh:
         out3 = torch.empty(3, dtype=torch.float64, device=self.device) if out3 is None else out3
         flag = torch.empty(1, dtype=torch.int32, device=self.device) if flag is None else flag
         grad_exact(self.handle, vhat, prec, g, out3, flag, stream)
-        self.forces_gen += 1
         return g, out3, flag
 
     def energy_forces(self, vhat, prec="mixed", stream=None, out3=None, flag=None):
-        """Energy plus element forces kept for grad_gather; returns (out3, flag, generation)."""
+        """Energy plus the exact gradient kept for grad_gather; returns (out3, flag,
+        generation)."""
         self._check_vhat(vhat)
         out3 = torch.empty(3, dtype=torch.float64, device=self.device) if out3 is None else out3
         flag = torch.empty(1, dtype=torch.int32, device=self.device) if flag is None else flag
@@ -235,7 +235,6 @@ class Mesh:
         g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device)
         flag = torch.empty(1, dtype=torch.int32, device=self.device)
         grad_patch_fd(self.handle, vhat, eps, g, flag, stream)
-        self.forces_gen += 1
         return g, flag
 
 

@@ -2,12 +2,12 @@
 
 ``P1Energy.apply(vhat, mesh, prec)`` returns the 0-d energy J(vhat) on the device.
 
-When ``vhat`` requires grad, the forward pass runs the element phase of the exact gradient
-(energy plus element forces, ``p1e_energy_forces``) and the backward pass runs its node phase
-(``p1e_grad_gather``), which applies the incoming gradient as a device-side scale: one pass
-over the mesh in total and no extra elementwise kernels. If another call rewrote the mesh's
-force scratch between the two passes, backward recomputes the gradient at the saved input.
-The bad-element count of the forward pass is kept on ``mesh.last_flag``.
+When ``vhat`` requires grad, the forward pass computes the energy and the exact gradient in
+one pass over the mesh (``p1e_energy_forces``, which keeps the gradient on the device), and
+the backward pass scales the kept gradient by the incoming gradient, a device-side scalar
+(``p1e_grad_gather``). If another call rewrote the kept gradient between the two passes,
+backward recomputes it at the saved input. The bad-element count of the forward pass is kept
+on ``mesh.last_flag``.
 """
 
 import torch

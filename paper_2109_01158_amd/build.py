@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libp1e.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["p1e_api.cpp", "p1e_kernels.hip", "p1e_batch.hip", "p1e_serve.cpp"]
+SOURCES = ["p1e_api.cpp", "p1e_tiles.cpp", "p1e_kernels.hip", "p1e_batch.hip", "p1e_serve.cpp"]
 
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 arithmetic; contraction is
 # off because the kernels place their fused multiply-adds explicitly.

@@ -4,8 +4,8 @@
 // Setup follows Sections 3-4 of Moskovka & Valdman (arXiv 2109.01158): element sizes and
 // basis gradients (Section 4.1), nodal patches of free nodes (Section 4.2, Remark 1) and the
 // linear term b = M f (Section 3.2). The paper stores each patch as long matrices that
-// replicate element data per patch row; here a patch row is one 4-byte (element, local
-// vertex) pair and element data is stored once, so the gradient gathers through it.
+// replicate element data per patch row; here element data is stored once, elements are
+// grouped into tiles (p1e_tiles.cpp) and the patches are summed tile by tile.
 
 #include <hip/hip_runtime.h>
 
@@ -71,27 +71,9 @@ void prof_end(hipStream_t s) {
 // ------------------------------------------------------------------------- buffer layout
 static uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-static int node_stride(int d) { return d == 3 ? 4 : d; }
-
-uint64_t u_bytes(const p1e_mesh *m, int modes) {
-  uint64_t es = (modes & (P1E_FP64 | P1E_FD)) ? 8 : 4;
-  return (uint64_t)m->nn * node_stride(m->d) * es;
-}
-
-// whole blocks of element records: the element kernel writes full blocks without tail checks
-uint64_t r_bytes(const p1e_mesh *m, int modes) {
-  uint64_t es = (modes & (P1E_FP64 | P1E_FD)) ? 8 : 4;
-  return (uint64_t)padded_elements(m->ne) * m->k * m->d * es;
-}
-
-int64_t part_slots(const p1e_mesh *m) {
-  int64_t n = std::max<int64_t>(element_blocks(m->ne), node_blocks(m->nn));
-  return std::max<int64_t>(n, 1);
-}
-
 struct Layout {
-  uint64_t node_info, node_int, xref, vD, bhat, conn, geo64, geo32, geo_cls, row_ptr, ent, row_info, u,
-      r, part, badp, total;
+  uint64_t wref, bhat, conn_loc, geo64, geo32, geo_cls, ttile, trec, tlent, hrec, hpart, gw,
+      part, badp, total;
 };
 
 static Layout make_layout(const p1e_mesh *m, int modes) {
@@ -103,23 +85,22 @@ static Layout make_layout(const p1e_mesh *m, int modes) {
     return at;
   };
   const int dd = m->dim * m->dim + 1;
-  L.node_info = take(4ull * m->nn);
-  L.node_int = take(4ull * m->nn);
-  L.xref = take(m->kind == P1E_NEOHOOKE ? 8ull * m->nn * m->dim : 0);
-  L.vD = take(8ull * m->nn * m->d);
+  const uint64_t nt1 = (uint64_t)std::max<int64_t>(m->ntiles, 1);
+  L.wref = take(8ull * m->nn * m->d);
   L.bhat = take(8ull * m->nfd);
-  L.conn = take(4ull * m->ne * m->k);
+  L.conn_loc = take(2ull * m->ne * m->k);
   const uint64_t grec = m->nclass ? (uint64_t)m->nclass : (uint64_t)m->ne;  // geometry records
   L.geo64 = take((modes & (P1E_FP64 | P1E_FD)) ? 8ull * dd * grec : 0);
   L.geo32 = take((modes & P1E_MIXED) ? 4ull * dd * grec : 0);
   L.geo_cls = take(m->nclass ? (uint64_t)m->ne : 0);
-  L.row_ptr = take(4ull * (m->nf + 1));
-  L.ent = take(4ull * m->nnz);
-  L.row_info = take(4ull * m->nf);
-  L.u = take(u_bytes(m, modes));
-  L.r = take(r_bytes(m, modes));
-  L.part = take(16ull * 2 * part_slots(m));  // element partials, then node partials
-  L.badp = take(4ull * part_slots(m));
+  L.ttile = take(4ull * m->ttile.size());
+  L.trec = take(4ull * m->trec.size());
+  L.tlent = take(2ull * m->tlent.size());
+  L.hrec = take(4ull * m->hrec.size());
+  L.hpart = take(8ull * m->nslots * m->d);
+  L.gw = take(8ull * m->nfd);
+  L.part = take(16ull * 2 * nt1);  // energy partials, then b.v partials
+  L.badp = take(4ull * nt1);
   L.total = off;
   return L;
 }
@@ -219,44 +200,44 @@ struct MortonKey {
   }
 };
 
-// Internal numbering of nodes and elements along a Morton curve, so that the elements of a
-// nodal patch, and the patches of neighbouring nodes, sit close together in memory. The
-// external DOF numbering (vhat, gradients) is not affected.
-void locality_order(const p1e_mesh_desc *D, std::vector<int32_t> &nperm,
+// Internal numbering. Elements: along a Morton curve of their centroids, so that a run of
+// consecutive elements (a tile) is a compact cluster whose nodes are mostly its own
+// (P1E_INPUT_ORDER keeps the caller's order). Nodes keep the caller's numbering: a tile lists
+// its nodes in ascending order, so its reads of vhat, b and x and its writes of the gradient
+// (all in the caller's DOF order) run through contiguous stretches of memory.
+void internal_order(const p1e_mesh_desc *D, std::vector<int32_t> &nperm,
                     std::vector<int32_t> &eperm) {
   const int dim = D->dim, k = dim + 1;
   const int64_t nn = D->nn, ne = D->ne;
-  nperm.resize(nn);
   eperm.resize(ne);
-  for (int64_t i = 0; i < nn; ++i) nperm[i] = (int32_t)i;
   for (int64_t e = 0; e < ne; ++e) eperm[e] = (int32_t)e;
-  if (!(D->flags & (P1E_LOCALITY_ORDER | P1E_LOCALITY_ROWS))) return;
-  MortonKey key{dim, {0, 0, 0}, 0.0};
-  double hi[3] = {0, 0, 0}, ext = 0.0;
-  for (int a = 0; a < dim; ++a) {
-    key.lo[a] = INFINITY;
-    hi[a] = -INFINITY;
-  }
-  for (int64_t i = 0; i < nn; ++i)
+  if (!(D->flags & P1E_INPUT_ORDER) && ne > 1) {
+    MortonKey key{dim, {0, 0, 0}, 0.0};
+    double hi[3] = {0, 0, 0}, ext = 0.0;
     for (int a = 0; a < dim; ++a) {
-      key.lo[a] = std::min(key.lo[a], D->coords[i * dim + a]);
-      hi[a] = std::max(hi[a], D->coords[i * dim + a]);
+      key.lo[a] = INFINITY;
+      hi[a] = -INFINITY;
     }
-  for (int a = 0; a < dim; ++a) ext = std::max(ext, hi[a] - key.lo[a]);
-  const int bits = dim == 3 ? 21 : 32;
-  key.scale = ext > 0.0 ? (double)((1ull << bits) - 1) / ext : 0.0;
-  std::vector<uint64_t> nk(nn), ek(ne);
-  for (int64_t i = 0; i < nn; ++i) nk[i] = key(D->coords + i * dim);
-  for (int64_t e = 0; e < ne; ++e) {
-    double c[3] = {0, 0, 0};
-    for (int l = 0; l < k; ++l)
-      for (int a = 0; a < dim; ++a) c[a] += D->coords[(int64_t)D->conn[e * k + l] * dim + a];
-    for (int a = 0; a < dim; ++a) c[a] /= k;
-    ek[e] = key(c);
-  }
-  std::stable_sort(nperm.begin(), nperm.end(), [&](int32_t a, int32_t b) { return nk[a] < nk[b]; });
-  if (D->flags & P1E_LOCALITY_ORDER)
+    for (int64_t i = 0; i < nn; ++i)
+      for (int a = 0; a < dim; ++a) {
+        key.lo[a] = std::min(key.lo[a], D->coords[i * dim + a]);
+        hi[a] = std::max(hi[a], D->coords[i * dim + a]);
+      }
+    for (int a = 0; a < dim; ++a) ext = std::max(ext, hi[a] - key.lo[a]);
+    const int bits = dim == 3 ? 21 : 32;
+    key.scale = ext > 0.0 ? (double)((1ull << bits) - 1) / ext : 0.0;
+    std::vector<uint64_t> ek(ne);
+    for (int64_t e = 0; e < ne; ++e) {
+      double c[3] = {0, 0, 0};
+      for (int l = 0; l < k; ++l)
+        for (int a = 0; a < dim; ++a) c[a] += D->coords[(int64_t)D->conn[e * k + l] * dim + a];
+      for (int a = 0; a < dim; ++a) c[a] /= k;
+      ek[e] = key(c);
+    }
     std::stable_sort(eperm.begin(), eperm.end(), [&](int32_t a, int32_t b) { return ek[a] < ek[b]; });
+  }
+  nperm.resize(nn);
+  for (int64_t i = 0; i < nn; ++i) nperm[i] = (int32_t)i;
 }
 
 // Geometry classes: meshes made by uniform refinement of structured grids have only a few
@@ -329,13 +310,13 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
 
   // ---- internal numbering (internal -> external) and its inverse for nodes
   std::vector<int32_t> nperm, eperm;
-  locality_order(D, nperm, eperm);
+  internal_order(D, nperm, eperm);
   std::vector<int32_t> ninv(nn);
   for (int64_t i = 0; i < nn; ++i) ninv[nperm[i]] = (int32_t)i;
 
   // ---- element geometry (Section 4.1) and connectivity, structure of arrays, internal order
   const int dd = dim * dim + 1;
-  m->conn.resize((size_t)k * ne);
+  std::vector<int32_t> conn((size_t)k * ne);
   m->geo64.resize((size_t)dd * ne);
   double vmin = INFINITY, vmax = 0.0;
   HostAcc vsum;
@@ -343,7 +324,7 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   for (int64_t e = 0; e < ne; ++e) {
     const int64_t ex = eperm[e];
     const int32_t *T = D->conn + ex * k;
-    for (int l = 0; l < k; ++l) m->conn[(size_t)l * ne + e] = ninv[T[l]];
+    for (int l = 0; l < k; ++l) conn[(size_t)l * ne + e] = ninv[T[l]];
     double Bi[3][3], h;
     double det = edge_inverse(dim, D->coords, T, Bi, &h);
     if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * std::pow(h, dim))
@@ -374,48 +355,38 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   }
   m->nfd = nfd;
 
-  // ---- node arrays in external order (the prepass streams them and writes the nodal field
-  // at the internal position node_int[i]); free-node rows in internal node order
-  m->node_info = ext_info;
-  m->node_int = ninv;
-  m->vD.assign((size_t)nn * d, 0.0);
-  if (D->dirichlet && D->dirichlet_values)
-    for (int64_t i = 0; i < nn * d; ++i)
-      if (D->dirichlet[i]) m->vD[i] = D->dirichlet_values[i];
-  if (m->kind == P1E_NEOHOOKE) m->xref.assign(D->coords, D->coords + (size_t)nn * dim);
-  std::vector<int32_t> free_row(nn, -1);
+  // ---- nodes in internal order: DOF map, and the values the kernels turn into the nodal
+  // field u (u = v - x for Neo-Hookean, u = v for the p-Laplacian): for a free component
+  // the subtrahend (x or 0), for a prescribed one u itself
+  const bool nh = m->kind == P1E_NEOHOOKE;
+  m->ninfo.resize(nn);
+  m->wref.assign((size_t)nn * d, 0.0);
   int64_t nf = 0;
-  for (int64_t i = 0; i < nn; ++i)
-    if (ext_info[nperm[i]] & 7) free_row[i] = (int32_t)nf++;
+  for (int64_t i = 0; i < nn; ++i) {
+    const int64_t x = nperm[i];
+    const int info = ext_info[x];
+    m->ninfo[i] = info;
+    for (int j = 0; j < d; ++j) {
+      const double xr = nh ? D->coords[x * dim + j] : 0.0;
+      double w;
+      if ((info >> j) & 1) {
+        w = xr;
+      } else {
+        w = (D->dirichlet && D->dirichlet[x * d + j] && D->dirichlet_values)
+                ? D->dirichlet_values[x * d + j]
+                : 0.0;
+        w -= xr;
+      }
+      m->wref[(size_t)i * d + j] = w;
+    }
+    if (info & 7) ++nf;
+  }
   m->nf = nf;
 
-  // ---- free-node patch rows (Section 4.2) as CSR of (element << 2 | local vertex), internal
-  // element ids ascending within each row (counting sort over the element loop)
-  m->row_ptr.assign(nf + 1, 0);
-  for (int64_t e = 0; e < ne; ++e)
-    for (int l = 0; l < k; ++l) {
-      int32_t r = free_row[m->conn[(size_t)l * ne + e]];
-      if (r >= 0) m->row_ptr[r + 1] += 1;
-    }
-  int maxv = 0;
-  for (int64_t r = 0; r < nf; ++r) {
-    maxv = std::max(maxv, m->row_ptr[r + 1]);
-    m->row_ptr[r + 1] += m->row_ptr[r];
-  }
-  m->max_valence = maxv;
-  m->nnz = m->row_ptr[nf];
-  m->ent.resize(m->nnz);
-  {
-    std::vector<int32_t> fill(m->row_ptr.begin(), m->row_ptr.end() - 1);
-    for (int64_t e = 0; e < ne; ++e)
-      for (int l = 0; l < k; ++l) {
-        int32_t r = free_row[m->conn[(size_t)l * ne + e]];
-        if (r >= 0) m->ent[fill[r]++] = ((uint32_t)e << 2) | (uint32_t)l;
-      }
-  }
-  m->row_info.resize(nf);
-  for (int64_t i = 0; i < nn; ++i)
-    if (free_row[i] >= 0) m->row_info[free_row[i]] = ext_info[nperm[i]];
+  // ---- element tiles, local patch rows and halo rows (Section 4.2 patches)
+  int rc = build_tiles(m, conn);
+  if (rc != P1E_OK) return rc;
+  std::vector<int32_t>().swap(conn);
 
   // ---- b = M f (Section 3.2): element mass matrix |T| (1 + delta_ab) / ((dim+1)(dim+2)),
   // so b_a += |T| (sum_c f_c + f_a) / ((dim+1)(dim+2)); external numbering
@@ -510,6 +481,10 @@ int p1e_mesh_get_info(const p1e_mesh *m, p1e_mesh_info *o) {
   o->dirichlet_bv = m->dirichlet_bv;
   o->alignment = kAlign;
   o->geometry_classes = m->nclass;
+  o->n_tiles = m->ntiles;
+  o->n_tile_nodes = m->ntnodes;
+  o->n_halo_rows = m->nhalo;
+  o->n_halo_slots = m->nslots;
   return P1E_OK;
 }
 
@@ -541,40 +516,41 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
     g32.resize(g64.size());
     for (size_t i = 0; i < g32.size(); ++i) g32[i] = (float)g64[i];
   }
-  bool ok = up(L.node_info, m->node_info.data(), 4 * m->node_info.size()) &&
-            up(L.node_int, m->node_int.data(), 4 * m->node_int.size()) &&
-            up(L.xref, m->xref.data(), 8 * m->xref.size()) &&
-            up(L.vD, m->vD.data(), 8 * m->vD.size()) &&
+  bool ok = up(L.wref, m->wref.data(), 8 * m->wref.size()) &&
             up(L.bhat, m->bhat.data(), 8 * m->bhat.size()) &&
-            up(L.conn, m->conn.data(), 4 * m->conn.size()) &&
+            up(L.conn_loc, m->conn_loc.data(), 2 * m->conn_loc.size()) &&
             ((mask & (P1E_FP64 | P1E_FD)) ? up(L.geo64, g64.data(), 8ull * dd * grec) : true) &&
             ((mask & P1E_MIXED) ? up(L.geo32, g32.data(), 4ull * dd * grec) : true) &&
             up(L.geo_cls, m->geo_cls.data(), m->geo_cls.size()) &&
-            up(L.row_ptr, m->row_ptr.data(), 4 * m->row_ptr.size()) &&
-            up(L.ent, m->ent.data(), 4 * m->ent.size()) &&
-            up(L.row_info, m->row_info.data(), 4 * m->row_info.size());
+            up(L.ttile, m->ttile.data(), 4 * m->ttile.size()) &&
+            up(L.trec, m->trec.data(), 4 * m->trec.size()) &&
+            up(L.tlent, m->tlent.data(), 2 * m->tlent.size()) &&
+            up(L.hrec, m->hrec.data(), 4 * m->hrec.size());
   hipError_t se = hipStreamSynchronize(s);
   if (!ok || se != hipSuccess)
     return fail(P1E_EHIP, std::string("upload failed: ") + hipGetErrorString(hipGetLastError()));
-  DevMesh &D = m->dev;
-  D.node_info = (const int32_t *)(base + L.node_info);
-  D.node_int = (const int32_t *)(base + L.node_int);
-  D.xref = (const double *)(base + L.xref);
-  D.vD = (const double *)(base + L.vD);
+  TileMesh &D = m->dev;
+  D = TileMesh{};
+  D.nn = (int32_t)m->nn;
+  D.ne = (int32_t)m->ne;
+  D.nfd = (int32_t)m->nfd;
+  D.ntiles = (int32_t)m->ntiles;
+  D.nhalo = (int32_t)m->nhalo;
+  D.wref = (const double *)(base + L.wref);
   D.bhat = (const double *)(base + L.bhat);
-  D.conn = (const int32_t *)(base + L.conn);
+  D.conn_loc = (const uint16_t *)(base + L.conn_loc);
   D.geo64 = (mask & (P1E_FP64 | P1E_FD)) ? (const double *)(base + L.geo64) : nullptr;
   D.geo32 = (mask & P1E_MIXED) ? (const float *)(base + L.geo32) : nullptr;
   D.geo_cls = m->nclass ? (const uint8_t *)(base + L.geo_cls) : nullptr;
   D.nclass = m->nclass;
-  D.row_ptr = (const int32_t *)(base + L.row_ptr);
-  D.ent = (const uint32_t *)(base + L.ent);
-  D.row_info = (const int32_t *)(base + L.row_info);
-  D.u = base + L.u;
-  D.r = base + L.r;
+  D.ttile = (const int4 *)(base + L.ttile);
+  D.trec = (const int4 *)(base + L.trec);
+  D.tlent = (const uint16_t *)(base + L.tlent);
+  D.hrec = (const int4 *)(base + L.hrec);
+  D.hpart = (double *)(base + L.hpart);
+  D.gw = (double *)(base + L.gw);
   D.part = (double2 *)(base + L.part);
   D.badp = (int32_t *)(base + L.badp);
-  m->part_cap = part_slots(m);
   m->bound_modes = mask;
   m->forces_prec = 0;
   int dev = -1;
@@ -607,9 +583,7 @@ int p1e_grad_exact(p1e_mesh *m, const double *vhat, int prec, double *g, double 
   int rc = check_call(m, vhat, prec);
   if (rc) return rc;
   if ((!g && m->nfd > 0) || !flag) return fail(P1E_EINVAL, "null output pointer");
-  rc = run_grad_exact(m, vhat, prec, g, out3, flag, (hipStream_t)stream);
-  m->forces_prec = rc == P1E_OK ? prec : 0;
-  return rc;
+  return run_grad_exact(m, vhat, prec, g, out3, flag, (hipStream_t)stream);
 }
 
 int p1e_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
@@ -627,9 +601,9 @@ int p1e_grad_gather(p1e_mesh *m, int prec, const double *scale, double *g, void 
   if (!m) return fail(P1E_EINVAL, "null mesh");
   if (prec != P1E_FP64 && prec != P1E_MIXED) return fail(P1E_EINVAL, "prec must be FP64 or MIXED");
   if (m->forces_prec != prec)
-    return fail(P1E_ESTATE, "no element forces of this precision: call p1e_energy_forces first");
+    return fail(P1E_ESTATE, "no gradient of this precision: call p1e_energy_forces first");
   if (!g && m->nfd > 0) return fail(P1E_EINVAL, "null output pointer");
-  return run_gather(m, prec, scale, g, (hipStream_t)stream);
+  return run_scale(m, scale, g, (hipStream_t)stream);
 }
 
 int p1e_grad_patch_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t *flag,
@@ -638,7 +612,6 @@ int p1e_grad_patch_fd(p1e_mesh *m, const double *vhat, double eps, double *g, in
   if (rc) return rc;
   if (!(eps > 0.0) || !std::isfinite(eps)) return fail(P1E_EINVAL, "eps must be > 0");
   if ((!g && m->nfd > 0) || !flag) return fail(P1E_EINVAL, "null output pointer");
-  m->forces_prec = 0;  // the patch differences overwrite the element force records
   return run_grad_fd(m, vhat, eps, g, flag, (hipStream_t)stream);
 }
 

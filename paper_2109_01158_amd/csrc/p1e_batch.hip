@@ -7,8 +7,8 @@
 // One engine step advances every active slot by one L-BFGS line-search trial (memory m,
 // two-loop recursion with H0 = (s.y / y.y) I, Armijo backtracking by halving, first step
 // scaled so that the largest nodal update is 0.1 h):
-//   evaluate   J and grad J at the trial point vt (prepass, element forces, finalize, patch
-//              gather; the same bodies as the single-mesh path, Sections 5 and 6.2)
+//   evaluate   J and grad J at the trial point vt (element tiles, halo rows, finalize; the
+//              same bodies as the single-mesh path, Sections 5 and 6.2)
 //   decide     accept (Armijo) or halve the step
 //   update     v, g and the newest (s, y) pair of accepted slots; trial point of rejected ones
 //   direction  two-loop recursion for slots that accepted, then the next trial point
@@ -46,66 +46,42 @@ __device__ __forceinline__ const int2 *tiles(const EngineDev &E, int &count) {
 }
 
 // ----------------------------------------------------------------------- evaluation
-template <typename T, int D, bool SUBX, int CLS>
-__global__ __launch_bounds__(kBlockNode) void kb_prepass(EngineDev E) {
-  int count;
-  const int2 *tl = tiles<TK_NODE, CLS>(E, count);
-  for (int t = blockIdx.x; t < count; t += gridDim.x) {
-    const int2 st = tl[t];
-    if (!evaluating(E, st.x)) continue;
-    const SlotDev &S = E.slots[st.x];
-    const int i = st.y * kBlockNode + threadIdx.x;
-    double s = 0.0, c = 0.0;
-    int cnt = 0;
-    if (i < S.nn)
-      prepass_node<T, D, SUBX>(i, S.node_info, S.node_int, S.vt, S.vD, S.xref, S.bhat, (T *)S.u,
-                               s, c);
-    block_reduce<kBlockNode>(s, c, cnt);
-    if (threadIdx.x == 0) S.part[S.ntile_e + st.y] = make_double2(s, c);
-    __syncthreads();
-  }
-}
+// element tiles of every evaluating slot of class C (persistent grid over the tile table)
+template <typename T>
+constexpr int batch_tile_threads() { return sizeof(T) == 4 ? 1024 : 512; }
 
-template <int DIM, int D, int KIND, typename T, int CLS>
-__global__ __launch_bounds__(kBlockElem) void kb_element(EngineDev E) {
+template <int DIM, int D, int KIND, typename T, int C>
+__global__ __launch_bounds__((batch_tile_threads<T>())) void kb_tile(EngineDev E) {
+  constexpr int NT = batch_tile_threads<T>();
+  __shared__ TileShared<DIM, D, T, MODE_FORCE, true> sh;
   int count;
-  const int2 *tl = tiles<TK_ELEM, CLS>(E, count);
+  const int2 *tl = tiles<TK_TILE, C>(E, count);
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const int2 st = tl[t];
     if (!evaluating(E, st.x)) continue;
     const SlotDev &S = E.slots[st.x];
-    double s = 0.0, c = 0.0;
-    int cnt = 0;
     const Params prm{S.C1, S.D1, S.p, 0.0};
-    if (S.gcls != nullptr)  // class table read through the caches (it differs per slot)
-      element_tile<DIM, D, KIND, T, MODE_FORCE, true>(st.y, S.ne, S.nep, S.conn,
-                                                      (const T *)S.geo, S.gcls, (const T *)S.u,
-                                                      (T *)S.r, prm, s, c, cnt);
+    const T *geo = sizeof(T) == 4 ? (const T *)S.M.geo32 : (const T *)S.M.geo64;
+    if (S.M.geo_cls != nullptr)
+      tile_pass<DIM, D, KIND, T, MODE_FORCE, true, NT>(S.M, st.y, geo, S.vt, S.gt, nullptr,
+                                                       prm, sh);
     else
-      element_tile<DIM, D, KIND, T, MODE_FORCE, false>(st.y, S.ne, S.nep, S.conn,
-                                                       (const T *)S.geo, nullptr,
-                                                       (const T *)S.u, (T *)S.r, prm, s, c, cnt);
-    block_reduce<kBlockElem>(s, c, cnt);
-    if (threadIdx.x == 0) {
-      S.part[st.y] = make_double2(s, c);
-      S.badp[st.y] = cnt;
-    }
-    __syncthreads();
+      tile_pass<DIM, D, KIND, T, MODE_FORCE, false, NT>(S.M, st.y, geo, S.vt, S.gt, nullptr,
+                                                        prm, sh);
   }
 }
 
-template <int K, int D, typename T, int GL, int CLS>
-__global__ __launch_bounds__(kBlock) void kb_gather(EngineDev E) {
+// halo rows (kBlock per tile) of every evaluating slot of class C
+template <int D, int C>
+__global__ __launch_bounds__(kBlock) void kb_halo(EngineDev E) {
   int count;
-  const int2 *tl = tiles<TK_ROW, CLS>(E, count);
+  const int2 *tl = tiles<TK_HALO, C>(E, count);
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const int2 st = tl[t];
     if (!evaluating(E, st.x)) continue;
     const SlotDev &S = E.slots[st.x];
-    const int row = st.y * (kBlock / GL) + threadIdx.x / GL;
-    gather_row<K, D, T, GL, P1E_GATHER_UNROLL>(row, threadIdx.x % GL, S.nf, S.nep, S.row_ptr,
-                                               S.ent, S.row_info, (const T *)S.r, S.bhat,
-                                               nullptr, S.gt);
+    const int h = st.y * kBlock + threadIdx.x;
+    if (h < S.M.nhalo) halo_row<D>(S.M, h, S.gt, nullptr);
   }
 }
 
@@ -144,8 +120,9 @@ __global__ __launch_bounds__(kVB) void kb_finalize(EngineDev E) {
   const SlotDev &S = E.slots[slot];
   double s, c, s2, c2;
   int cnt, dummy;
-  slot_sum(S.part, S.ntile_e, 1, 0, S.badp, s, c, cnt);
-  slot_sum(S.part + S.ntile_e, S.ntile_n, 1, 0, nullptr, s2, c2, dummy);
+  slot_sum(S.M.part, S.M.ntiles, 1, 0, S.M.badp, s, c, cnt);
+  __syncthreads();
+  slot_sum(S.M.part + S.M.ntiles, S.M.ntiles, 1, 0, nullptr, s2, c2, dummy);
   if (threadIdx.x == 0) {
     double *sc = E.sc + slot * kNSc;
     int *st = E.st + slot * kNSt;
@@ -211,7 +188,7 @@ __device__ __forceinline__ VTile vtile(const EngineDev &E, int t) {
   const int2 st = E.vmap[t];
   VTile v;
   v.slot = st.x;
-  v.n = E.slots[st.x].nfd;
+  v.n = E.slots[st.x].M.nfd;
   v.i0 = st.y * kVecTile;
   return v;
 }
@@ -513,32 +490,24 @@ __global__ __launch_bounds__(kVB) void kb_vtrial(EngineDev E) {
 }
 
 // ----------------------------------------------------------------------- launch sequence
-constexpr int kGridElem = 2048, kGridNode = 512, kGridRow = 4096, kGridVec = 2048;
+constexpr int kGridTile = 1024, kGridHalo = 2048, kGridVec = 2048;
 
 template <typename T>
 int eval_launches(const EngineDev &E, hipStream_t s) {
-  hipLaunchKernelGGL((kb_prepass<T, 1, false, CLS_PLAP2>), dim3(kGridNode), dim3(kBlockNode), 0, s, E);
-  hipLaunchKernelGGL((kb_prepass<T, 1, false, CLS_PLAP3>), dim3(kGridNode), dim3(kBlockNode), 0, s, E);
-  hipLaunchKernelGGL((kb_prepass<T, 2, true, CLS_NH2>), dim3(kGridNode), dim3(kBlockNode), 0, s, E);
-  hipLaunchKernelGGL((kb_prepass<T, 3, true, CLS_NH3>), dim3(kGridNode), dim3(kBlockNode), 0, s, E);
-  hipLaunchKernelGGL((kb_element<2, 1, P1E_PLAPLACE, T, CLS_PLAP2>), dim3(kGridElem), dim3(kBlockElem), 0, s, E);
-  hipLaunchKernelGGL((kb_element<3, 1, P1E_PLAPLACE, T, CLS_PLAP3>), dim3(kGridElem), dim3(kBlockElem), 0, s, E);
-  hipLaunchKernelGGL((kb_element<2, 2, P1E_NEOHOOKE, T, CLS_NH2>), dim3(kGridElem), dim3(kBlockElem), 0, s, E);
-  hipLaunchKernelGGL((kb_element<3, 3, P1E_NEOHOOKE, T, CLS_NH3>), dim3(kGridElem), dim3(kBlockElem), 0, s, E);
+  constexpr int NT = batch_tile_threads<T>();
+  hipLaunchKernelGGL((kb_tile<2, 1, P1E_PLAPLACE, T, CLS_PLAP2>), dim3(kGridTile), dim3(NT), 0, s, E);
+  hipLaunchKernelGGL((kb_tile<3, 1, P1E_PLAPLACE, T, CLS_PLAP3>), dim3(kGridTile), dim3(NT), 0, s, E);
+  hipLaunchKernelGGL((kb_tile<2, 2, P1E_NEOHOOKE, T, CLS_NH2>), dim3(kGridTile), dim3(NT), 0, s, E);
+  hipLaunchKernelGGL((kb_tile<3, 3, P1E_NEOHOOKE, T, CLS_NH3>), dim3(kGridTile), dim3(NT), 0, s, E);
   hipLaunchKernelGGL(kb_finalize, dim3(E.max_slots), dim3(kVB), 0, s, E);
-  hipLaunchKernelGGL((kb_gather<3, 1, T, P1E_GATHER_LANES_2D, CLS_PLAP2>), dim3(kGridRow), dim3(kBlock), 0, s, E);
-  hipLaunchKernelGGL((kb_gather<4, 1, T, P1E_GATHER_LANES_3D, CLS_PLAP3>), dim3(kGridRow), dim3(kBlock), 0, s, E);
-  hipLaunchKernelGGL((kb_gather<3, 2, T, P1E_GATHER_LANES_2D, CLS_NH2>), dim3(kGridRow), dim3(kBlock), 0, s, E);
-  hipLaunchKernelGGL((kb_gather<4, 3, T, P1E_GATHER_LANES_3D, CLS_NH3>), dim3(kGridRow), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_halo<1, CLS_PLAP2>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_halo<1, CLS_PLAP3>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_halo<2, CLS_NH2>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_halo<3, CLS_NH3>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
   return P1E_OK;
 }
 
 }  // namespace
-
-int rows_per_tile(int cls) {
-  const int gl = (cls == CLS_PLAP3 || cls == CLS_NH3) ? P1E_GATHER_LANES_3D : P1E_GATHER_LANES_2D;
-  return kBlock / gl;
-}
 
 int batch_step(const EngineDev &E, hipStream_t s) {
   if (E.prec == P1E_MIXED) eval_launches<float>(E, s);

@@ -1,7 +1,7 @@
 // p1e_device.h -- device-side building blocks shared by the single-mesh kernels
 // (p1e_kernels.hip) and the batched multi-request kernels (p1e_batch.hip): compensated sums,
 // block reductions, nodal field access, the densities and their stresses, and the bodies of
-// the node, element and patch passes. Not part of the public ABI.
+// the element-tile pass and of the halo-row pass. Not part of the public ABI.
 //
 // Precision. P1E_FP64 runs everything in double. P1E_MIXED evaluates the element algebra in
 // float on the displacement gradient G = F - I, with the cancellation-free forms
@@ -21,21 +21,12 @@
 #ifndef P1E_STREAM_NT
 #define P1E_STREAM_NT 0
 #endif
-#ifndef P1E_GATHER_LANES_3D
-#define P1E_GATHER_LANES_3D 8
-#endif
-#ifndef P1E_GATHER_LANES_2D
-#define P1E_GATHER_LANES_2D 4
-#endif
-#ifndef P1E_GATHER_UNROLL
-#define P1E_GATHER_UNROLL 3
-#endif
 namespace p1e {
 namespace dev {
 
 // Loads of arrays that one pass reads exactly once (connectivity, geometry, patch entries).
 // With P1E_STREAM_NT they are marked non-temporal, leaving cache capacity to the data that
-// is re-read (nodal fields, element force records).
+// is re-read (nodal values shared by neighbouring tiles).
 template <typename T>
 __device__ __forceinline__ T stream_load(const T *p) {
 #if P1E_STREAM_NT
@@ -89,6 +80,51 @@ __device__ __forceinline__ void block_reduce(double &s, double &c, int &cnt) {
       pair_add(s, c, sh_s[w], sh_c[w]);
       cnt += sh_n[w];
     }
+  }
+}
+
+// Block sums of two per-thread values and a count, for the element tiles, where each thread
+// holds one or two elements' worth: a plain FP64 tree within each 64-wide wavefront (an
+// error of at most 6 ulps of the wavefront's sum of magnitudes), then compensated (TwoSum)
+// sums of the per-wavefront results by the first wavefront. Fixed shuffle and LDS order:
+// the result does not depend on timing. Thread 0 gets (ra, rb, rc).
+template <int NT>
+__device__ __forceinline__ void tile_reduce2(double a, double b, int cnt, double2 &ra,
+                                             double2 &rb, int &rc) {
+  constexpr int NW = NT / 64;
+  __shared__ double sh_a[NW], sh_b[NW];
+  __shared__ int sh_n[NW];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double a2 = __shfl_xor(a, off, 64);
+    const double b2 = __shfl_xor(b, off, 64);
+    a += a2;
+    b += b2;
+  }
+  if (__any(cnt != 0))  // bad elements are rare: wave-uniform test
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh_a[wave] = a;
+    sh_b[wave] = b;
+    sh_n[wave] = cnt;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double sa = lane < NW ? sh_a[lane] : 0.0, ca = 0.0;
+    double sb = lane < NW ? sh_b[lane] : 0.0, cb = 0.0;
+    int n = lane < NW ? sh_n[lane] : 0;
+#pragma unroll
+    for (int off = NW / 2; off > 0; off >>= 1) {
+      const double sa2 = __shfl_down(sa, off, 64), ca2 = __shfl_down(ca, off, 64);
+      const double sb2 = __shfl_down(sb, off, 64), cb2 = __shfl_down(cb, off, 64);
+      n += __shfl_down(n, off, 64);
+      pair_add(sa, ca, sa2, ca2);
+      pair_add(sb, cb, sb2, cb2);
+    }
+    ra = make_double2(sa, ca);
+    rb = make_double2(sb, cb);
+    rc = n;
   }
 }
 
@@ -355,14 +391,15 @@ __device__ __forceinline__ void store_entries(T *__restrict__ r, int nep, int e,
 // the density (energy of the element added to (s, c), bad elements counted in cnt) and, by
 // MODE, the element forces |T| dW/dF grad phi_l (Section 6.2) or the per-element central
 // differences of |T| W under a perturbation of one row of F (Section 6.1), written as
-// vertex-major entries r[l][e] (nep = padded element count).
+// vertex-major entries r[(l nep + er) D + j].
 // geo: [DIM*DIM][ne] entries of B^-1 followed by [ne] sizes |T|; or, with CLS, a table of
 // records [DIM*DIM entries of B^-1, |T|] and cls = the element's class.
 template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
-__device__ __forceinline__ void element_pass(int e, int ne, int nep, const T (&uu)[DIM + 1][D],
+__device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 1][D],
                                              const T *__restrict__ geo, int cls,
-                                             T *__restrict__ r, const Params &prm, double &s,
-                                             double &c, int &cnt) {
+                                             T *__restrict__ r, int nep, int er,
+                                             const Params &prm, double &s, double &c,
+                                             int &cnt) {
   constexpr int K = DIM + 1;
   T Bi[DIM][DIM];
   T vol;
@@ -414,7 +451,7 @@ __device__ __forceinline__ void element_pass(int e, int ne, int nep, const T (&u
         out[l * D + j] = acc;
         out[j] -= acc;
       }
-    store_entries<T, D, K>(r, nep, e, out);
+    store_entries<T, D, K>(r, nep, er, out);
   }
   if constexpr (MODE == MODE_FD) {
     // Central differences of |T| W under v_n +- eps for every DOF n of this element: only
@@ -456,7 +493,7 @@ __device__ __forceinline__ void element_pass(int e, int ne, int nep, const T (&u
         out[l * D + j] = (T)((double)vol * (Wp - Wm) * inv2e);
       }
     }
-    store_entries<T, D, K>(r, nep, e, out);
+    store_entries<T, D, K>(r, nep, er, out);
   }
   if (bad) {
     cnt += 1;
@@ -468,152 +505,199 @@ __device__ __forceinline__ void element_pass(int e, int ne, int nep, const T (&u
   }
 }
 
-// One tile of the element pass: elements tile * kElemTile + k * kBlockElem + threadIdx.x,
-// k < kElemPerThread (each k a coalesced sweep of the block), summed into (s, c, cnt).
-// Latency hiding: the connectivity (and classes) of all of the thread's elements are loaded
-// up front, and the vertex values of element k + 1 are gathered while element k is
-// computed. Lanes past ne load the last element's indices and compute nothing.
-template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
-__device__ __forceinline__ void element_tile(int tile, int ne, int nep,
-                                             const int32_t *__restrict__ conn,
-                                             const T *__restrict__ geo,
-                                             const uint8_t *__restrict__ gcls,
-                                             const T *__restrict__ u, T *__restrict__ r,
-                                             const Params &prm, double &s, double &c,
-                                             int &cnt) {
-  constexpr int K = DIM + 1, E = kElemPerThread;
-  const int e0 = tile * kElemTile + threadIdx.x;
-  int nd[E][K], cl[E];
+// LDS of one element tile: the staged nodal values, the element results (vertex-major,
+// [dim+1][kTileElems][D]), the tile's local patch entries and the geometry class table.
+// 16-byte aligned: nodal values and patch entries move as 16-byte vectors.
+template <int DIM, int D, typename T, int MODE, bool CLS>
+struct alignas(16) TileShared {
+  static constexpr int K = DIM + 1, NS = NodeVec<T, D>::NS, REC = DIM * DIM + 1;
+  static constexpr int NENT = (K * kTileElems + kEntAlign - 1) / kEntAlign * kEntAlign;
+  T us[kTileNodes * NS];
+  T fs[MODE == MODE_ENERGY ? 4 : K * kTileElems * D];
+  uint16_t lent[MODE == MODE_ENERGY ? kEntAlign : NENT];
+  T tab[CLS ? kMaxGeoClasses * REC : 4];
+};
+
+// One element tile t of mesh M, by one workgroup of NT threads (kTileElems / NT elements and
+// kTileNodes / NT node records per thread):
+//  0. issue the loads that depend on nothing else: the local connectivity (and classes) of
+//     the thread's elements, its node records, and the tile's local patch entries (into LDS);
+//  1. stage the nodal field u (u = v - x for Neo-Hookean, u = v for the p-Laplacian) of the
+//     tile's nodes in LDS; the tile that meets a node first adds b.v of its free DOFs;
+//  2. element pass of the tile's elements, vertex values read from LDS, element results
+//     written to LDS; energies into (s, c);
+//  3. for each free node of the tile: its local patch row summed from LDS in ascending
+//     element order (Section 4.2 patch restricted to the tile); a node whose whole patch
+//     lies in the tile writes g = scale * (sum - b) in free-DOF order, the others write the
+//     sum to their halo slot;
+//  4. block sums (tile_reduce2): energy -> part[t], b.v -> part[ntiles + t], bad count.
+// Every order is fixed: the results do not depend on timing. No atomics.
+// geo: the global geometry arrays (or class table, staged in sh.tab when CLS).
+template <int DIM, int D, int KIND, typename T, int MODE, bool CLS, int NT, class SH>
+__device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__restrict__ geo,
+                                          const double *__restrict__ vhat,
+                                          double *__restrict__ g,
+                                          const double *__restrict__ scale, const Params &prm,
+                                          SH &sh) {
+  constexpr int K = DIM + 1, REC = DIM * DIM + 1;
+  constexpr int EPT = kTileElems / NT, NPT = kTileNodes / NT;
+  static_assert(EPT * NT == kTileElems && NPT * NT == kTileNodes, "tile split");
+  const int tid = threadIdx.x;
+  const int4 ta = M.ttile[t], tb = M.ttile[t + 1];
+  const int e0 = ta.x, net = tb.x - ta.x, r0 = ta.y, nloc = tb.y - ta.y;
+  // 0. independent loads; lanes past the tile's end read its last element
+  int nd[EPT][K], cl[EPT];
 #pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int e = min(e0 + k * kBlockElem, ne - 1);
+  for (int k = 0; k < EPT; ++k) {
+    const int e = e0 + min(k * NT + tid, net - 1);
 #pragma unroll
-    for (int l = 0; l < K; ++l) nd[k][l] = stream_load(conn + (int64_t)l * ne + e);
-    cl[k] = CLS ? (int)stream_load(gcls + e) : 0;
+    for (int l = 0; l < K; ++l) nd[k][l] = stream_load(M.conn_loc + (int64_t)l * M.ne + e);
+    cl[k] = CLS ? (int)stream_load(M.geo_cls + e) : 0;
   }
-  T ua[K][D], ub[K][D];
+  int4 rec[NPT];
 #pragma unroll
-  for (int l = 0; l < K; ++l) NodeVec<T, D>::load(u, nd[0][l], ua[l]);
+  for (int k = 0; k < NPT; ++k) {
+    const int a = k * NT + tid;
+    rec[k] = a < nloc ? M.trec[r0 + a] : make_int4(0, 0, 0, 0);
+  }
+  if constexpr (MODE != MODE_ENERGY) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(M.tlent + ta.z);
+    uint4 *dst = reinterpret_cast<uint4 *>(sh.lent);
+    for (int q = tid; q < (tb.z - ta.z) / kEntAlign; q += NT) dst[q] = src[q];
+  }
+  if constexpr (CLS)
+    for (int q = tid; q < M.nclass * REC; q += NT) sh.tab[q] = geo[q];
+  // 1. nodal field of the tile; b.v of the nodes this tile owns
+  double sb = 0.0, cb = 0.0;
 #pragma unroll
-  for (int k = 0; k < E; ++k) {
-    if (k + 1 < E) {
+  for (int k = 0; k < NPT; ++k) {
+    const int a = k * NT + tid;
+    if (a < nloc) {
+      const int gi = rec[k].x, mask = rec[k].y & 7;
+      const bool owner = (rec[k].z >> 1) & 1;
+      int fb = rec[k].y >> 3;
+      T o[D];
 #pragma unroll
-      for (int l = 0; l < K; ++l) NodeVec<T, D>::load(u, nd[k + 1][l], ub[l]);
-    }
-    const int e = e0 + k * kBlockElem;
-    if (e < ne)
-      element_pass<DIM, D, KIND, T, MODE, CLS>(e, ne, nep, ua, geo, cl[k], r, prm, s, c, cnt);
-    if (k + 1 < E) {
-#pragma unroll
-      for (int l = 0; l < K; ++l)
-#pragma unroll
-        for (int j = 0; j < D; ++j) ua[l][j] = ub[l][j];
+      for (int j = 0; j < D; ++j) {
+        const double w = M.wref[(int64_t)gi * D + j];
+        double val = w;
+        if ((mask >> j) & 1) {
+          const double vj = vhat[fb];
+          val = vj - w;
+          if (owner) {
+            double t2, err;
+            two_sum(sb, M.bhat[fb] * vj, t2, err);
+            sb = t2;
+            cb += err;
+          }
+          ++fb;
+        }
+        o[j] = (T)val;
+      }
+      NodeVec<T, D>::store(sh.us, a, o);
     }
   }
+  __syncthreads();
+  // 2. elements
+  double s = 0.0, c = 0.0;
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int le = k * NT + tid;
+    if (le < net) {
+      T uu[K][D];
+#pragma unroll
+      for (int l = 0; l < K; ++l) NodeVec<T, D>::load(sh.us, nd[k][l], uu[l]);
+      if constexpr (CLS)
+        element_pass<DIM, D, KIND, T, MODE, true>(e0 + le, M.ne, uu, sh.tab, cl[k], sh.fs,
+                                                  kTileElems, le, prm, s, c, cnt);
+      else
+        element_pass<DIM, D, KIND, T, MODE, false>(e0 + le, M.ne, uu, geo, 0, sh.fs,
+                                                   kTileElems, le, prm, s, c, cnt);
+    }
+  }
+  // 3. patch sums of the tile's free nodes
+  if constexpr (MODE != MODE_ENERGY) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int w = rec[k].w;
+      if (w == 0) continue;  // no free DOF, or past the tile's nodes
+      double acc[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc[j] = 0.0;
+      // entries in rounds of 4 whose LDS reads are issued together; the sum stays sequential
+      // in ascending element order (absent slots re-read the last entry and add zero)
+      const int p0 = w & 0xffff, n = w >> 16;
+      for (int p = 0; p < n; p += 4) {
+        int x[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ok[u] = p + u < n;
+          x[u] = sh.lent[p0 + (ok[u] ? p + u : n - 1)];
+        }
+        T q[4][D];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int j = 0; j < D; ++j) q[u][j] = sh.fs[((x[u] & 3) * kTileElems + (x[u] >> 2)) * D + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int j = 0; j < D; ++j) acc[j] += ok[u] ? (double)q[u][j] : 0.0;
+      }
+      const int z = rec[k].z, mask = rec[k].y & 7;
+      int f = rec[k].y >> 3;
+      if (z & 1) {
+        const double sc = scale ? *scale : 1.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+          if ((mask >> j) & 1) {
+            g[f] = sc * (acc[j] - M.bhat[f]);
+            ++f;
+          }
+      } else {
+        double *hp = M.hpart + (int64_t)(z >> 2) * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) hp[j] = acc[j];
+      }
+    }
+  }
+  // 4. partials
+  double2 rj, rb;
+  int rc;
+  tile_reduce2<NT>(s + c, sb + cb, cnt, rj, rb, rc);
+  if (tid == 0) {
+    M.part[t] = rj;
+    M.part[M.ntiles + t] = rb;
+    M.badp[t] = rc;
+  }
+  __syncthreads();  // a persistent caller reuses the LDS for its next tile
 }
 
-// The node prepass for node i (caller's order): the nodal field of v (u = v - x when
-// SUB_X) stored at the node's internal position, and b.v of its free DOFs added to (s, c).
-template <typename T, int D, bool SUB_X>
-__device__ __forceinline__ void prepass_node(int i, const int32_t *__restrict__ node_info,
-                                             const int32_t *__restrict__ node_int,
-                                             const double *__restrict__ vhat,
-                                             const double *__restrict__ vD,
-                                             const double *__restrict__ xref,
-                                             const double *__restrict__ bhat,
-                                             T *__restrict__ u, double &s, double &c) {
-  const int info = node_info[i];
-  const int mask = info & 7;
-  int fb = info >> 3;
-  T o[D];
+// Halo row h: a free node whose patch spans several tiles (or none) sums its slots (one per
+// tile, ascending tile order) and writes g = scale * (sum - b).
+template <int D>
+__device__ __forceinline__ void halo_row(const TileMesh &M, int h, double *__restrict__ g,
+                                         const double *__restrict__ scale) {
+  const int4 hr = M.hrec[h];
+  double acc[D];
 #pragma unroll
-  for (int j = 0; j < D; ++j) {
-    double val;
+  for (int j = 0; j < D; ++j) acc[j] = 0.0;
+  const double *hp = M.hpart + (int64_t)hr.x * D;
+  for (int q = 0; q < hr.y; ++q)
+#pragma unroll
+    for (int j = 0; j < D; ++j) acc[j] += hp[q * D + j];
+  const int mask = hr.z & 7;
+  int f = hr.z >> 3;
+  const double sc = scale ? *scale : 1.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j)
     if ((mask >> j) & 1) {
-      val = vhat[fb];
-      double prod = bhat[fb] * val, t, e;
-      two_sum(s, prod, t, e);
-      s = t;
-      c += e;
-      ++fb;
-    } else {
-      val = vD[(int64_t)i * D + j];
+      g[f] = sc * (acc[j] - M.bhat[f]);
+      ++f;
     }
-    if constexpr (SUB_X) val -= xref[(int64_t)i * D + j];
-    o[j] = (T)val;
-  }
-  NodeVec<T, D>::store(u, node_int[i], o);
-}
-
-// GL lanes per free node: the lanes of a group stride over the node's patch entries (U
-// entries per lane per round, their loads issued together), then combine their sums by a
-// butterfly over the group (every lane ends with the same sum, as FP addition is
-// commutative), and the group's first lane writes g = scale * (sum - b) in free-DOF order
-// (scale: optional device scalar, the incoming gradient of a differentiation hook). Fixed
-// order of operations: deterministic. No atomics. Every lane of the wave must call this
-// (row >= nf for idle lanes).
-template <int K, int D, typename T, int GL, int U>
-__device__ __forceinline__ void gather_row(int row, int sub, int nf, int nep,
-                                           const int32_t *__restrict__ row_ptr,
-                                           const uint32_t *__restrict__ ent,
-                                           const int32_t *__restrict__ row_info,
-                                           const T *__restrict__ r,
-                                           const double *__restrict__ bhat,
-                                           const double *__restrict__ scale,
-                                           double *__restrict__ g) {
-  double acc[D], bv[D];
-  int fb0 = 0, mask = 0;
-#pragma unroll
-  for (int j = 0; j < D; ++j) acc[j] = bv[j] = 0.0;
-  if (row < nf) {
-    const int t0 = row_ptr[row], t1 = row_ptr[row + 1];
-    // the row's DOF map and load vector do not depend on the entries: fetch them first so
-    // their latency overlaps the entry loads
-    if (sub == 0) {
-      const int info = row_info[row];
-      mask = info & 7;
-      fb0 = info >> 3;
-      int fb = fb0;
-#pragma unroll
-      for (int j = 0; j < D; ++j)
-        if ((mask >> j) & 1) bv[j] = bhat[fb++];
-    }
-    for (int base = t0 + sub; base < t1; base += GL * U) {
-      // branch-free round: out-of-row slots load the row's last entry and add zero, so
-      // all U loads of the round are in flight together
-      uint32_t x[U];
-      bool ok[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int t = base + u * GL;
-        ok[u] = t < t1;
-        x[u] = stream_load(ent + (ok[u] ? t : t1 - 1));
-      }
-      Entry<T, D> q[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        q[u] = *reinterpret_cast<const Entry<T, D> *>(
-            r + ((int64_t)(x[u] & 3) * nep + (x[u] >> 2)) * D);
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int j = 0; j < D; ++j) acc[j] += ok[u] ? (double)q[u].v[j] : 0.0;
-    }
-  }
-#pragma unroll
-  for (int off = GL / 2; off > 0; off >>= 1)
-#pragma unroll
-    for (int j = 0; j < D; ++j) acc[j] += __shfl_xor(acc[j], off, 64);
-  if (row < nf && sub == 0) {
-    const double sc = scale ? *scale : 1.0;
-    int fb = fb0;
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-      if ((mask >> j) & 1) {
-        g[fb] = sc * (acc[j] - bv[j]);
-        ++fb;
-      }
-  }
 }
 
 }  // namespace dev

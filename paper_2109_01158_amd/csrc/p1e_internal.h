@@ -1,5 +1,6 @@
 // p1e_internal.h -- mesh handle layout and kernel launchers shared by the host setup
-// (p1e_api.cpp) and the gfx950 kernels (p1e_kernels.hip). Not part of the public ABI.
+// (p1e_api.cpp, p1e_tiles.cpp), the single-mesh kernels (p1e_kernels.hip) and the batched
+// engine (p1e_batch.hip, p1e_serve.cpp). Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,41 +13,53 @@
 
 namespace p1e {
 
-constexpr int kBlock = 256;        // threads per block of the patch gather
-constexpr int kBlockElem = 512;    // threads per block of the element kernel
-#ifndef P1E_ELEM_PER_THREAD
-#define P1E_ELEM_PER_THREAD 4
-#endif
-constexpr int kElemPerThread = P1E_ELEM_PER_THREAD;    // elements per thread (one tile)
-constexpr int kElemTile = kBlockElem * kElemPerThread;  // elements per element-kernel tile
-constexpr int kBlockNode = 1024;   // threads (= nodes) per block of the node prepass
+// Element tiles: one workgroup evaluates one tile of consecutive (internal) elements. The
+// tile's nodal values and patch entries are staged in LDS, its element forces are written
+// to LDS, and each of its nodes sums its share of the patch from LDS (Section 4.2 patches
+// split by tile).
+constexpr int kTileElems = 1024;   // elements per tile (at most)
+constexpr int kTileNodes = 1024;   // distinct nodes per tile (at most)
+constexpr int kEntAlign = 8;       // each tile's patch entries start on a 16-byte boundary
+constexpr int kBlock = 256;        // threads per block of the halo-row and vector kernels
 constexpr uint64_t kAlign = 256;   // alignment of every sub-array in the bound buffer
-constexpr int kMaxGeoClasses = 256; // geometry classes kept as one-byte indices
+constexpr int kMaxGeoClasses = 64; // geometry classes kept as one-byte indices
 
-// Device view of a bound mesh. All arrays live in the caller's buffer.
-struct DevMesh {
-  // node arrays in the caller's (external) node order
-  const int32_t *node_info = nullptr;  // [nn]  (first free DOF << 3) | free-component mask
-  const int32_t *node_int = nullptr;   // [nn]  internal number of each node
-  const double *xref = nullptr;        // [nn][dim] reference coordinates (Neo-Hookean)
-  const double *vD = nullptr;          // [nn][d] prescribed values
-  // element and patch arrays in internal (locality) order
-  const double *bhat = nullptr;        // [n_free_dofs] b = M f on the free DOFs
-  const int32_t *conn = nullptr;       // [dim+1][ne] structure of arrays
+// Device view of a bound mesh (all arrays in the caller's buffer). Internal numbering: the
+// elements in tile order, the nodes in order of first use by the elements.
+//
+// Tile node record (int4), one per node of a tile, in ascending internal node:
+//   x = internal node, y = (first free DOF << 3) | free-component mask,
+//   z = (halo slot << 2) | owner << 1 | complete   (complete: the node's whole patch lies in
+//       the tile; owner: this is the first tile of the node, which adds its b.v),
+//   w = first local patch entry | entry count << 16.
+// Halo row record (int4), one per free node whose patch spans several tiles (or no
+// element): x = first slot, y = slot count, z = (first free DOF << 3) | mask.
+struct TileMesh {
+  int32_t nn = 0, ne = 0, nfd = 0;
+  int32_t ntiles = 0, nhalo = 0;
+  const double *wref = nullptr;  // [nn][d] per component: free -> subtrahend (x for
+                                 // Neo-Hookean, 0 for the p-Laplacian), prescribed -> u
+  const double *bhat = nullptr;  // [nfd] b = M f on the free DOFs
+  // elements (internal order)
+  const uint16_t *conn_loc = nullptr;  // [dim+1][ne] vertex -> node index within the tile
   // element geometry: B^-1 entries (row l-1 = grad phi_l) and |T|, either per element as
   // [dim*dim+1][ne], or (geometry classes) as a table [nclass][dim*dim+1] indexed by geo_cls
-  const double *geo64 = nullptr;       // FP64
-  const float *geo32 = nullptr;        // FP32 (mixed mode)
-  const uint8_t *geo_cls = nullptr;    // [ne] class of each element, or nullptr
-  int nclass = 0;
-  const int32_t *row_ptr = nullptr;    // [nf+1] patch rows of free nodes
-  const uint32_t *ent = nullptr;       // [nnz] (element << 2) | local vertex, ascending element
-  const int32_t *row_info = nullptr;   // [nf] node_info of each free node
-  void *u = nullptr;                   // scratch: nodal field [nn][ns] in internal node order,
-                                       // ns = 4 if d == 3 else d
-  void *r = nullptr;                   // scratch: per-element forces / differences [(dim+1)d][ne]
-  double2 *part = nullptr;             // scratch: compensated block partials
-  int32_t *badp = nullptr;             // scratch: bad-element counts per block
+  const double *geo64 = nullptr;    // FP64
+  const float *geo32 = nullptr;     // FP32 (mixed mode)
+  const uint8_t *geo_cls = nullptr; // [ne] class of each element, or nullptr
+  int32_t nclass = 0;
+  // tiles
+  const int4 *ttile = nullptr;  // [ntiles+1] {first element, first node record, first patch
+                                //  entry, 0}; the last one closes the ranges
+  const int4 *trec = nullptr;   // [sum nloc] tile node records
+  const uint16_t *tlent = nullptr;  // local patch entries (element << 2 | l), per node
+                                    // ascending element
+  const int4 *hrec = nullptr;   // [nhalo] halo row records
+  // scratch
+  double *hpart = nullptr;   // [slots][d] partial patch sums of halo rows, by row
+  double *gw = nullptr;      // [nfd] gradient kept by p1e_energy_forces
+  double2 *part = nullptr;   // [2][max(ntiles,1)] compensated partials: energy, then b.v
+  int32_t *badp = nullptr;   // [max(ntiles,1)] bad-element counts
 };
 
 }  // namespace p1e
@@ -59,26 +72,25 @@ struct p1e_mesh {
   double total_vol = 0.0, min_vol = 0.0, max_vol = 0.0, dirichlet_bv = 0.0;
 
   // host copies (kept so the mesh can be bound again)
-  std::vector<int32_t> conn;       // [k][ne]
   std::vector<double> geo64;       // [dim*dim+1][ne] (empty when classed)
   int nclass = 0;                  // distinct element geometries when <= kMaxGeoClasses, else 0
   std::vector<uint8_t> geo_cls;    // [ne] class of each element
   std::vector<double> geo_tab;     // [nclass][dim*dim+1]
-  std::vector<int32_t> node_info;  // [nn] external order
-  std::vector<int32_t> node_int;   // [nn] external -> internal node number
-  std::vector<double> xref;        // [nn][dim] (Neo-Hookean only)
-  std::vector<double> vD;          // [nn][d]
+  std::vector<int32_t> ninfo;      // [nn] internal order
+  std::vector<double> wref;        // [nn][d] internal order
   std::vector<double> bhat;        // [nfd]
-  std::vector<int32_t> row_ptr;    // [nf+1]
-  std::vector<uint32_t> ent;       // [nnz]
-  std::vector<int32_t> row_info;   // [nf]
+  std::vector<uint16_t> conn_loc;  // [k][ne]
+  std::vector<int32_t> ttile;      // [ntiles+1][4]
+  std::vector<int32_t> trec;       // [sum nloc][4]
+  std::vector<uint16_t> tlent;
+  std::vector<int32_t> hrec;       // [nhalo][4]
+  int64_t ntiles = 0, nhalo = 0, nslots = 0, ntnodes = 0;
 
   // binding
   int bound_modes = 0;
   int device = -1;
-  p1e::DevMesh dev;
-  int64_t part_cap = 0;  // number of double2 partial slots
-  int forces_prec = 0;   // precision of the element forces held in scratch (0 = none)
+  p1e::TileMesh dev;
+  int forces_prec = 0;   // precision of the gradient held in dev.gw (0 = none)
 };
 
 namespace p1e {
@@ -90,17 +102,10 @@ int fail(int code, const std::string &msg);
 void prof_begin(const char *name, hipStream_t s);
 void prof_end(hipStream_t s);
 
-// number of blocks of the streaming kernels over n items
 inline int64_t nblocks(int64_t n, int per = kBlock) { return (n + per - 1) / per; }
-inline int64_t element_blocks(int64_t ne) { return nblocks(ne, kElemTile); }
-inline int64_t node_blocks(int64_t nn) { return nblocks(nn, kBlockNode); }
-// per-element scratch is padded to whole element blocks
-inline int64_t padded_elements(int64_t ne) { return element_blocks(ne) * kElemTile; }
 
-// device bytes of each scratch array for the given mode mask
-uint64_t u_bytes(const p1e_mesh *m, int modes);
-uint64_t r_bytes(const p1e_mesh *m, int modes);
-int64_t part_slots(const p1e_mesh *m);
+// host setup of the element tiles, node order and halo rows (p1e_tiles.cpp)
+int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn);
 
 // launchers (p1e_kernels.hip). All enqueue on stream and return P1E_OK or a status.
 int run_energy(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
@@ -111,7 +116,7 @@ int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t 
                 hipStream_t s);
 int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
                       hipStream_t s);
-int run_gather(p1e_mesh *m, int prec, const double *scale, double *g, hipStream_t s);
+int run_scale(p1e_mesh *m, const double *scale, double *g, hipStream_t s);
 
 }  // namespace p1e
 
@@ -144,30 +149,19 @@ enum ElemClass { CLS_PLAP2 = 0, CLS_PLAP3, CLS_NH2, CLS_NH3, kNumClasses };
 
 // one slot as the batched kernels see it
 struct SlotDev {
-  // mesh (layout of p1e_mesh_bind inside the slot's allocation)
-  const int32_t *node_info, *node_int;
-  const double *xref, *vD, *bhat;
-  const int32_t *conn;
-  const void *geo;  // double or float by engine precision (class table when gcls is set)
-  const uint8_t *gcls;
-  const int32_t *row_ptr;
-  const uint32_t *ent;
-  const int32_t *row_info;
-  void *u, *r;
-  double2 *part;   // [ntile_e] element partials, then [ntile_n] node partials
-  int32_t *badp;   // [ntile_e]
+  TileMesh M;      // the slot's mesh (layout of p1e_mesh_bind inside the slot's allocation)
   double2 *vpart;  // [ntile_v][4] vector-reduction partials
-  int32_t nn, ne, nep, nf, nfd, ntile_e, ntile_n, ntile_v;
+  int32_t ntile_h, ntile_v;
   double C1, D1, p, dirichlet_bv;
   // L-BFGS vectors, nfd doubles each; S and Y hold kMaxHistory vectors each
   double *v, *g, *d, *vt, *gt, *S, *Y;
 };
 
-// tile tables: (slot, tile) pairs; element, node and row tiles grouped by class
-enum TileKind { TK_ELEM = 0, TK_NODE = 1, TK_ROW = 2 };
+// tile tables: (slot, tile) pairs; element tiles and halo-row tiles grouped by class
+enum TileKind { TK_TILE = 0, TK_HALO = 1, kNumTileKinds = 2 };
 // counts[] layout: for kind k and class c, offset at 2*(k*kNumClasses + c), count next to it;
 // the number of vector tiles at kCountVec
-constexpr int kCountVec = 2 * 3 * kNumClasses;
+constexpr int kCountVec = 2 * kNumTileKinds * kNumClasses;
 constexpr int kNumCounts = kCountVec + 1;
 
 // device tables of an engine (all in the table area of its workspace)
@@ -175,7 +169,7 @@ struct EngineDev {
   SlotDev *slots;   // [max_slots]
   double *sc;       // [max_slots][kNSc]
   int32_t *st;      // [max_slots][kNSt]
-  int2 *map[3];     // element, node, row tiles
+  int2 *map[kNumTileKinds];  // element tiles, halo-row tiles
   int2 *vmap;       // vector tiles over all slots
   int32_t *counts;  // [kNumCounts]
   int32_t max_slots, history;
@@ -184,7 +178,5 @@ struct EngineDev {
 
 // enqueue one engine step on stream s (p1e_batch.hip)
 int batch_step(const EngineDev &E, hipStream_t s);
-// rows per patch-row tile for a class (matches the gather's lanes per row)
-int rows_per_tile(int cls);
 
 }  // namespace p1e

@@ -56,34 +56,34 @@ uint64_t state_bytes(const p1e_mesh *m, int history) {
   return aup(5 * n * 8) + aup(2ull * history * n * 8) + aup(ntv * 4 * 16);
 }
 
-// capacities of the tile tables for a workspace of pool_bytes (each tile needs at least
-// this many bytes of slot data, plus one partial tile per slot)
+// capacities of the tile tables for a workspace of pool_bytes: every element tile but a
+// mesh's last holds at least 12 KiB of slot data (1024 elements or 1024 nodes), every
+// halo-row tile (kBlock rows) at least 32 KiB (gradient, load and L-BFGS vectors per row);
+// plus one partial tile per slot
 struct TableCaps {
-  int64_t slots, elem, node, row, vec;
+  int64_t slots, tile, halo, vec;
 };
 TableCaps table_caps(int max_slots, uint64_t pool_bytes) {
   TableCaps c;
   c.slots = max_slots;
-  c.elem = (int64_t)(pool_bytes / (kElemTile * 40)) + 2 * max_slots;
-  c.node = (int64_t)(pool_bytes / (kBlockNode * 16)) + 2 * max_slots;
-  c.row = (int64_t)(pool_bytes / (32 * 64)) + 2 * max_slots;
+  c.tile = (int64_t)(pool_bytes / 12288) + 2 * max_slots;
+  c.halo = (int64_t)(pool_bytes / 32768) + 2 * max_slots;
   c.vec = (int64_t)(pool_bytes / (kVecTile * 64)) + 2 * max_slots;
   return c;
 }
+int64_t halo_tiles(const p1e_mesh *m) { return (m->nhalo + kBlock - 1) / kBlock; }
 // exact capacities for one slot holding mesh m
 TableCaps table_caps_for(const p1e_mesh *m) {
   TableCaps c;
   c.slots = 1;
-  c.elem = element_blocks(m->ne) + 1;
-  c.node = node_blocks(m->nn) + 1;
-  c.row = (m->nf + 31) / 32 + 1;
+  c.tile = m->ntiles + 1;
+  c.halo = halo_tiles(m) + 1;
   c.vec = (std::max<int64_t>(m->nfd, 1) + kVecTile - 1) / kVecTile + 1;
   return c;
 }
 uint64_t table_bytes(const TableCaps &c) {
   return aup(sizeof(SlotDev) * c.slots) + aup(8ull * kNSc * c.slots) + aup(4ull * kNSt * c.slots) +
-         aup(8ull * c.elem) + aup(8ull * c.node) + aup(8ull * c.row) + aup(8ull * c.vec) +
-         aup(4ull * kNumCounts);
+         aup(8ull * c.tile) + aup(8ull * c.halo) + aup(8ull * c.vec) + aup(4ull * kNumCounts);
 }
 
 // ---------------------------------------------------------------------------- engine
@@ -119,9 +119,8 @@ struct Engine {
     E.slots = (SlotDev *)take(sizeof(SlotDev) * max_slots);
     E.sc = (double *)take(8ull * kNSc * max_slots);
     E.st = (int32_t *)take(4ull * kNSt * max_slots);
-    E.map[TK_ELEM] = (int2 *)take(8ull * caps.elem);
-    E.map[TK_NODE] = (int2 *)take(8ull * caps.node);
-    E.map[TK_ROW] = (int2 *)take(8ull * caps.row);
+    E.map[TK_TILE] = (int2 *)take(8ull * caps.tile);
+    E.map[TK_HALO] = (int2 *)take(8ull * caps.halo);
     E.vmap = (int2 *)take(8ull * caps.vec);
     E.counts = (int32_t *)take(4ull * kNumCounts);
     E.max_slots = max_slots;
@@ -161,29 +160,8 @@ struct Engine {
     const int64_t n = m->nfd;
     const uint64_t n1 = (uint64_t)std::max<int64_t>(n, 1);
     SlotDev S{};
-    const DevMesh &D = m->dev;
-    S.node_info = D.node_info;
-    S.node_int = D.node_int;
-    S.xref = D.xref;
-    S.vD = D.vD;
-    S.bhat = D.bhat;
-    S.conn = D.conn;
-    S.geo = E.prec == P1E_MIXED ? (const void *)D.geo32 : (const void *)D.geo64;
-    S.gcls = D.geo_cls;
-    S.row_ptr = D.row_ptr;
-    S.ent = D.ent;
-    S.row_info = D.row_info;
-    S.u = D.u;
-    S.r = D.r;
-    S.part = D.part;
-    S.badp = D.badp;
-    S.nn = (int)m->nn;
-    S.ne = (int)m->ne;
-    S.nep = (int)padded_elements(m->ne);
-    S.nf = (int)m->nf;
-    S.nfd = (int)n;
-    S.ntile_e = (int)element_blocks(m->ne);
-    S.ntile_n = (int)node_blocks(m->nn);
+    S.M = m->dev;
+    S.ntile_h = (int)halo_tiles(m);
     S.ntile_v = (int)((n + kVecTile - 1) / kVecTile);
     S.C1 = m->C1;
     S.D1 = m->D1;
@@ -245,18 +223,16 @@ struct Engine {
   // rebuild and upload the tile tables of the occupied slots
   int upload_tables() {
     if (!tables_dirty) return P1E_OK;
-    std::vector<int2> maps[3];
+    std::vector<int2> maps[kNumTileKinds];
     std::vector<int2> vmap;
     std::vector<int32_t> counts(kNumCounts, 0);
-    for (int kind = 0; kind < 3; ++kind)
+    for (int kind = 0; kind < kNumTileKinds; ++kind)
       for (int c = 0; c < kNumClasses; ++c) {
         counts[2 * (kind * kNumClasses + c)] = (int32_t)maps[kind].size();
         for (int k = 0; k < E.max_slots; ++k) {
           if (cls_h[k] != c) continue;
           const SlotDev &S = slots_h[k];
-          int n = kind == TK_ELEM ? S.ntile_e
-                  : kind == TK_NODE ? S.ntile_n
-                                    : (S.nf + rows_per_tile(c) - 1) / rows_per_tile(c);
+          const int n = kind == TK_TILE ? S.M.ntiles : S.ntile_h;
           for (int t = 0; t < n; ++t) maps[kind].push_back(make_int2(k, t));
         }
         counts[2 * (kind * kNumClasses + c) + 1] =
@@ -266,12 +242,12 @@ struct Engine {
       if (cls_h[k] >= 0)
         for (int t = 0; t < slots_h[k].ntile_v; ++t) vmap.push_back(make_int2(k, t));
     counts[kCountVec] = (int32_t)vmap.size();
-    if ((int64_t)maps[TK_ELEM].size() > caps.elem || (int64_t)maps[TK_NODE].size() > caps.node ||
-        (int64_t)maps[TK_ROW].size() > caps.row || (int64_t)vmap.size() > caps.vec)
+    if ((int64_t)maps[TK_TILE].size() > caps.tile || (int64_t)maps[TK_HALO].size() > caps.halo ||
+        (int64_t)vmap.size() > caps.vec)
       return fail(P1E_ENOMEM, "tile tables over capacity");
     bool ok = hipMemcpyAsync(E.slots, slots_h.data(), sizeof(SlotDev) * E.max_slots,
                              hipMemcpyHostToDevice, stream) == hipSuccess;
-    for (int kind = 0; kind < 3; ++kind)
+    for (int kind = 0; kind < kNumTileKinds; ++kind)
       if (!maps[kind].empty())
         ok = ok && hipMemcpyAsync(E.map[kind], maps[kind].data(), 8ull * maps[kind].size(),
                                   hipMemcpyHostToDevice, stream) == hipSuccess;
@@ -417,12 +393,13 @@ struct p1e_server {
         if (r->vhat0.empty()) {  // default start: prescribed values and v = x (Neo-Hookean) or 0
           r->vhat0.assign(r->mesh->nfd, 0.0);
           if (r->mesh->kind == P1E_NEOHOOKE) {
+            // the free components of node i keep x in wref (internal order)
             for (int64_t i = 0; i < r->mesh->nn; ++i) {
-              int info = r->mesh->node_info[i];
+              int info = r->mesh->ninfo[i];
               int mask = info & 7;
               int64_t fb = info >> 3;
               for (int j = 0; j < r->mesh->d; ++j)
-                if (mask >> j & 1) r->vhat0[fb++] = r->mesh->xref[i * r->mesh->dim + j];
+                if (mask >> j & 1) r->vhat0[fb++] = r->mesh->wref[i * r->mesh->d + j];
             }
           }
         }
@@ -729,7 +706,7 @@ int p1e_minimize(p1e_mesh *m, double *vhat, const p1e_lbfgs_opts *o, void *ws, u
     E.release();
     return rc;
   }
-  m->forces_prec = 0;  // the engine overwrites the mesh's force scratch
+  m->forces_prec = 0;  // the engine overwrites the mesh's scratch arrays
   rc = E.attach(0, m, (char *)ws + tb, vhat, nullptr, o->max_iters);
   int64_t steps = 0;
   const int64_t max_steps = (int64_t)(o->max_iters + 1) * (kMaxLineTrials + 1) + 1;

@@ -91,8 +91,8 @@ def _mix():
     ]
 
 
-def _serve(P, probs, iters, max_slots, pool_mb=256, use_graph=True):
-    srv = P.Server(pool_mb << 20, max_slots=max_slots, history=5, max_iters=iters, prec="fp64",
+def _serve(P, probs, iters, max_slots, pool_bytes=256 << 20, use_graph=True):
+    srv = P.Server(pool_bytes, max_slots=max_slots, history=5, max_iters=iters, prec="fp64",
                    use_graph=use_graph, setup_threads=4)
     ids = [srv.submit(p, vhat0=p.vhat()) for p in probs]
     out, peak = {}, 0
@@ -135,9 +135,11 @@ def test_server_memory_admission(P):
     full, _ = _serve(P, probs, iters, max_slots=8)
     biggest = max(r["device_bytes"] for r, _ in full)
     total = sum(r["device_bytes"] for r, _ in full)
-    # a pool that holds the largest request but only about half of all of them at once
-    pool_mb = int(max(1.05 * biggest, 0.5 * total) * 1.02) // (1 << 20) + 1
-    tight, peak = _serve(P, probs, iters, max_slots=8, pool_mb=pool_mb)
+    # a pool whose data part holds the largest request but only about half of all of them
+    # at once (the engine tables sit at the head of the pool)
+    data = int(max(1.05 * biggest, 0.5 * total))
+    pool = data + int(P.lib().p1e_server_table_bytes(8, data * 2))
+    tight, peak = _serve(P, probs, iters, max_slots=8, pool_bytes=pool)
     assert peak < len(probs)
     for (a, va), (b, vb) in zip(full, tight):
         assert a["J"] == b["J"] and np.array_equal(va, vb)

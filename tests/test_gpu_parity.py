@@ -244,7 +244,7 @@ def test_internal_order_does_not_change_results(P, oracle_mod):
     prob = S.neohooke_box_3d(14, 6, 5, 1.0, 6 / 14, 5 / 14, seed=11)
     v = torch.tensor(prob.vhat(), device="cuda")
     outs = []
-    for flags in (0, P.P1E_LOCALITY_ORDER):
+    for flags in (0, P.P1E_INPUT_ORDER):
         m = P.Mesh.from_problem(prob, modes=P.P1E_FP64 | P.P1E_FD, flags=flags)
         g, o, _ = m.grad_exact(v, "fp64")
         f, _ = m.grad_patch_fd(v, 1e-6)
