@@ -48,7 +48,10 @@ __device__ __forceinline__ const int2 *tiles(const EngineDev &E, int &count) {
 // ----------------------------------------------------------------------- evaluation
 // element tiles of every evaluating slot of class C (persistent grid over the tile table)
 template <typename T>
-constexpr int batch_tile_threads() { return sizeof(T) == 4 ? 1024 : 512; }
+constexpr int batch_tile_threads() {
+  return sizeof(T) == 4 ? (kTileElems < 1024 ? kTileElems : 1024)
+                        : (kTileElems < 512 ? kTileElems : 512);
+}
 
 template <int DIM, int D, int KIND, typename T, int C>
 __global__ __launch_bounds__((batch_tile_threads<T>())) void kb_tile(EngineDev E) {

@@ -83,49 +83,31 @@ __device__ __forceinline__ void block_reduce(double &s, double &c, int &cnt) {
   }
 }
 
-// Block sums of two per-thread values and a count, for the element tiles, where each thread
-// holds one or two elements' worth: a plain FP64 tree within each 64-wide wavefront (an
-// error of at most 6 ulps of the wavefront's sum of magnitudes), then compensated (TwoSum)
-// sums of the per-wavefront results by the first wavefront. Fixed shuffle and LDS order:
-// the result does not depend on timing. Thread 0 gets (ra, rb, rc).
-template <int NT>
-__device__ __forceinline__ void tile_reduce2(double a, double b, int cnt, double2 &ra,
-                                             double2 &rb, int &rc) {
-  constexpr int NW = NT / 64;
-  __shared__ double sh_a[NW], sh_b[NW];
-  __shared__ int sh_n[NW];
+// Sum of a double over one 64-wide wavefront by a butterfly: every lane gets the same plain
+// FP64 tree sum (at most 6 ulps of the wavefront's sum of magnitudes; fixed order).
+__device__ __forceinline__ double wave_sum(double a) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double a2 = __shfl_xor(a, off, 64);
-    const double b2 = __shfl_xor(b, off, 64);
-    a += a2;
-    b += b2;
-  }
-  if (__any(cnt != 0))  // bad elements are rare: wave-uniform test
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    sh_a[wave] = a;
-    sh_b[wave] = b;
-    sh_n[wave] = cnt;
-  }
-  __syncthreads();
-  if (wave == 0) {
-    double sa = lane < NW ? sh_a[lane] : 0.0, ca = 0.0;
-    double sb = lane < NW ? sh_b[lane] : 0.0, cb = 0.0;
-    int n = lane < NW ? sh_n[lane] : 0;
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  return a;
+}
+__device__ __forceinline__ int wave_count(int n) {
+  if (__any(n != 0))  // counts are rare (bad elements): wave-uniform test
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+  return n;
+}
+
+// Compensated (TwoSum) sum of NW per-wavefront values v[0..NW) by the lanes of one wavefront;
+// lane 0 gets the (sum, correction) pair.
+template <int NW>
+__device__ __forceinline__ double2 waves_combine(const double *v) {
+  const int lane = threadIdx.x & 63;
+  double s = lane < NW ? v[lane] : 0.0, c = 0.0;
 #pragma unroll
-    for (int off = NW / 2; off > 0; off >>= 1) {
-      const double sa2 = __shfl_down(sa, off, 64), ca2 = __shfl_down(ca, off, 64);
-      const double sb2 = __shfl_down(sb, off, 64), cb2 = __shfl_down(cb, off, 64);
-      n += __shfl_down(n, off, 64);
-      pair_add(sa, ca, sa2, ca2);
-      pair_add(sb, cb, sb2, cb2);
-    }
-    ra = make_double2(sa, ca);
-    rb = make_double2(sb, cb);
-    rc = n;
+  for (int off = NW / 2; off > 0; off >>= 1) {
+    const double s2 = __shfl_down(s, off, 64), c2 = __shfl_down(c, off, 64);
+    pair_add(s, c, s2, c2);
   }
+  return make_double2(s, c);
 }
 
 // The dispatcher hands consecutive workgroups to the 8 XCDs in turn, and each XCD has its
@@ -513,10 +495,75 @@ struct alignas(16) TileShared {
   static constexpr int K = DIM + 1, NS = NodeVec<T, D>::NS, REC = DIM * DIM + 1;
   static constexpr int NENT = (K * kTileElems + kEntAlign - 1) / kEntAlign * kEntAlign;
   T us[kTileNodes * NS];
-  T fs[MODE == MODE_ENERGY ? 4 : K * kTileElems * D];
+  T fs[MODE == MODE_ENERGY ? 4 : K * kTileElems * D + 4];  // + a zero record at the end
   uint16_t lent[MODE == MODE_ENERGY ? kEntAlign : NENT];
   T tab[CLS ? kMaxGeoClasses * REC : 4];
+  double red[2 * 16];  // per-wavefront shares: energy, then b.v
+  int nbad[16];
 };
+
+// Patch sums of a tile's free nodes (Section 4.2 patch restricted to the tile), GL lanes per
+// node: the lanes of a node take every GL-th entry of its local patch row (ascending element,
+// rounds of 4 whose LDS reads are issued together; absent slots read a zero record) and
+// combine their
+// sums by a butterfly, so every lane holds the same value. A node whose whole patch lies in
+// the tile writes g = scale * (sum - b) in free-DOF order; the others write the sum to their
+// halo slot. Node records are read again (they were loaded by the staging threads).
+template <class SH>
+struct DIM_OF_SH {
+  static constexpr int K = SH::K;
+};
+template <int D, typename T, int NT, int GL, class SH>
+__device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int nloc,
+                                                const double *__restrict__ scale,
+                                                double *__restrict__ g, SH &sh) {
+  const int sub = threadIdx.x % GL;
+  for (int a = threadIdx.x / GL; a < nloc; a += NT / GL) {
+    const int4 rec = M.trec[r0 + a];
+    if (rec.w == 0) continue;  // no free DOF (uniform over the node's lanes)
+    double acc[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) acc[j] = 0.0;
+    const int p0 = rec.w & 0xffff, n = rec.w >> 16;
+    constexpr int kZero = (DIM_OF_SH<SH>::K) * kTileElems * D;  // the zero record
+    for (int p = sub; p < n; p += 4 * GL) {
+      int x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = p + u * GL < n ? sh.lent[p0 + p + u * GL] : kZero;
+      T q[4][D];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < D; ++j) q[u][j] = sh.fs[x[u] + j];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[j] += (double)q[u][j];
+    }
+    if constexpr (GL > 1) {
+#pragma unroll
+      for (int off = GL / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[j] += __shfl_xor(acc[j], off, 64);
+    }
+    if (sub != 0) continue;
+    const int mask = rec.y & 7;
+    int f = rec.y >> 3;
+    if (rec.z & 1) {
+      const double sc = scale ? *scale : 1.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if ((mask >> j) & 1) {
+          g[f] = sc * (acc[j] - M.bhat[f]);
+          ++f;
+        }
+    } else {
+      double *hp = M.hpart + (int64_t)(rec.z >> 2) * D;
+#pragma unroll
+      for (int j = 0; j < D; ++j) hp[j] = acc[j];
+    }
+  }
+}
 
 // One element tile t of mesh M, by one workgroup of NT threads (kTileElems / NT elements and
 // kTileNodes / NT node records per thread):
@@ -526,11 +573,10 @@ struct alignas(16) TileShared {
 //     tile's nodes in LDS; the tile that meets a node first adds b.v of its free DOFs;
 //  2. element pass of the tile's elements, vertex values read from LDS, element results
 //     written to LDS; energies into (s, c);
-//  3. for each free node of the tile: its local patch row summed from LDS in ascending
-//     element order (Section 4.2 patch restricted to the tile); a node whose whole patch
-//     lies in the tile writes g = scale * (sum - b) in free-DOF order, the others write the
-//     sum to their halo slot;
-//  4. block sums (tile_reduce2): energy -> part[t], b.v -> part[ntiles + t], bad count.
+//  3. patch sums of the tile's free nodes from LDS (tile_patch_sums);
+//  4. block sums: per-wavefront plain sums (taken right after the phase that produces the
+//     values), then compensated sums of the wavefront shares: energy -> part[t],
+//     b.v -> part[ntiles + t], bad count.
 // Every order is fixed: the results do not depend on timing. No atomics.
 // geo: the global geometry arrays (or class table, staged in sh.tab when CLS).
 template <int DIM, int D, int KIND, typename T, int MODE, bool CLS, int NT, class SH>
@@ -567,6 +613,8 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
   }
   if constexpr (CLS)
     for (int q = tid; q < M.nclass * REC; q += NT) sh.tab[q] = geo[q];
+  if constexpr (MODE != MODE_ENERGY)
+    if (tid < D) sh.fs[K * kTileElems * D + tid] = T(0);
   // 1. nodal field of the tile; b.v of the nodes this tile owns
   double sb = 0.0, cb = 0.0;
 #pragma unroll
@@ -597,6 +645,13 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
       NodeVec<T, D>::store(sh.us, a, o);
     }
   }
+  constexpr int NW = NT / 64;
+  static_assert(NW <= 16, "per-wavefront shares in LDS");
+  const int lane = tid & 63, wave = tid >> 6;
+  {
+    const double wb = wave_sum(sb + cb);  // this wavefront's share of b.v
+    if (lane == 0) sh.red[NW + wave] = wb;
+  }
   __syncthreads();
   // 2. elements
   double s = 0.0, c = 0.0;
@@ -616,62 +671,34 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
                                                    kTileElems, le, prm, s, c, cnt);
     }
   }
+  {
+    const double wj = wave_sum(s + c);  // this wavefront's share of the energy
+    const int wn = wave_count(cnt);
+    if (lane == 0) {
+      sh.red[wave] = wj;
+      sh.nbad[wave] = wn;
+    }
+  }
   // 3. patch sums of the tile's free nodes
   if constexpr (MODE != MODE_ENERGY) {
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      const int w = rec[k].w;
-      if (w == 0) continue;  // no free DOF, or past the tile's nodes
-      double acc[D];
-#pragma unroll
-      for (int j = 0; j < D; ++j) acc[j] = 0.0;
-      // entries in rounds of 4 whose LDS reads are issued together; the sum stays sequential
-      // in ascending element order (absent slots re-read the last entry and add zero)
-      const int p0 = w & 0xffff, n = w >> 16;
-      for (int p = 0; p < n; p += 4) {
-        int x[4];
-        bool ok[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ok[u] = p + u < n;
-          x[u] = sh.lent[p0 + (ok[u] ? p + u : n - 1)];
-        }
-        T q[4][D];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int j = 0; j < D; ++j) q[u][j] = sh.fs[((x[u] & 3) * kTileElems + (x[u] >> 2)) * D + j];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int j = 0; j < D; ++j) acc[j] += ok[u] ? (double)q[u][j] : 0.0;
-      }
-      const int z = rec[k].z, mask = rec[k].y & 7;
-      int f = rec[k].y >> 3;
-      if (z & 1) {
-        const double sc = scale ? *scale : 1.0;
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-          if ((mask >> j) & 1) {
-            g[f] = sc * (acc[j] - M.bhat[f]);
-            ++f;
-          }
-      } else {
-        double *hp = M.hpart + (int64_t)(z >> 2) * D;
-#pragma unroll
-        for (int j = 0; j < D; ++j) hp[j] = acc[j];
-      }
-    }
+    if (nloc <= NT / 2)
+      tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh);
+    else
+      tile_patch_sums<D, T, NT, 1>(M, r0, nloc, scale, g, sh);
   }
-  // 4. partials
-  double2 rj, rb;
-  int rc;
-  tile_reduce2<NT>(s + c, sb + cb, cnt, rj, rb, rc);
-  if (tid == 0) {
-    M.part[t] = rj;
-    M.part[M.ntiles + t] = rb;
-    M.badp[t] = rc;
+  // 4. partials: compensated sums of the per-wavefront shares
+  __syncthreads();
+  if (wave == 0) {
+    const double2 rj = waves_combine<NW>(sh.red);
+    const double2 rb = waves_combine<NW>(sh.red + NW);
+    if (lane == 0) {
+      int n = 0;
+      for (int w = 0; w < NW; ++w) n += sh.nbad[w];
+      M.part[t] = rj;
+      M.part[M.ntiles + t] = rb;
+      M.badp[t] = n;
+    }
   }
   __syncthreads();  // a persistent caller reuses the LDS for its next tile
 }

@@ -17,9 +17,13 @@ namespace p1e {
 // tile's nodal values and patch entries are staged in LDS, its element forces are written
 // to LDS, and each of its nodes sums its share of the patch from LDS (Section 4.2 patches
 // split by tile).
-constexpr int kTileElems = 1024;   // elements per tile (at most)
-constexpr int kTileNodes = 1024;   // distinct nodes per tile (at most)
+#ifndef P1E_TILE_ELEMS
+#define P1E_TILE_ELEMS 1024
+#endif
+constexpr int kTileElems = P1E_TILE_ELEMS;  // elements per tile (at most)
+constexpr int kTileNodes = P1E_TILE_ELEMS;  // distinct nodes per tile (at most)
 constexpr int kEntAlign = 8;       // each tile's patch entries start on a 16-byte boundary
+static_assert((4 * kTileElems) * 3 < 65536, "patch entry offsets fit 16 bits");
 constexpr int kBlock = 256;        // threads per block of the halo-row and vector kernels
 constexpr uint64_t kAlign = 256;   // alignment of every sub-array in the bound buffer
 constexpr int kMaxGeoClasses = 64; // geometry classes kept as one-byte indices
@@ -52,8 +56,8 @@ struct TileMesh {
   const int4 *ttile = nullptr;  // [ntiles+1] {first element, first node record, first patch
                                 //  entry, 0}; the last one closes the ranges
   const int4 *trec = nullptr;   // [sum nloc] tile node records
-  const uint16_t *tlent = nullptr;  // local patch entries (element << 2 | l), per node
-                                    // ascending element
+  const uint16_t *tlent = nullptr;  // local patch entries: offset (l kTileElems + e) d of the
+                                    // element result in the tile's LDS, per node ascending e
   const int4 *hrec = nullptr;   // [nhalo] halo row records
   // scratch
   double *hpart = nullptr;   // [slots][d] partial patch sums of halo rows, by row

@@ -35,11 +35,22 @@ using namespace dev;
 // ----------------------------------------------------------------------- kernels
 // threads per tile workgroup: one element and at most one node per thread, except for the
 // patch differences in FP64 (more registers per element; two each)
+#ifndef P1E_TILE_THREADS
+#define P1E_TILE_THREADS 1024
+#endif
 template <typename T, int MODE>
-constexpr int tile_threads() { return MODE == MODE_FD ? 512 : 1024; }
+constexpr int tile_threads() {
+  return MODE == MODE_FD ? (kTileElems >= 1024 ? kTileElems / 2 : kTileElems)
+                         : (kTileElems > P1E_TILE_THREADS ? P1E_TILE_THREADS : kTileElems);
+}
+// waves per SIMD to keep registers for: two FP32 tiles fit in LDS (160 KiB), so two
+// workgroups per CU (with 1024 threads: 8 waves per SIMD, at most 64 VGPRs); FP64 tiles
+// run one per CU
+template <typename T, int MODE>
+constexpr int tile_waves_per_eu() { return sizeof(T) == 4 ? 2 * tile_threads<T, MODE>() / 256 : 1; }
 
 template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
-__global__ __launch_bounds__((tile_threads<T, MODE>())) void k_tile(TileMesh M,
+__global__ __launch_bounds__((tile_threads<T, MODE>())) __attribute__((amdgpu_waves_per_eu(tile_waves_per_eu<T, MODE>()))) void k_tile(TileMesh M,
                                                                   const T *__restrict__ geo,
                                                                   const double *__restrict__ vhat,
                                                                   double *__restrict__ g,

@@ -121,7 +121,8 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
     for (int64_t e = e0; e < e1; ++e)
       for (int l = 0; l < k; ++l) {
         const int a = loc[conn[(size_t)l * ne + e]];
-        if (is_free(nodes[a])) m->tlent[ent0 + fill[a]++] = (uint16_t)(((e - e0) << 2) | l);
+        if (is_free(nodes[a]))  // LDS offset of the entry's result: (l kTileElems + e) d
+          m->tlent[ent0 + fill[a]++] = (uint16_t)((l * kTileElems + (e - e0)) * m->d);
       }
     for (int a = 0; a < nloc; ++a) {
       const int32_t v = nodes[a];
