@@ -234,87 +234,94 @@ __device__ __forceinline__ double log_excess(double d) {
   return k0 ? q0 : qk;
 }
 
-// Neo-Hookean density at F = I + G (eq. neoHook), returned in double.
+// Invariants of G = F - I used by the Neo-Hookean density and stress, in T: tr G, s2 (sum of
+// the principal 2x2 minors, 0 in 2D), det G, |G|^2, and (3D) cof G. det F = 1 + tr + s2 + det G.
 template <int DIM, typename T>
-__device__ __forceinline__ double nh_energy(const T G[DIM][DIM], double C1, double D1,
-                                            bool &bad) {
-  T tr, s2, dG, n2 = T(0);
+struct NhInv {
+  T tr, s2, dG, n2;
+  T cg[DIM][DIM];
+};
+template <int DIM, typename T>
+__device__ __forceinline__ NhInv<DIM, T> nh_invariants(const T G[DIM][DIM]) {
+  NhInv<DIM, T> v;
   if constexpr (DIM == 3) {
-    tr = G[0][0] + G[1][1] + G[2][2];
-    s2 = G[0][0] * G[1][1] + G[0][0] * G[2][2] + G[1][1] * G[2][2] - G[0][1] * G[1][0] -
-         G[0][2] * G[2][0] - G[1][2] * G[2][1];
-    dG = G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) -
-         G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +
-         G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3, m1 = (m + 1) % 3, m2 = (m + 2) % 3;
+        v.cg[j][m] = mad(G[j1][m1], G[j2][m2], -(G[j1][m2] * G[j2][m1]));
+      }
+    v.tr = G[0][0] + G[1][1] + G[2][2];
+    v.s2 = v.cg[0][0] + v.cg[1][1] + v.cg[2][2];
+    v.dG = mad(G[0][0], v.cg[0][0], mad(G[0][1], v.cg[0][1], G[0][2] * v.cg[0][2]));
   } else {
-    tr = G[0][0] + G[1][1];
-    s2 = T(0);
-    dG = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+    v.tr = G[0][0] + G[1][1];
+    v.s2 = T(0);
+    v.dG = mad(G[0][0], G[1][1], -(G[0][1] * G[1][0]));
+    v.cg[0][0] = G[1][1], v.cg[0][1] = -G[1][0], v.cg[1][0] = -G[0][1], v.cg[1][1] = G[0][0];
   }
+  T n2 = T(0);
 #pragma unroll
   for (int j = 0; j < DIM; ++j)
 #pragma unroll
-    for (int m = 0; m < DIM; ++m) n2 += G[j][m] * G[j][m];
-  const double delta = (double)tr + (double)s2 + (double)dG;  // det F - 1
+    for (int m = 0; m < DIM; ++m) n2 = mad(G[j][m], G[j][m], n2);
+  v.n2 = n2;
+  return v;
+}
+
+// Neo-Hookean density from the invariants (eq. neoHook), in double:
+//   W = C1 (|G|^2 - 2 (s2 + det G) + 2 q) + D1 delta^2,  delta = det F - 1,
+//   q = delta - log det F (log_excess), using |F|^2 - dim = 2 tr G + |G|^2.
+template <int DIM, typename T>
+__device__ __forceinline__ double nh_density(const NhInv<DIM, T> &v, double C1, double D1,
+                                             bool &bad) {
+  const double delta = (double)v.tr + (double)v.s2 + (double)v.dG;
   if (!(delta > -1.0)) {
     bad = true;
     return 0.0;
   }
-  const double q = log_excess(delta);  // (det F - 1) - log det F >= 0
-  // |F|^2 - dim - 2 log det F = |G|^2 - 2 (s2 + det G) + 2 q
-  const double W = C1 * ((double)n2 - 2.0 * ((double)s2 + (double)dG) + 2.0 * q) +
+  const double q = log_excess(delta);
+  const double W = C1 * ((double)v.n2 - 2.0 * ((double)v.s2 + (double)v.dG) + 2.0 * q) +
                    D1 * delta * delta;
   if (!isfinite(W)) bad = true;
   return W;
 }
 
-// First Piola stress P = dW/dF at F = I + G, in T:
-//   P = 2 C1 (J F - cof F) / J + 2 D1 (J - 1) cof F,  J = det F.
+// Neo-Hookean density at F = I + G (eq. neoHook), returned in double.
 template <int DIM, typename T>
-__device__ __forceinline__ void nh_stress(const T G[DIM][DIM], T C1, T D1, T P[DIM][DIM]) {
-  if constexpr (DIM == 3) {
-    T cg[3][3];  // cof G
-    cg[0][0] = G[1][1] * G[2][2] - G[1][2] * G[2][1];
-    cg[0][1] = G[1][2] * G[2][0] - G[1][0] * G[2][2];
-    cg[0][2] = G[1][0] * G[2][1] - G[1][1] * G[2][0];
-    cg[1][0] = G[0][2] * G[2][1] - G[0][1] * G[2][2];
-    cg[1][1] = G[0][0] * G[2][2] - G[0][2] * G[2][0];
-    cg[1][2] = G[0][1] * G[2][0] - G[0][0] * G[2][1];
-    cg[2][0] = G[0][1] * G[1][2] - G[0][2] * G[1][1];
-    cg[2][1] = G[0][2] * G[1][0] - G[0][0] * G[1][2];
-    cg[2][2] = G[0][0] * G[1][1] - G[0][1] * G[1][0];
-    const T tr = G[0][0] + G[1][1] + G[2][2];
-    const T s2 = cg[0][0] + cg[1][1] + cg[2][2];
-    const T dG = G[0][0] * cg[0][0] + G[0][1] * cg[0][1] + G[0][2] * cg[0][2];
-    const T delta = tr + s2 + dG;
-    const T J = T(1) + delta;
-    const T a = T(2) * C1 / J, bcoef = T(2) * D1 * delta;
-    const T diagA = s2 + dG;    // (J F - cof F) = diagA I + J G + G^T - cof G
-    const T diagC = T(1) + tr;  // cof F = diagC I - G^T + cof G
+__device__ __forceinline__ double nh_energy(const T G[DIM][DIM], double C1, double D1,
+                                            bool &bad) {
+  return nh_density<DIM, T>(nh_invariants<DIM, T>(G), C1, D1, bad);
+}
+
+// Density and first Piola stress P = dW/dF at F = I + G from one set of invariants:
+//   P = 2 C1 (J F - cof F) / J + 2 D1 (J - 1) cof F,  J = det F,
+// with (3D) J F - cof F = (s2 + det G) I + J G + G^T - cof G, cof F = (1 + tr G) I - G^T + cof G,
+// so that with a = 2 C1 / J, b = 2 D1 (J - 1):
+//   P = a J G + (a - b)(G^T - cof G) + (a (s2 + det G) + b (1 + tr G)) I;
+// (2D) J F - cof F = det G I + J G + G^T, cof F = I + cof G = (1 + tr G) I - G^T:
+//   P = a J G + (a - b) G^T + (a det G + b (1 + tr G)) I.
+// The density is bitwise the one of nh_energy.
+template <int DIM, typename T>
+__device__ __forceinline__ double nh_energy_stress(const T G[DIM][DIM], double C1, double D1,
+                                                   bool &bad, T P[DIM][DIM]) {
+  const NhInv<DIM, T> v = nh_invariants<DIM, T>(G);
+  const double W = nh_density<DIM, T>(v, C1, D1, bad);
+  const T delta = v.tr + v.s2 + v.dG;
+  const T J = T(1) + delta;
+  const T a = T(2) * (T)C1 / J, bcoef = T(2) * (T)D1 * delta;
+  const T alpha = a * J, beta = a - bcoef;
+  const T gamma = mad(a, v.s2 + v.dG, bcoef * (T(1) + v.tr));
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
+  for (int j = 0; j < DIM; ++j)
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        T A = J * G[j][m] + G[m][j] - cg[j][m] + (j == m ? diagA : T(0));
-        T C = cg[j][m] - G[m][j] + (j == m ? diagC : T(0));
-        P[j][m] = a * A + bcoef * C;
-      }
-  } else {
-    const T dG = G[0][0] * G[1][1] - G[0][1] * G[1][0];
-    const T delta = G[0][0] + G[1][1] + dG;
-    const T J = T(1) + delta;
-    const T a = T(2) * C1 / J, bcoef = T(2) * D1 * delta;
-    const T cg[2][2] = {{G[1][1], -G[1][0]}, {-G[0][1], G[0][0]}};
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        // J F - cof F = det G I + J G + G^T ;  cof F = I + cof G
-        T A = J * G[j][m] + G[m][j] + (j == m ? dG : T(0));
-        T C = cg[j][m] + (j == m ? T(1) : T(0));
-        P[j][m] = a * A + bcoef * C;
-      }
-  }
+    for (int m = 0; m < DIM; ++m) {
+      const T X = DIM == 3 ? G[m][j] - v.cg[j][m] : G[m][j];
+      const T p = mad(alpha, G[j][m], beta * X);
+      P[j][m] = j == m ? p + gamma : p;
+    }
+  return W;
 }
 
 // p-Laplacian density |g|^p / p (eq. pLaplacian), in double
@@ -411,14 +418,15 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
       G[j][m] = acc;
     }
   bool bad = false;
-  const double W = density<DIM, D, KIND, T>(G, prm, bad);
+  double W;
+  T P[D][DIM];
+  if constexpr (MODE == MODE_FORCE && KIND == P1E_NEOHOOKE) {
+    W = nh_energy_stress<DIM, T>(G, prm.C1, prm.D1, bad, P);
+  } else {
+    W = density<DIM, D, KIND, T>(G, prm, bad);
+    if constexpr (MODE == MODE_FORCE) pl_stress<DIM, T>(G[0], (T)prm.p, P[0]);
+  }
   if constexpr (MODE == MODE_FORCE) {
-    T P[D][DIM];
-    if constexpr (KIND == P1E_NEOHOOKE) {
-      nh_stress<DIM, T>(G, (T)prm.C1, (T)prm.D1, P);
-    } else {
-      pl_stress<DIM, T>(G[0], (T)prm.p, P[0]);
-    }
     T out[K * D];
 #pragma unroll
     for (int j = 0; j < D; ++j) out[j] = T(0);
