@@ -717,20 +717,40 @@ template <int D>
 __device__ __forceinline__ void halo_row(const TileMesh &M, int h, double *__restrict__ g,
                                          const double *__restrict__ scale) {
   const int4 hr = M.hrec[h];
+  const int mask = hr.z & 7, fb = hr.z >> 3;
+  double bv[D];  // fetched first: its latency overlaps the slot loads
+  {
+    int f = fb;
+#pragma unroll
+    for (int j = 0; j < D; ++j) bv[j] = ((mask >> j) & 1) ? M.bhat[f++] : 0.0;
+  }
   double acc[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) acc[j] = 0.0;
   const double *hp = M.hpart + (int64_t)hr.x * D;
-  for (int q = 0; q < hr.y; ++q)
+  // slots in rounds of 4 whose loads are issued together; the sum stays sequential in tile
+  // order (absent slots re-read the last one and add zero)
+  for (int q = 0; q < hr.y; q += 4) {
+    double x[4][D];
+    bool ok[4];
 #pragma unroll
-    for (int j = 0; j < D; ++j) acc[j] += hp[q * D + j];
-  const int mask = hr.z & 7;
-  int f = hr.z >> 3;
+    for (int u = 0; u < 4; ++u) {
+      ok[u] = q + u < hr.y;
+      const int qq = ok[u] ? q + u : hr.y - 1;
+#pragma unroll
+      for (int j = 0; j < D; ++j) x[u][j] = hp[qq * D + j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc[j] += ok[u] ? x[u][j] : 0.0;
+  }
   const double sc = scale ? *scale : 1.0;
+  int f = fb;
 #pragma unroll
   for (int j = 0; j < D; ++j)
     if ((mask >> j) & 1) {
-      g[f] = sc * (acc[j] - M.bhat[f]);
+      g[f] = sc * (acc[j] - bv[j]);
       ++f;
     }
 }

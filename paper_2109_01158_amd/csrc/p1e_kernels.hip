@@ -143,11 +143,20 @@ __global__ __launch_bounds__(kBlock) void k_halo(TileMesh M, double *__restrict_
   if (h < M.nhalo) halo_row<D>(M, h, g, nullptr);
 }
 
+// two DOFs per thread as one 16-byte access when g is 16-byte aligned (gw always is)
 __global__ __launch_bounds__(kBlock) void k_scale(int n, const double *__restrict__ gw,
                                                   const double *__restrict__ scale,
                                                   double *__restrict__ g) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) g[i] = (scale ? *scale : 1.0) * gw[i];
+  const int i = 2 * (blockIdx.x * kBlock + threadIdx.x);
+  if (i >= n) return;
+  const double sc = scale ? *scale : 1.0;
+  if (i + 1 < n && (reinterpret_cast<uintptr_t>(g) & 15) == 0) {
+    const double2 w = *reinterpret_cast<const double2 *>(gw + i);
+    *reinterpret_cast<double2 *>(g + i) = make_double2(sc * w.x, sc * w.y);
+  } else {
+    g[i] = sc * gw[i];
+    if (i + 1 < n) g[i + 1] = sc * gw[i + 1];
+  }
 }
 
 // ----------------------------------------------------------------------- launchers
@@ -248,7 +257,7 @@ int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, i
 int run_scale(p1e_mesh *m, const double *scale, double *g, hipStream_t s) {
   if (m->nfd == 0) return P1E_OK;
   prof_begin("k_scale", s);
-  hipLaunchKernelGGL(k_scale, dim3(nblocks(m->nfd)), dim3(kBlock), 0, s, (int)m->nfd,
+  hipLaunchKernelGGL(k_scale, dim3(nblocks((m->nfd + 1) / 2)), dim3(kBlock), 0, s, (int)m->nfd,
                      (const double *)m->dev.gw, scale, g);
   prof_end(s);
   return check_launch("k_scale");
