@@ -15,7 +15,6 @@
 #include <mutex>
 #include <new>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "p1e_internal.h"
@@ -128,16 +127,16 @@ struct HostAcc {
 double edge_inverse(int dim, const double *X, const int32_t *T, double Binv[3][3],
                     double *hmax) {
   double B[3][3] = {{0}};
-  double h = 0.0;
+  double h2 = 0.0;
   for (int c = 0; c < dim; ++c) {
     double len2 = 0.0;
     for (int r = 0; r < dim; ++r) {
       B[r][c] = X[(int64_t)T[c + 1] * dim + r] - X[(int64_t)T[0] * dim + r];
       len2 += B[r][c] * B[r][c];
     }
-    h = std::max(h, std::sqrt(len2));
+    h2 = std::max(h2, len2);
   }
-  *hmax = h;
+  *hmax = std::sqrt(h2);
   if (dim == 2) {
     double det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
     Binv[0][0] = B[1][1] / det;
@@ -226,15 +225,37 @@ void internal_order(const p1e_mesh_desc *D, std::vector<int32_t> &nperm,
     for (int a = 0; a < dim; ++a) ext = std::max(ext, hi[a] - key.lo[a]);
     const int bits = dim == 3 ? 21 : 32;
     key.scale = ext > 0.0 ? (double)((1ull << bits) - 1) / ext : 0.0;
-    std::vector<uint64_t> ek(ne);
+    // (key, element) pairs, stable LSD radix sort by key, 16 bits per pass (equal keys keep
+    // the input order); passes over key bits that are all zero are skipped
+    struct KE {
+      uint64_t key;
+      int64_t e;
+    };
+    std::vector<KE> ek(ne), tmp(ne);
+    uint64_t used = 0;
     for (int64_t e = 0; e < ne; ++e) {
       double c[3] = {0, 0, 0};
       for (int l = 0; l < k; ++l)
         for (int a = 0; a < dim; ++a) c[a] += D->coords[(int64_t)D->conn[e * k + l] * dim + a];
       for (int a = 0; a < dim; ++a) c[a] /= k;
-      ek[e] = key(c);
+      ek[e] = {key(c), e};
+      used |= ek[e].key;
     }
-    std::stable_sort(eperm.begin(), eperm.end(), [&](int32_t a, int32_t b) { return ek[a] < ek[b]; });
+    std::vector<int64_t> cnt(1 << 16);
+    for (int shift = 0; shift < 64; shift += 16) {
+      if (((used >> shift) & 0xffff) == 0) continue;
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (int64_t e = 0; e < ne; ++e) cnt[(ek[e].key >> shift) & 0xffff] += 1;
+      int64_t run = 0;
+      for (auto &c : cnt) {
+        const int64_t n = c;
+        c = run;
+        run += n;
+      }
+      for (int64_t e = 0; e < ne; ++e) tmp[cnt[(ek[e].key >> shift) & 0xffff]++] = ek[e];
+      ek.swap(tmp);
+    }
+    for (int64_t e = 0; e < ne; ++e) eperm[e] = (int32_t)ek[e].e;
   }
   nperm.resize(nn);
   for (int64_t i = 0; i < nn; ++i) nperm[i] = (int32_t)i;
@@ -251,33 +272,44 @@ void classify_geometry(p1e_mesh *m) {
   const int dd = m->dim * m->dim + 1;
   const int64_t ne = m->ne;
   if (ne == 0) return;
-  std::vector<double> scale(dd, 0.0);
-  for (int q = 0; q < dd; ++q)
-    for (int64_t e = 0; e < ne; ++e)
-      scale[q] = std::max(scale[q], std::fabs(m->geo64[(size_t)q * ne + e]));
-  std::unordered_map<std::string, int> ids;
+  std::vector<double> inv(dd, 0.0);
+  for (int q = 0; q < dd; ++q) {
+    double mx = 0.0;
+    for (int64_t e = 0; e < ne; ++e) mx = std::max(mx, std::fabs(m->geo64[(size_t)q * ne + e]));
+    inv[q] = mx > 0.0 ? std::ldexp(1.0, 40) / mx : 0.0;
+  }
+  // open-addressing table of the classes' quantized keys (kMaxGeoClasses < kSlots / 2)
+  constexpr int kSlots = 4 * kMaxGeoClasses;
+  std::vector<int64_t> keys;  // [class][dd]
+  std::vector<int> slot_cls(kSlots, -1);
   std::vector<double> tab;
   std::vector<uint8_t> cls((size_t)ne);
-  std::string key(sizeof(int64_t) * dd, '\0');
+  std::vector<int64_t> key(dd);
   for (int64_t e = 0; e < ne; ++e) {
+    uint64_t h = 1469598103934665603ull;
     for (int q = 0; q < dd; ++q) {
-      const double v = m->geo64[(size_t)q * ne + e];
-      const int64_t k = scale[q] > 0.0 ? (int64_t)std::llround(std::ldexp(v / scale[q], 40)) : 0;
-      std::memcpy(&key[sizeof(int64_t) * q], &k, sizeof(int64_t));
+      key[q] = (int64_t)std::llrint(m->geo64[(size_t)q * ne + e] * inv[q]);
+      h = (h ^ (uint64_t)key[q]) * 1099511628211ull;
     }
-    auto it = ids.find(key);
-    int id;
-    if (it == ids.end()) {
-      id = (int)ids.size();
+    int sl = (int)((h ^ (h >> 29)) % kSlots), id = -1;
+    for (;; sl = (sl + 1) % kSlots) {
+      const int c = slot_cls[sl];
+      if (c < 0) break;
+      if (std::equal(key.begin(), key.end(), keys.begin() + (size_t)c * dd)) {
+        id = c;
+        break;
+      }
+    }
+    if (id < 0) {
+      id = (int)(keys.size() / dd);
       if (id >= kMaxGeoClasses) return;  // not a few-shape mesh: keep per-element arrays
-      ids.emplace(key, id);
+      slot_cls[sl] = id;
+      keys.insert(keys.end(), key.begin(), key.end());
       for (int q = 0; q < dd; ++q) tab.push_back(m->geo64[(size_t)q * ne + e]);
-    } else {
-      id = it->second;
     }
     cls[e] = (uint8_t)id;
   }
-  m->nclass = (int)ids.size();
+  m->nclass = (int)(keys.size() / dd);
   m->geo_tab = std::move(tab);
   m->geo_cls = std::move(cls);
   std::vector<double>().swap(m->geo64);
@@ -327,7 +359,7 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
     for (int l = 0; l < k; ++l) conn[(size_t)l * ne + e] = ninv[T[l]];
     double Bi[3][3], h;
     double det = edge_inverse(dim, D->coords, T, Bi, &h);
-    if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * std::pow(h, dim))
+    if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * (dim == 3 ? h * h * h : h * h))
       return fail(P1E_EDEGEN, "element " + std::to_string(ex) + " is degenerate");
     double vol = std::fabs(det) / fact;
     for (int l = 0; l < dim; ++l)

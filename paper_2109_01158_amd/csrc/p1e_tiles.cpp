@@ -12,6 +12,7 @@
 // Every sum has a fixed order.
 
 #include <algorithm>
+#include <numeric>
 #include <vector>
 
 #include "p1e_internal.h"
@@ -83,8 +84,12 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
   m->ttile.clear();
   m->trec.clear();
   m->tlent.clear();
+  m->ttile.reserve(4 * (nt + 1));
+  m->trec.reserve(4 * (size_t)std::accumulate(ntile_of.begin(), ntile_of.end(), int64_t(0)));
+  m->tlent.reserve((size_t)k * ne + kEntAlign * nt);
   m->conn_loc.assign((size_t)k * ne, 0);
-  std::vector<int32_t> loc(nn, -1), cnt, pos, nodes, seen_tiles(nn, 0);
+  std::vector<int32_t> loc(nn, -1), cnt, pos, fill, nodes, seen_tiles(nn, 0);
+  nodes.reserve(kTileNodes);
   for (int64_t t = 0; t < nt; ++t) {
     const int64_t e0 = tile_e[t], e1 = tile_e[t + 1];
     nodes.clear();
@@ -117,7 +122,7 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
       if (is_free(nodes[a])) run += cnt[a];
     }
     m->tlent.resize(ent0 + (run + kEntAlign - 1) / kEntAlign * kEntAlign, 0);
-    std::vector<int32_t> fill(pos);
+    fill.assign(pos.begin(), pos.end());
     for (int64_t e = e0; e < e1; ++e)
       for (int l = 0; l < k; ++l) {
         const int a = loc[conn[(size_t)l * ne + e]];
