@@ -69,14 +69,14 @@ def algorithmic_bytes(info, prec, classed):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("p1e_device.h", "p1e_kernels.hip", "p1e_internal.h"):
+    for f in ("p1e_device.h", "p1e_kernels.hip", "p1e_internal.h", "p1e_tiles.cpp"):
         with open(os.path.join(ROOT, "paper_2109_01158_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(config, prec, kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary of this workload,
+def profile_record(config, prec):
+    """The committed counter summary of this workload (HBM traffic and VALU issue per kernel),
     or None if there is none or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_jgrad_{prec}_{config}.json")
     if not os.path.exists(path):
@@ -85,7 +85,7 @@ def measured_traffic(config, prec, kernel):
         t = json.load(f)
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return t["traffic_bytes_per_launch"].get(kernel)
+    return t
 
 
 def cpu_baseline(prob, target_s=12.0):
@@ -173,6 +173,7 @@ def main():
         if k in abytes:
             s["alg_GBs"] = abytes[k] / (s["avg_us"] * 1e-6) / 1e9
     step_bytes = sum(abytes.values())
+    prof = profile_record(a.config, a.prec)
 
     extras = {}
     if not a.no_extras:
@@ -223,9 +224,11 @@ def main():
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": measured_traffic(a.config, a.prec, dom),
+                     "traffic": (prof or {}).get("traffic_bytes_per_launch", {}).get(dom),
                      "alg_bytes_per_launch": dom_bytes,
-                     "alg_bytes_per_element": dom_bytes / info["ne"] if dom_bytes else None},
+                     "alg_bytes_per_element": dom_bytes / info["ne"] if dom_bytes else None,
+                     "valu_issue_frac_profiled":
+                         (prof or {}).get("valu_issue", {}).get(dom, {}).get("frac")},
         "ms_per_step_with_kernel_events": ms_events,
         "step_alg_bytes_per_element": step_bytes / info["ne"],
         "step_alg_GBs": step_bytes / (ms * 1e-3) / 1e9,
