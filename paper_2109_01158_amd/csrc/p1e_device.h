@@ -383,7 +383,8 @@ __device__ __forceinline__ void store_entries(T *__restrict__ r, int nep, int e,
 // vertex-major entries r[(l nep + er) D + j].
 // geo: [DIM*DIM][ne] entries of B^-1 followed by [ne] sizes |T|; or, with CLS, a table of
 // records [DIM*DIM entries of B^-1, |T|] and cls = the element's class.
-template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
+// FIRST: (s, c) holds nothing yet, so the element's energy is assigned instead of added
+template <int DIM, int D, int KIND, typename T, int MODE, bool CLS, bool FIRST = false>
 __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 1][D],
                                              const T *__restrict__ geo, int cls,
                                              T *__restrict__ r, int nep, int er,
@@ -487,6 +488,8 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
   }
   if (bad) {
     cnt += 1;
+  } else if (FIRST) {
+    s = (double)vol * W;
   } else {
     double t, err;
     two_sum(s, (double)vol * W, t, err);
@@ -633,6 +636,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
       const bool owner = (rec[k].z >> 1) & 1;
       int fb = rec[k].y >> 3;
       T o[D];
+      double bvn = 0.0;  // b.v of this node's free DOFs
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         const double w = M.wref[(int64_t)gi * D + j];
@@ -640,17 +644,22 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
         if ((mask >> j) & 1) {
           const double vj = vhat[fb];
           val = vj - w;
-          if (owner) {
-            double t2, err;
-            two_sum(sb, M.bhat[fb] * vj, t2, err);
-            sb = t2;
-            cb += err;
-          }
+          bvn = fma(M.bhat[fb], vj, bvn);
           ++fb;
         }
         o[j] = (T)val;
       }
       NodeVec<T, D>::store(sh.us, a, o);
+      if (owner) {
+        if (NPT == 1) {
+          sb = bvn;
+        } else {
+          double t2, err;
+          two_sum(sb, bvn, t2, err);
+          sb = t2;
+          cb += err;
+        }
+      }
     }
   }
   constexpr int NW = NT / 64;
@@ -671,12 +680,13 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
       T uu[K][D];
 #pragma unroll
       for (int l = 0; l < K; ++l) NodeVec<T, D>::load(sh.us, nd[k][l], uu[l]);
+      constexpr bool FIRST = EPT == 1;
       if constexpr (CLS)
-        element_pass<DIM, D, KIND, T, MODE, true>(e0 + le, M.ne, uu, sh.tab, cl[k], sh.fs,
-                                                  kTileElems, le, prm, s, c, cnt);
+        element_pass<DIM, D, KIND, T, MODE, true, FIRST>(e0 + le, M.ne, uu, sh.tab, cl[k],
+                                                         sh.fs, kTileElems, le, prm, s, c, cnt);
       else
-        element_pass<DIM, D, KIND, T, MODE, false>(e0 + le, M.ne, uu, geo, 0, sh.fs,
-                                                   kTileElems, le, prm, s, c, cnt);
+        element_pass<DIM, D, KIND, T, MODE, false, FIRST>(e0 + le, M.ne, uu, geo, 0, sh.fs,
+                                                          kTileElems, le, prm, s, c, cnt);
     }
   }
   {
