@@ -186,13 +186,6 @@ struct NodeVec<T, 1> {
 };
 
 // ----------------------------------------------------------------------- densities
-template <typename T>
-__device__ __forceinline__ T fpow(T x, T y);
-template <>
-__device__ __forceinline__ float fpow<float>(float x, float y) { return powf(x, y); }
-template <>
-__device__ __forceinline__ double fpow<double>(double x, double y) { return pow(x, y); }
-
 // q(d) = d - log(1 + d) >= 0 for d > -1, in double, without the cancellation of the plain
 // difference near d = 0 (where q ~ d^2 / 2). Binary exponent reduction 1 + d = 2^k m with
 // m in [1/sqrt 2, sqrt 2), then log m = 2 atanh s = 2 s + 2 s^3 S(s^2), s = (m - 1)/(m + 1),
@@ -324,26 +317,59 @@ __device__ __forceinline__ double nh_energy_stress(const T G[DIM][DIM], double C
   return W;
 }
 
-// p-Laplacian density |g|^p / p (eq. pLaplacian), in double
+// s^(p/2) for s >= 0, in double. When 2p is an integer k <= 64 (the benchmarks use p = 1.5,
+// 3, 5): s^(k/4) = s^floor(k/4) (s^(1/4))^(k mod 4) by products and square roots only (an
+// error of a few ulps); otherwise pow. The branch depends on p alone (uniform per mesh).
+__device__ __forceinline__ double half_pow(double s, double p) {
+  const double k2 = 2.0 * p;
+  const int k = (int)k2;
+  if ((double)k == k2 && k >= 0 && k <= 64) {
+    double r = 1.0;
+    for (int i = 0; i < (k >> 2); ++i) r *= s;
+    const int f = k & 3;
+    if (f != 0) {
+      const double q = sqrt(s);
+      if (f == 2) {
+        r *= q;
+      } else {
+        const double q4 = sqrt(q);
+        r *= f == 1 ? q4 : q * q4;
+      }
+    }
+    return r;
+  }
+  return pow(s, 0.5 * p);
+}
+
 template <int DIM, typename T>
-__device__ __forceinline__ double pl_energy(const T g[DIM], double p, bool &bad) {
+__device__ __forceinline__ T pl_norm2(const T g[DIM]) {
   T s = T(0);
 #pragma unroll
   for (int m = 0; m < DIM; ++m) s += g[m] * g[m];
-  const double W = pow((double)s, 0.5 * p) / p;
+  return s;
+}
+
+// p-Laplacian density |g|^p / p (eq. pLaplacian), in double
+template <int DIM, typename T>
+__device__ __forceinline__ double pl_energy(const T g[DIM], double p, bool &bad) {
+  const double W = half_pow((double)pl_norm2<DIM, T>(g), p) / p;
   if (!isfinite(W)) bad = true;
   return W;
 }
 
-// its gradient |g|^(p-2) g, defined as 0 at g = 0
+// the density and its gradient |g|^(p-2) g (0 at g = 0) from one power |g|^p; the density
+// is bitwise the one of pl_energy
 template <int DIM, typename T>
-__device__ __forceinline__ void pl_stress(const T g[DIM], T p, T P[DIM]) {
-  T s = T(0);
-#pragma unroll
-  for (int m = 0; m < DIM; ++m) s += g[m] * g[m];
-  const T sc = s > T(0) ? fpow<T>(s, T(0.5) * (p - T(2))) : T(0);
+__device__ __forceinline__ double pl_energy_stress(const T g[DIM], double p, bool &bad,
+                                                   T P[DIM]) {
+  const T s = pl_norm2<DIM, T>(g);
+  const double sp = half_pow((double)s, p);
+  const double W = sp / p;
+  if (!isfinite(W)) bad = true;
+  const T sc = s > T(0) ? (T)(sp / (double)s) : T(0);
 #pragma unroll
   for (int m = 0; m < DIM; ++m) P[m] = sc * g[m];
+  return W;
 }
 
 // density dispatch on a D x DIM gradient
@@ -423,9 +449,10 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
   T P[D][DIM];
   if constexpr (MODE == MODE_FORCE && KIND == P1E_NEOHOOKE) {
     W = nh_energy_stress<DIM, T>(G, prm.C1, prm.D1, bad, P);
+  } else if constexpr (MODE == MODE_FORCE) {
+    W = pl_energy_stress<DIM, T>(G[0], prm.p, bad, P[0]);
   } else {
     W = density<DIM, D, KIND, T>(G, prm, bad);
-    if constexpr (MODE == MODE_FORCE) pl_stress<DIM, T>(G[0], (T)prm.p, P[0]);
   }
   if constexpr (MODE == MODE_FORCE) {
     T out[K * D];

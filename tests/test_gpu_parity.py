@@ -38,6 +38,9 @@ def _cases():
         "plap_square_33": lambda: S.config_problem("plap_square_33"),
         "plap_p1.5_45": lambda: S.plaplace_square(n=45, p=1.5, seed=3),
         "plap_p5_37": lambda: S.plaplace_square(n=37, p=5.0, seed=4),
+        # p = 4.5 and 2.7: the quarter-root branch and the general power of |g|^p
+        "plap_p4.5_19": lambda: S.plaplace_square(n=19, p=4.5, seed=10),
+        "plap_p2.7_23": lambda: S.plaplace_square(n=23, p=2.7, seed=11),
         "plap_lshape_16": lambda: S.plaplace_lshape(16, p=3.0, seed=5),
         "nh2d_beam_60x13": lambda: S.neohooke_beam_2d(60, 13, 2.0, 13 * 2.0 / 60, seed=6),
         "nh3d_box_13x7x5": lambda: S.neohooke_box_3d(13, 7, 5, 1.0, 7 / 13, 5 / 13, seed=7),
