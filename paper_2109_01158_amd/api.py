@@ -224,7 +224,7 @@ class Mesh:
         return out3, flag, self.forces_gen
 
     def grad_gather(self, prec="mixed", scale=None, stream=None, g=None):
-        """g = scale * (patch sums of the forces of the last energy_forces/grad_exact - b)."""
+        """g = scale * (the gradient kept by the last energy_forces call)."""
         g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device) if g is None else g
         grad_gather(self.handle, prec, scale, g, stream)
         return g

@@ -474,7 +474,7 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
   if constexpr (MODE == MODE_FD) {
     // Central differences of |T| W under v_n +- eps for every DOF n of this element: only
     // row j of F changes, by +-eps grad phi_l (Section 6.1). Differenced per element; the
-    // patch sum happens in k_gather.
+    // patch sums happen in the tile's node phase and the halo rows.
     const double inv2e = 1.0 / (2.0 * prm.eps);
     T out[K * D];
 #pragma unroll

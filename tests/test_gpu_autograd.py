@@ -1,7 +1,7 @@
 """The differentiation hook: torch.autograd.Function with the exact gradient as backward,
 checked by gradcheck (FP64), against the oracle gradient and against the patch
 central-difference gradient, including a scaled incoming gradient and the case where the
-forward pass's element forces were overwritten before backward."""
+gradient kept by the forward pass was overwritten before backward."""
 
 import numpy as np
 import pytest
