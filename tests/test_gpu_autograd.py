@@ -60,7 +60,7 @@ def test_scaled_incoming_gradient_and_stale_forces(P, oracle_mod):
     (3.0 * P.p1_energy(v1, mesh, "fp64")).backward()
     g1 = O.grad_exact(prob.v)
     assert np.allclose(v1.grad.cpu().numpy(), 3.0 * g1, rtol=1e-12, atol=1e-12 * np.abs(g1).max())
-    # two forwards, then the first backward: its forces were overwritten -> recomputed
+    # two forwards, then the first backward: its kept gradient was overwritten -> recomputed
     v2 = v1.detach().clone().requires_grad_(True)
     v3 = (v1.detach() * 1.0001).requires_grad_(True)
     J2 = P.p1_energy(v2, mesh, "fp64")
