@@ -302,33 +302,6 @@ __global__ __launch_bounds__(kVB) void kb_vcopy(EngineDev E) {
   }
 }
 
-// partial of (S or Y)[hist i] . d
-__global__ __launch_bounds__(kVB) void kb_vdot(EngineDev E, int i, int use_y) {
-  const int count = E.counts[kCountVec];
-  for (int t = blockIdx.x; t < count; t += gridDim.x) {
-    const VTile V = vtile(E, t);
-    if (!needs_dir(E, V.slot)) continue;
-    const int h = hist_index(E, V.slot, i);
-    if (h < 0) continue;
-    const SlotDev &S = E.slots[V.slot];
-    const double *w = (use_y ? S.Y : S.S) + (int64_t)h * V.n;
-    double s = 0.0, c = 0.0;
-    int cnt = 0;
-    for (int k = 0; k < kVecTile; k += kVB) {
-      const int j = V.i0 + k + threadIdx.x;
-      if (j < V.n) {
-        double tt, e;
-        two_sum(s, w[j] * S.d[j], tt, e);
-        s = tt;
-        c += e;
-      }
-    }
-    block_reduce<kVB>(s, c, cnt);
-    if (threadIdx.x == 0) S.vpart[4 * (V.i0 / kVecTile)] = make_double2(s, c);
-    __syncthreads();
-  }
-}
-
 // one block per slot: first loop (phase 0) a_i = rho s_i.q, coef = -a_i;
 // second loop (phase 1) b = rho y_i.r, coef = a_i - b
 __global__ __launch_bounds__(kVB) void kb_coef(EngineDev E, int i, int phase) {
@@ -352,62 +325,59 @@ __global__ __launch_bounds__(kVB) void kb_coef(EngineDev E, int i, int phase) {
   }
 }
 
-// d += coef * (S or Y)[hist i]
-__global__ __launch_bounds__(kVB) void kb_vaxpy(EngineDev E, int i, int use_y) {
-  const int count = E.counts[kCountVec];
-  for (int t = blockIdx.x; t < count; t += gridDim.x) {
-    const VTile V = vtile(E, t);
-    if (!needs_dir(E, V.slot)) continue;
-    const int h = hist_index(E, V.slot, i);
-    if (h < 0) continue;
-    const SlotDev &S = E.slots[V.slot];
-    const double coef = E.sc[V.slot * kNSc + SC_COEF];
-    const double *w = (use_y ? S.Y : S.S) + (int64_t)h * V.n;
-    for (int k = 0; k < kVecTile; k += kVB) {
-      const int j = V.i0 + k + threadIdx.x;
-      if (j < V.n) S.d[j] = fma(coef, w[j], S.d[j]);
-    }
-  }
-}
-
-// d *= gamma (H0 = gamma I) when pairs are stored
-__global__ __launch_bounds__(kVB) void kb_vscale(EngineDev E) {
-  const int count = E.counts[kCountVec];
-  for (int t = blockIdx.x; t < count; t += gridDim.x) {
-    const VTile V = vtile(E, t);
-    if (!needs_dir(E, V.slot) || E.st[V.slot * kNSt + ST_NH] == 0) continue;
-    const SlotDev &S = E.slots[V.slot];
-    const double gamma = E.sc[V.slot * kNSc + SC_GAMMA];
-    for (int k = 0; k < kVecTile; k += kVB) {
-      const int j = V.i0 + k + threadIdx.x;
-      if (j < V.n) S.d[j] *= gamma;
-    }
-  }
-}
-
-// d = -d, partials g.d, max|d|, g.g, max|g|
-__global__ __launch_bounds__(kVB) void kb_vneg(EngineDev E) {
+// One pass of the two-loop recursion over d, in this order per entry:
+//   if ia >= 0:  d += coef * (Y if ya else S)[hist ia]       (the previous update)
+//   if scale:    d *= gamma (H0 = gamma I) when pairs are stored
+//   if neg:      d = -d, with the partials g.d, max|d|, g.g, max|g|
+//   if ib >= 0:  partial of (Y if yb else S)[hist ib] . d     (the next coefficient)
+// Fusing an update with the next dot halves the passes over the vectors; each entry sees
+// the same operations in the same order as separate passes would apply.
+__global__ __launch_bounds__(kVB) void kb_vstep(EngineDev E, int ia, int ya, int scale, int neg,
+                                                int ib, int yb) {
   __shared__ double sh[2][kVB / 64];
   const int count = E.counts[kCountVec];
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const VTile V = vtile(E, t);
     if (!needs_dir(E, V.slot)) continue;
     const SlotDev &S = E.slots[V.slot];
-    double gd = 0, gdc = 0, gg = 0, ggc = 0, md = 0, mg = 0;
+    const int ha = ia >= 0 ? hist_index(E, V.slot, ia) : -1;
+    const int hb = ib >= 0 ? hist_index(E, V.slot, ib) : -1;
+    const bool sc = scale && E.st[V.slot * kNSt + ST_NH] > 0;
+    if (ha < 0 && hb < 0 && !sc && !neg) continue;
+    const double coef = E.sc[V.slot * kNSc + SC_COEF];
+    const double gamma = E.sc[V.slot * kNSc + SC_GAMMA];
+    const double *wa = ha >= 0 ? (ya ? S.Y : S.S) + (int64_t)ha * V.n : nullptr;
+    const double *wb = hb >= 0 ? (yb ? S.Y : S.S) + (int64_t)hb * V.n : nullptr;
+    double s = 0.0, c = 0.0, gg = 0.0, ggc = 0.0, md = 0.0, mg = 0.0;
     for (int k = 0; k < kVecTile; k += kVB) {
       const int j = V.i0 + k + threadIdx.x;
       if (j < V.n) {
-        const double dj = -S.d[j], gj = S.g[j];
-        S.d[j] = dj;
+        double dj = S.d[j];
+        if (wa) dj = fma(coef, wa[j], dj);
+        if (sc) dj *= gamma;
         double tt, e;
-        two_sum(gd, gj * dj, tt, e), gd = tt, gdc += e;
-        two_sum(gg, gj * gj, tt, e), gg = tt, ggc += e;
-        md = fmax(md, fabs(dj));
-        mg = fmax(mg, fabs(gj));
+        if (neg) {
+          dj = -dj;
+          const double gj = S.g[j];
+          two_sum(s, gj * dj, tt, e), s = tt, c += e;
+          two_sum(gg, gj * gj, tt, e), gg = tt, ggc += e;
+          md = fmax(md, fabs(dj));
+          mg = fmax(mg, fabs(gj));
+        } else if (wb) {
+          two_sum(s, wb[j] * dj, tt, e), s = tt, c += e;
+        }
+        S.d[j] = dj;
       }
     }
+    if (!neg && !wb) continue;  // uniform over the block
     int cnt = 0;
-    block_reduce<kVB>(gd, gdc, cnt);
+    block_reduce<kVB>(s, c, cnt);
+    double2 *p = S.vpart + 4 * (V.i0 / kVecTile);
+    if (!neg) {
+      if (threadIdx.x == 0) p[0] = make_double2(s, c);
+      __syncthreads();
+      continue;
+    }
     __syncthreads();
     block_reduce<kVB>(gg, ggc, cnt);
     for (int o = 32; o > 0; o >>= 1) {
@@ -424,8 +394,7 @@ __global__ __launch_bounds__(kVB) void kb_vneg(EngineDev E) {
         md = fmax(md, sh[0][w]);
         mg = fmax(mg, sh[1][w]);
       }
-      double2 *p = S.vpart + 4 * (V.i0 / kVecTile);
-      p[0] = make_double2(gd, gdc);
+      p[0] = make_double2(s, c);
       p[1] = make_double2(md, 0.0);
       p[2] = make_double2(gg, ggc);
       p[3] = make_double2(mg, 0.0);
@@ -520,18 +489,25 @@ int batch_step(const EngineDev &E, hipStream_t s) {
   hipLaunchKernelGGL(kb_vupdate, dim3(kGridVec), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_hist, dim3(E.max_slots), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_vcopy, dim3(kGridVec), dim3(kVB), 0, s, E);
-  for (int i = 0; i < E.history; ++i) {
-    hipLaunchKernelGGL(kb_vdot, dim3(kGridVec), dim3(kVB), 0, s, E, i, 0);
+  // two-loop recursion: q = g; for i = newest..oldest: a_i = rho_i s_i.q, q -= a_i y_i;
+  // r = gamma q; for i = oldest..newest: b = rho_i y_i.r, r += (a_i - b) s_i; d = -r
+  const int m = E.history;
+  auto vstep = [&](int ia, int ya, int scale, int neg, int ib, int yb) {
+    hipLaunchKernelGGL(kb_vstep, dim3(kGridVec), dim3(kVB), 0, s, E, ia, ya, scale, neg, ib, yb);
+  };
+  vstep(-1, 0, 0, 0, 0, 0);
+  hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, 0, 0);
+  for (int i = 1; i < m; ++i) {
+    vstep(i - 1, 1, 0, 0, i, 0);
     hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, i, 0);
-    hipLaunchKernelGGL(kb_vaxpy, dim3(kGridVec), dim3(kVB), 0, s, E, i, 1);
   }
-  hipLaunchKernelGGL(kb_vscale, dim3(kGridVec), dim3(kVB), 0, s, E);
-  for (int i = E.history - 1; i >= 0; --i) {
-    hipLaunchKernelGGL(kb_vdot, dim3(kGridVec), dim3(kVB), 0, s, E, i, 1);
+  vstep(m - 1, 1, 1, 0, m - 1, 1);
+  hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, m - 1, 1);
+  for (int i = m - 2; i >= 0; --i) {
+    vstep(i + 1, 0, 0, 0, i, 1);
     hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, i, 1);
-    hipLaunchKernelGGL(kb_vaxpy, dim3(kGridVec), dim3(kVB), 0, s, E, i, 0);
   }
-  hipLaunchKernelGGL(kb_vneg, dim3(kGridVec), dim3(kVB), 0, s, E);
+  vstep(0, 0, 0, 1, -1, 0);
   hipLaunchKernelGGL(kb_dirfin, dim3(E.max_slots), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_vtrial, dim3(kGridVec), dim3(kVB), 0, s, E);
   hipError_t e = hipGetLastError();
