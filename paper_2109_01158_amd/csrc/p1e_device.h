@@ -83,12 +83,31 @@ __device__ __forceinline__ void block_reduce(double &s, double &c, int &cnt) {
   }
 }
 
-// Sum of a double over one 64-wide wavefront by a butterfly: every lane gets the same plain
-// FP64 tree sum (at most 6 ulps of the wavefront's sum of magnitudes; fixed order).
+// a double from another lane by a DPP lane permutation within rows of 16 (CTRL: quad_perm,
+// row_half_mirror or row_mirror; every lane has a source)
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_double(double x, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                          __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+
+// Sum of a double over one 64-wide wavefront, the same in every lane: within each row of 16
+// lanes a butterfly of DPP permutations (partners 1 and 2 within quads, then the mirrored
+// half-row and row: each step adds two equal-sized partial sums), then the four row sums
+// combined as (r0 + r1) + (r2 + r3). A plain FP64 tree (at most 6 ulps of the wavefront's sum
+// of magnitudes) in a fixed order, without the LDS.
 __device__ __forceinline__ double wave_sum(double a) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-  return a;
+  constexpr int kXor1 = 0xb1, kXor2 = 0x4e, kHalfMirror = 0x141, kMirror = 0x140;
+  a += dpp_double<kXor1>(a);
+  a += dpp_double<kXor2>(a);
+  a += dpp_double<kHalfMirror>(a);
+  a += dpp_double<kMirror>(a);
+  return (lane_double(a, 0) + lane_double(a, 16)) + (lane_double(a, 32) + lane_double(a, 48));
 }
 __device__ __forceinline__ int wave_count(int n) {
   if (__any(n != 0))  // counts are rare (bad elements): wave-uniform test
@@ -543,8 +562,7 @@ struct alignas(16) TileShared {
 // Patch sums of a tile's free nodes (Section 4.2 patch restricted to the tile), GL lanes per
 // node: the lanes of a node take every GL-th entry of its local patch row (ascending element,
 // rounds of 4 whose LDS reads are issued together; absent slots read a zero record) and
-// combine their
-// sums by a butterfly, so every lane holds the same value. A node whose whole patch lies in
+// combine their sums, so every lane holds the same value. A node whose whole patch lies in
 // the tile writes g = scale * (sum - b) in free-DOF order; the others write the sum to their
 // halo slot. Node records are read again (they were loaded by the staging threads).
 template <class SH>
@@ -578,11 +596,10 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
 #pragma unroll
         for (int j = 0; j < D; ++j) acc[j] += (double)q[u][j];
     }
-    if constexpr (GL > 1) {
+    static_assert(GL == 1 || GL == 2, "one or two lanes per node");
+    if constexpr (GL == 2) {  // the node's two lanes are neighbours: a DPP swap within quads
 #pragma unroll
-      for (int off = GL / 2; off > 0; off >>= 1)
-#pragma unroll
-        for (int j = 0; j < D; ++j) acc[j] += __shfl_xor(acc[j], off, 64);
+      for (int j = 0; j < D; ++j) acc[j] += dpp_double<0xb1>(acc[j]);
     }
     if (sub != 0) continue;
     const int mask = rec.y & 7;
