@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 #include <cstdint>
 
 #include "p1e_internal.h"
@@ -87,8 +88,8 @@ __device__ __forceinline__ void block_reduce(double &s, double &c, int &cnt) {
 // row_half_mirror or row_mirror; every lane has a source)
 template <int CTRL>
 __device__ __forceinline__ double dpp_double(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double lane_double(double x, int lane) {
@@ -216,6 +217,13 @@ struct NodeVec<T, 1> {
 //  k != 0: q = d - k log 2 - 2 s - 2 s^3 S - (1 + d - t)/t with t = fl(1 + d); the last term
 //         undoes the rounding of t (d - (t - 1) is exact here), q >= 0.06 so no cancellation.
 // About 40 double instructions, against over 100 for a general-purpose log1p.
+// A double constant handed to the arithmetic as a scalar register: the FMAs then read it as a
+// uniform operand instead of materialising it in vector registers (two vector moves each).
+__device__ __forceinline__ double scalar_const(double c) {
+  double r;
+  asm("s_mov_b64 %0, %1" : "=s"(r) : "s"(c));
+  return r;
+}
 __device__ __forceinline__ double log_excess(double d) {
   const double t = 1.0 + d;
   int k;
@@ -224,18 +232,18 @@ __device__ __forceinline__ double log_excess(double d) {
   m = lo ? 2.0 * m : m;
   k = lo ? k - 1 : k;
   const bool k0 = k == 0;
-  const double s = (k0 ? d : m - 1.0) / (k0 ? 2.0 + d : m + 1.0);
+  // s = num / den with den in [1.7, 2.5]: the hardware reciprocal refined by two Newton steps,
+  // then one residual correction of the quotient (Markstein's scheme; within 1 ulp)
+  const double num = k0 ? d : m - 1.0, den = k0 ? 2.0 + d : m + 1.0;
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  double s = num * r;
+  s = fma(r, fma(-den, s, num), s);
   const double w = s * s;
-  double S = 1.0 / 21.0;
-  S = fma(S, w, 1.0 / 19.0);
-  S = fma(S, w, 1.0 / 17.0);
-  S = fma(S, w, 1.0 / 15.0);
-  S = fma(S, w, 1.0 / 13.0);
-  S = fma(S, w, 1.0 / 11.0);
-  S = fma(S, w, 1.0 / 9.0);
-  S = fma(S, w, 1.0 / 7.0);
-  S = fma(S, w, 1.0 / 5.0);
-  S = fma(S, w, 1.0 / 3.0);
+  double S = 1.0 / 21.0;  // S(w) = sum w^i / (2i + 3), i = 9 .. 0 by Horner
+#pragma unroll
+  for (int i = 8; i >= 0; --i) S = fma(S, w, scalar_const(1.0 / (2 * i + 3)));
   const double tail = 2.0 * (s * w) * S;
   const double q0 = fma(s, d, -tail);
   constexpr double kLn2Hi = 6.93147180369123816490e-01;  // high 32 bits of log 2
@@ -310,7 +318,7 @@ __device__ __forceinline__ double nh_energy(const T G[DIM][DIM], double C1, doub
 // Density and first Piola stress P = dW/dF at F = I + G from one set of invariants:
 //   P = 2 C1 (J F - cof F) / J + 2 D1 (J - 1) cof F,  J = det F,
 // with (3D) J F - cof F = (s2 + det G) I + J G + G^T - cof G, cof F = (1 + tr G) I - G^T + cof G,
-// so that with a = 2 C1 / J, b = 2 D1 (J - 1):
+// so that with a = 2 C1 / J (a J = 2 C1), b = 2 D1 (J - 1):
 //   P = a J G + (a - b)(G^T - cof G) + (a (s2 + det G) + b (1 + tr G)) I;
 // (2D) J F - cof F = det G I + J G + G^T, cof F = I + cof G = (1 + tr G) I - G^T:
 //   P = a J G + (a - b) G^T + (a det G + b (1 + tr G)) I.
@@ -322,8 +330,14 @@ __device__ __forceinline__ double nh_energy_stress(const T G[DIM][DIM], double C
   const double W = nh_density<DIM, T>(v, C1, D1, bad);
   const T delta = v.tr + v.s2 + v.dG;
   const T J = T(1) + delta;
-  const T a = T(2) * (T)C1 / J, bcoef = T(2) * (T)D1 * delta;
-  const T alpha = a * J, beta = a - bcoef;
+  // a = 2 C1 / J (in float by the hardware reciprocal, within 1 ulp); a J = 2 C1 exactly
+  T a;
+  if constexpr (std::is_same<T, float>::value)
+    a = T(2) * (T)C1 * __builtin_amdgcn_rcpf(J);
+  else
+    a = T(2) * (T)C1 / J;
+  const T bcoef = T(2) * (T)D1 * delta;
+  const T alpha = T(2) * (T)C1, beta = a - bcoef;
   const T gamma = mad(a, v.s2 + v.dG, bcoef * (T(1) + v.tr));
 #pragma unroll
   for (int j = 0; j < DIM; ++j)
