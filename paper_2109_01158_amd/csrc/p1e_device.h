@@ -322,10 +322,11 @@ __device__ __forceinline__ double nh_energy(const T G[DIM][DIM], double C1, doub
 //   P = a J G + (a - b)(G^T - cof G) + (a (s2 + det G) + b (1 + tr G)) I;
 // (2D) J F - cof F = det G I + J G + G^T, cof F = I + cof G = (1 + tr G) I - G^T:
 //   P = a J G + (a - b) G^T + (a det G + b (1 + tr G)) I.
-// The density is bitwise the one of nh_energy.
+// P comes out multiplied by vol (the element size, folded into the three coefficients). The
+// density is bitwise the one of nh_energy.
 template <int DIM, typename T>
 __device__ __forceinline__ double nh_energy_stress(const T G[DIM][DIM], double C1, double D1,
-                                                   bool &bad, T P[DIM][DIM]) {
+                                                   T vol, bool &bad, T P[DIM][DIM]) {
   const NhInv<DIM, T> v = nh_invariants<DIM, T>(G);
   const double W = nh_density<DIM, T>(v, C1, D1, bad);
   const T delta = v.tr + v.s2 + v.dG;
@@ -337,8 +338,8 @@ __device__ __forceinline__ double nh_energy_stress(const T G[DIM][DIM], double C
   else
     a = T(2) * (T)C1 / J;
   const T bcoef = T(2) * (T)D1 * delta;
-  const T alpha = T(2) * (T)C1, beta = a - bcoef;
-  const T gamma = mad(a, v.s2 + v.dG, bcoef * (T(1) + v.tr));
+  const T alpha = T(2) * (T)C1 * vol, beta = (a - bcoef) * vol;
+  const T gamma = mad(a, v.s2 + v.dG, bcoef * (T(1) + v.tr)) * vol;
 #pragma unroll
   for (int j = 0; j < DIM; ++j)
 #pragma unroll
@@ -390,16 +391,16 @@ __device__ __forceinline__ double pl_energy(const T g[DIM], double p, bool &bad)
   return W;
 }
 
-// the density and its gradient |g|^(p-2) g (0 at g = 0) from one power |g|^p; the density
-// is bitwise the one of pl_energy
+// the density and vol times its gradient, vol |g|^(p-2) g (0 at g = 0), from one power |g|^p;
+// the density is bitwise the one of pl_energy
 template <int DIM, typename T>
-__device__ __forceinline__ double pl_energy_stress(const T g[DIM], double p, bool &bad,
+__device__ __forceinline__ double pl_energy_stress(const T g[DIM], double p, T vol, bool &bad,
                                                    T P[DIM]) {
   const T s = pl_norm2<DIM, T>(g);
   const double sp = half_pow((double)s, p);
   const double W = sp / p;
   if (!isfinite(W)) bad = true;
-  const T sc = s > T(0) ? (T)(sp / (double)s) : T(0);
+  const T sc = s > T(0) ? (T)(sp / (double)s) * vol : T(0);
 #pragma unroll
   for (int m = 0; m < DIM; ++m) P[m] = sc * g[m];
   return W;
@@ -481,9 +482,9 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
   double W;
   T P[D][DIM];
   if constexpr (MODE == MODE_FORCE && KIND == P1E_NEOHOOKE) {
-    W = nh_energy_stress<DIM, T>(G, prm.C1, prm.D1, bad, P);
+    W = nh_energy_stress<DIM, T>(G, prm.C1, prm.D1, vol, bad, P);  // P = |T| dW/dF
   } else if constexpr (MODE == MODE_FORCE) {
-    W = pl_energy_stress<DIM, T>(G[0], prm.p, bad, P[0]);
+    W = pl_energy_stress<DIM, T>(G[0], prm.p, vol, bad, P[0]);
   } else {
     W = density<DIM, D, KIND, T>(G, prm, bad);
   }
@@ -498,7 +499,6 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
         T acc = T(0);
 #pragma unroll
         for (int m = 0; m < DIM; ++m) acc = mad(P[j][m], Bi[l - 1][m], acc);
-        acc *= vol;
         out[l * D + j] = acc;
         out[j] -= acc;
       }
@@ -724,7 +724,8 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
   static_assert(NW <= 16, "per-wavefront shares in LDS");
   const int lane = tid & 63, wave = tid >> 6;
   {
-    const double wb = wave_sum(sb + cb);  // this wavefront's share of b.v
+    // this wavefront's share of b.v (none in wavefronts past the tile's nodes: uniform test)
+    const double wb = (NPT > 1 || wave * 64 < nloc) ? wave_sum(sb + cb) : 0.0;
     if (lane == 0) sh.red[NW + wave] = wb;
   }
   __syncthreads();
