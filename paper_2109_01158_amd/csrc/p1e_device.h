@@ -578,7 +578,8 @@ struct alignas(16) TileShared {
 // rounds of 4 whose LDS reads are issued together; absent slots read a zero record) and
 // combine their sums, so every lane holds the same value. A node whose whole patch lies in
 // the tile writes g = scale * (sum - b) in free-DOF order; the others write the sum to their
-// halo slot. Node records are read again (they were loaded by the staging threads).
+// halo slot. The record of a lane's first node comes from the caller (loaded before the
+// element pass, so its latency is hidden); b is loaded before the LDS sums.
 template <class SH>
 struct DIM_OF_SH {
   static constexpr int K = SH::K;
@@ -586,11 +587,20 @@ struct DIM_OF_SH {
 template <int D, typename T, int NT, int GL, class SH>
 __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int nloc,
                                                 const double *__restrict__ scale,
-                                                double *__restrict__ g, SH &sh) {
+                                                double *__restrict__ g, SH &sh, int4 rec0) {
   const int sub = threadIdx.x % GL;
   for (int a = threadIdx.x / GL; a < nloc; a += NT / GL) {
-    const int4 rec = M.trec[r0 + a];
+    const int4 rec = a < NT / GL ? rec0 : M.trec[r0 + a];  // rec0: loaded by the caller
     if (rec.w == 0) continue;  // no free DOF (uniform over the node's lanes)
+    const int mask = rec.y & 7, fb = rec.y >> 3;
+    const bool complete = rec.z & 1;
+    double bj[D];  // b of a complete node's free DOFs, loaded ahead of the sums
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      bj[j] = 0.0;
+      if (complete && sub == 0 && ((mask >> j) & 1))
+        bj[j] = M.bhat[fb + __popc(mask & ((1 << j) - 1))];
+    }
     double acc[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) acc[j] = 0.0;
@@ -616,14 +626,13 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
       for (int j = 0; j < D; ++j) acc[j] += dpp_double<0xb1>(acc[j]);
     }
     if (sub != 0) continue;
-    const int mask = rec.y & 7;
-    int f = rec.y >> 3;
-    if (rec.z & 1) {
+    if (complete) {
       const double sc = scale ? *scale : 1.0;
+      int f = fb;
 #pragma unroll
       for (int j = 0; j < D; ++j)
         if ((mask >> j) & 1) {
-          g[f] = sc * (acc[j] - M.bhat[f]);
+          g[f] = sc * (acc[j] - bj[j]);
           ++f;
         }
     } else {
@@ -660,7 +669,16 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
   const int tid = threadIdx.x;
   const int4 ta = M.ttile[t], tb = M.ttile[t + 1];
   const int e0 = ta.x, net = tb.x - ta.x, r0 = ta.y, nloc = tb.y - ta.y;
-  // 0. independent loads; lanes past the tile's end read its last element
+  // 0. independent loads, node records first (the nodal loads depend on them); the patch
+  // entries and the class table go to registers here and to LDS once the nodal loads are in
+  // flight, so that a tile waits for two memory round trips, not four. Lanes past the tile's
+  // end read its last element.
+  int4 rec[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int a = k * NT + tid;
+    rec[k] = a < nloc ? M.trec[r0 + a] : make_int4(0, 0, 0, 0);
+  }
   int nd[EPT][K], cl[EPT];
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
@@ -669,46 +687,70 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
     for (int l = 0; l < K; ++l) nd[k][l] = stream_load(M.conn_loc + (int64_t)l * M.ne + e);
     cl[k] = CLS ? (int)stream_load(M.geo_cls + e) : 0;
   }
-  int4 rec[NPT];
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int a = k * NT + tid;
-    rec[k] = a < nloc ? M.trec[r0 + a] : make_int4(0, 0, 0, 0);
-  }
+  constexpr int LQ = (K * kTileElems / kEntAlign + NT - 1) / NT;  // 16-byte entry groups
+  constexpr int TQ = (kMaxGeoClasses * REC + NT - 1) / NT;
+  const int nlq = (tb.z - ta.z) / kEntAlign, ntq = CLS ? M.nclass * REC : 0;
+  uint4 lq[LQ];
+  T tq[TQ];
   if constexpr (MODE != MODE_ENERGY) {
     const uint4 *src = reinterpret_cast<const uint4 *>(M.tlent + ta.z);
-    uint4 *dst = reinterpret_cast<uint4 *>(sh.lent);
-    for (int q = tid; q < (tb.z - ta.z) / kEntAlign; q += NT) dst[q] = src[q];
+#pragma unroll
+    for (int i = 0; i < LQ; ++i)
+      if (i * NT + tid < nlq) lq[i] = src[i * NT + tid];
   }
-  if constexpr (CLS)
-    for (int q = tid; q < M.nclass * REC; q += NT) sh.tab[q] = geo[q];
-  if constexpr (MODE != MODE_ENERGY)
-    if (tid < D) sh.fs[K * kTileElems * D + tid] = T(0);
-  // 1. nodal field of the tile; b.v of the nodes this tile owns
+  if constexpr (CLS) {
+#pragma unroll
+    for (int i = 0; i < TQ; ++i)
+      if (i * NT + tid < ntq) tq[i] = geo[i * NT + tid];
+  }
+  // 1. nodal field of the tile; b.v of the nodes this tile owns. Per node all loads first
+  // (one memory round trip), then the arithmetic; component j's DOF is the node's first free
+  // DOF plus the free components before j.
   double sb = 0.0, cb = 0.0;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int a = k * NT + tid;
+    const int mask = rec[k].y & 7;
+    double w[D], vj[D], bj[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) w[j] = 0.0, vj[j] = 0.0, bj[j] = 0.0;
     if (a < nloc) {
-      const int gi = rec[k].x, mask = rec[k].y & 7;
-      const bool owner = (rec[k].z >> 1) & 1;
-      int fb = rec[k].y >> 3;
+      const int gi = rec[k].x, fb = rec[k].y >> 3;
+#pragma unroll
+      for (int j = 0; j < D; ++j) w[j] = M.wref[(int64_t)gi * D + j];
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if ((mask >> j) & 1) {
+          const int f = fb + __popc(mask & ((1 << j) - 1));
+          vj[j] = vhat[f];
+          bj[j] = M.bhat[f];
+        }
+    }
+    if (k == 0) {  // registers -> LDS while the nodal loads are in flight
+      if constexpr (MODE != MODE_ENERGY) {
+        uint4 *dst = reinterpret_cast<uint4 *>(sh.lent);
+#pragma unroll
+        for (int i = 0; i < LQ; ++i)
+          if (i * NT + tid < nlq) dst[i * NT + tid] = lq[i];
+        if (tid < D) sh.fs[K * kTileElems * D + tid] = T(0);
+      }
+      if constexpr (CLS) {
+#pragma unroll
+        for (int i = 0; i < TQ; ++i)
+          if (i * NT + tid < ntq) sh.tab[i * NT + tid] = tq[i];
+      }
+    }
+    if (a < nloc) {
       T o[D];
       double bvn = 0.0;  // b.v of this node's free DOFs
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        const double w = M.wref[(int64_t)gi * D + j];
-        double val = w;
-        if ((mask >> j) & 1) {
-          const double vj = vhat[fb];
-          val = vj - w;
-          bvn = fma(M.bhat[fb], vj, bvn);
-          ++fb;
-        }
-        o[j] = (T)val;
+        const bool fr = (mask >> j) & 1;
+        o[j] = (T)(fr ? vj[j] - w[j] : w[j]);
+        if (fr) bvn = fma(bj[j], vj[j], bvn);
       }
       NodeVec<T, D>::store(sh.us, a, o);
-      if (owner) {
+      if ((rec[k].z >> 1) & 1) {  // owner
         if (NPT == 1) {
           sb = bvn;
         } else {
@@ -729,6 +771,12 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
     if (lane == 0) sh.red[NW + wave] = wb;
   }
   __syncthreads();
+  // the first node record of the patch-sum phase, loaded ahead of the element pass
+  int4 prec = make_int4(0, 0, 0, 0);
+  if constexpr (MODE != MODE_ENERGY) {
+    const int a = nloc <= NT / 2 ? tid / 2 : tid;
+    if (a < nloc) prec = M.trec[r0 + a];
+  }
   // 2. elements
   double s = 0.0, c = 0.0;
   int cnt = 0;
@@ -760,9 +808,9 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
   if constexpr (MODE != MODE_ENERGY) {
     __syncthreads();
     if (nloc <= NT / 2)
-      tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh);
+      tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh, prec);
     else
-      tile_patch_sums<D, T, NT, 1>(M, r0, nloc, scale, g, sh);
+      tile_patch_sums<D, T, NT, 1>(M, r0, nloc, scale, g, sh, prec);
   }
   // 4. partials: compensated sums of the per-wavefront shares
   __syncthreads();
