@@ -65,12 +65,17 @@ __global__ __launch_bounds__((batch_tile_threads<T>())) void kb_tile(EngineDev E
     const SlotDev &S = E.slots[st.x];
     const Params prm{S.C1, S.D1, S.p, 0.0};
     const T *geo = sizeof(T) == 4 ? (const T *)S.M.geo32 : (const T *)S.M.geo64;
-    if (S.M.geo_cls != nullptr)
-      tile_pass<DIM, D, KIND, T, MODE_FORCE, true, NT>(S.M, st.y, geo, S.vt, S.gt, nullptr,
-                                                       prm, sh);
-    else
-      tile_pass<DIM, D, KIND, T, MODE_FORCE, false, NT>(S.M, st.y, geo, S.vt, S.gt, nullptr,
-                                                        prm, sh);
+    using Split = TileSplit<DIM, NT>;
+    typename Split::Head h;
+    if (S.M.geo_cls != nullptr) {
+      tile_head<Split::NPT, NT>(S.M, st.y, h, threadIdx.x);
+      tile_pass<DIM, D, KIND, T, MODE_FORCE, true, NT>(S.M, h, geo, S.vt, S.gt, nullptr, prm,
+                                                       sh, threadIdx.x);
+    } else {
+      tile_head<Split::NPT, NT>(S.M, st.y, h, threadIdx.x);
+      tile_pass<DIM, D, KIND, T, MODE_FORCE, false, NT>(S.M, h, geo, S.vt, S.gt, nullptr, prm,
+                                                        sh, threadIdx.x);
+    }
   }
 }
 

@@ -143,6 +143,19 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// The tiles of a persistent grid of nb blocks (nb a multiple of the XCD count): block b works
+// on every (nb / X)-th tile of the contiguous range of XCD b % X, the same ranges as
+// xcd_tile with one block per tile. Returns the first tile (or n) and the step.
+__device__ __forceinline__ int xcd_first(int b, int nb, int n, int &end, int &step) {
+  constexpr int X = P1E_XCD_COUNT;
+  const int q = n / X, r = n % X;
+  const int x = b % X, k = b / X;
+  const int lo = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  end = lo + (x < r ? q + 1 : q);
+  step = nb / X;
+  return lo + k;
+}
+
 // explicit fused multiply-add: kernels are built without automatic contraction, so the
 // same expression rounds the same way in every kernel that uses it
 __device__ __forceinline__ float mad(float a, float b, float c) { return fmaf(a, b, c); }
@@ -567,7 +580,7 @@ struct alignas(16) TileShared {
   static constexpr int NENT = (K * kTileElems + kEntAlign - 1) / kEntAlign * kEntAlign;
   T us[kTileNodes * NS];
   T fs[MODE == MODE_ENERGY ? 4 : K * kTileElems * D + 4];  // + a zero record at the end
-  uint16_t lent[MODE == MODE_ENERGY ? kEntAlign : NENT];
+  uint16_t lent[MODE == MODE_ENERGY ? kEntAlign : NENT + kEntAlign];  // + slack read past rows
   T tab[CLS ? kMaxGeoClasses * REC : 4];
   double red[2 * 16];  // per-wavefront shares: energy, then b.v
   int nbad[16];
@@ -587,9 +600,11 @@ struct DIM_OF_SH {
 template <int D, typename T, int NT, int GL, class SH>
 __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int nloc,
                                                 const double *__restrict__ scale,
-                                                double *__restrict__ g, SH &sh, int4 rec0) {
-  const int sub = threadIdx.x % GL;
-  for (int a = threadIdx.x / GL; a < nloc; a += NT / GL) {
+                                                double *__restrict__ g, SH &sh, int4 rec0,
+                                                int tid) {
+  static_assert(3 * GL <= kEntAlign, "reads past a row stay within the entry slack");
+  const int sub = tid % GL;
+  for (int a = tid / GL; a < nloc; a += NT / GL) {
     const int4 rec = a < NT / GL ? rec0 : M.trec[r0 + a];  // rec0: loaded by the caller
     if (rec.w == 0) continue;  // no free DOF (uniform over the node's lanes)
     const int mask = rec.y & 7, fb = rec.y >> 3;
@@ -609,7 +624,10 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
     for (int p = sub; p < n; p += 4 * GL) {
       int x[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = p + u * GL < n ? sh.lent[p0 + p + u * GL] : kZero;
+      for (int u = 0; u < 4; ++u) {  // read unconditionally (at most 3 GL past the row's end)
+        const int raw = sh.lent[p0 + p + u * GL];
+        x[u] = p + u * GL < n ? raw : kZero;
+      }
       T q[4][D];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -657,28 +675,55 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
 //     b.v -> part[ntiles + t], bad count.
 // Every order is fixed: the results do not depend on timing. No atomics.
 // geo: the global geometry arrays (or class table, staged in sh.tab when CLS).
-template <int DIM, int D, int KIND, typename T, int MODE, bool CLS, int NT, class SH>
-__device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__restrict__ geo,
-                                          const double *__restrict__ vhat,
-                                          double *__restrict__ g,
-                                          const double *__restrict__ scale, const Params &prm,
-                                          SH &sh) {
-  constexpr int K = DIM + 1, REC = DIM * DIM + 1;
-  constexpr int EPT = kTileElems / NT, NPT = kTileNodes / NT;
-  static_assert(EPT * NT == kTileElems && NPT * NT == kTileNodes, "tile split");
-  const int tid = threadIdx.x;
-  const int4 ta = M.ttile[t], tb = M.ttile[t + 1];
-  const int e0 = ta.x, net = tb.x - ta.x, r0 = ta.y, nloc = tb.y - ta.y;
-  // 0. independent loads, node records first (the nodal loads depend on them); the patch
-  // entries and the class table go to registers here and to LDS once the nodal loads are in
-  // flight, so that a tile waits for two memory round trips, not four. Lanes past the tile's
-  // end read its last element.
+// What a tile's pass reads first: its bounds and its node records (the nodal loads depend
+// on them). A persistent caller loads the next tile's head while the current tile sums its
+// patches, so that a tile starts with one memory round trip instead of two.
+template <int NPT>
+struct TileHead {
+  int t;
+  int4 ta, tb;  // ttile[t], ttile[t + 1]
   int4 rec[NPT];
+};
+
+// records past the tile's nodes are zero
+template <int NPT, int NT>
+__device__ __forceinline__ void tile_head(const TileMesh &M, int t, TileHead<NPT> &h, int tid) {
+  h.t = t;
+  h.ta = M.ttile[t];
+  h.tb = M.ttile[t + 1];
+  const int r0 = h.ta.y, nloc = h.tb.y - h.ta.y;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int a = k * NT + tid;
-    rec[k] = a < nloc ? M.trec[r0 + a] : make_int4(0, 0, 0, 0);
+    h.rec[k] = a < nloc ? M.trec[r0 + a] : make_int4(0, 0, 0, 0);
   }
+}
+
+template <int DIM, int NT>
+struct TileSplit {
+  static constexpr int K = DIM + 1, EPT = kTileElems / NT, NPT = kTileNodes / NT;
+  static_assert(EPT * NT == kTileElems && NPT * NT == kTileNodes, "tile split");
+  using Head = TileHead<NPT>;
+};
+
+template <int DIM, int D, int KIND, typename T, int MODE, bool CLS, int NT, class SH>
+__device__ __forceinline__ void tile_pass(const TileMesh &M,
+                                          const typename TileSplit<DIM, NT>::Head &h,
+                                          const T *__restrict__ geo,
+                                          const double *__restrict__ vhat,
+                                          double *__restrict__ g,
+                                          const double *__restrict__ scale, const Params &prm,
+                                          SH &sh, int tid, int tnext = -1,
+                                          typename TileSplit<DIM, NT>::Head *next = nullptr) {
+  constexpr int K = DIM + 1, REC = DIM * DIM + 1;
+  constexpr int EPT = TileSplit<DIM, NT>::EPT, NPT = TileSplit<DIM, NT>::NPT;
+  const int t = h.t;
+  const int4 ta = h.ta, tb = h.tb;
+  const int e0 = ta.x, net = tb.x - ta.x, r0 = ta.y, nloc = tb.y - ta.y;
+  const auto &rec = h.rec;
+  // 0. independent loads: the elements' local connectivity and classes (lanes past the tile's
+  // end read its last element), the patch entries and the class table (to registers here,
+  // to LDS once the nodal loads are in flight; the node records are the head's).
   int nd[EPT][K], cl[EPT];
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
@@ -796,6 +841,8 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
                                                           kTileElems, le, prm, s, c, cnt);
     }
   }
+  // the next tile's head: in flight while this tile sums its patches
+  if (next != nullptr && tnext >= 0) tile_head<NPT, NT>(M, tnext, *next, tid);
   {
     const double wj = wave_sum(s + c);  // this wavefront's share of the energy
     const int wn = wave_count(cnt);
@@ -808,9 +855,9 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M, int t, const T *__r
   if constexpr (MODE != MODE_ENERGY) {
     __syncthreads();
     if (nloc <= NT / 2)
-      tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh, prec);
+      tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh, prec, tid);
     else
-      tile_patch_sums<D, T, NT, 1>(M, r0, nloc, scale, g, sh, prec);
+      tile_patch_sums<D, T, NT, 1>(M, r0, nloc, scale, g, sh, prec, tid);
   }
   // 4. partials: compensated sums of the per-wavefront shares
   __syncthreads();

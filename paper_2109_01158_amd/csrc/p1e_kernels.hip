@@ -2,10 +2,11 @@
 //
 // One call of the library is a short chain of kernels on the caller's stream:
 //
-//   k_tile      one workgroup per element tile: the tile's nodal field u (u = v - x for
-//               Neo-Hookean, u = v for the p-Laplacian) staged in LDS; per element G = grad u
-//               (eq. Dv), the density W (eqs. neoHook, pLaplacian) and |T| W into a
-//               compensated block sum (eq. Denergy), and, by mode, the element forces
+//   k_tile      per element tile (one per workgroup; in FP64 a persistent grid): the tile's
+//               nodal field u (u = v - x for Neo-Hookean, u = v for the p-Laplacian) staged in
+//               LDS; per element G = grad u (eq. Dv), the density W (eqs. neoHook,
+//               pLaplacian) and |T| W into a compensated block sum (eq. Denergy), and, by
+//               mode, the element forces
 //               |T| dW/dF grad phi_l (Section 6.2) or the per-element central differences
 //               of |T| W under the perturbation of one row of F (Section 6.1) in LDS; then
 //               per node of the tile the part of its patch sum (Section 4.2) that lies in the
@@ -49,16 +50,42 @@ constexpr int tile_threads() {
 template <typename T, int MODE>
 constexpr int tile_waves_per_eu() { return sizeof(T) == 4 ? 2 * tile_threads<T, MODE>() / 256 : 1; }
 
+// FP64 tiles (one per CU, registers to spare) run as a persistent grid that hides the
+// loads of a tile's head behind the previous tile; FP32 tiles (two per CU, 64 registers)
+// would spill the carried head, and run one per workgroup.
+template <typename T>
+constexpr bool tile_persistent() { return sizeof(T) == 8; }
+
 template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
 __global__ __launch_bounds__((tile_threads<T, MODE>())) __attribute__((amdgpu_waves_per_eu(tile_waves_per_eu<T, MODE>()))) void k_tile(TileMesh M,
                                                                   const T *__restrict__ geo,
                                                                   const double *__restrict__ vhat,
                                                                   double *__restrict__ g,
                                                                   Params prm) {
+  constexpr int NT = tile_threads<T, MODE>();
+  using Head = typename TileSplit<DIM, NT>::Head;
   __shared__ TileShared<DIM, D, T, MODE, CLS> sh;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
-  tile_pass<DIM, D, KIND, T, MODE, CLS, tile_threads<T, MODE>()>(M, t, geo, vhat, g, nullptr,
-                                                                 prm, sh);
+  if constexpr (!tile_persistent<T>()) {  // one tile per workgroup
+    Head h;
+    tile_head<TileSplit<DIM, NT>::NPT, NT>(M, xcd_tile(blockIdx.x, gridDim.x), h, threadIdx.x);
+    tile_pass<DIM, D, KIND, T, MODE, CLS, NT>(M, h, geo, vhat, g, nullptr, prm, sh,
+                                              threadIdx.x);
+    return;
+  }
+  int end, step;
+  int t = xcd_first(blockIdx.x, gridDim.x, M.ntiles, end, step);
+  if (t >= end) return;
+  // persistent: each tile loads the next one's head while it sums its patches
+  Head h, hn;
+  tile_head<TileSplit<DIM, NT>::NPT, NT>(M, t, h, threadIdx.x);
+  for (;;) {
+    const int tn = t + step < end ? t + step : -1;
+    tile_pass<DIM, D, KIND, T, MODE, CLS, NT>(M, h, geo, vhat, g, nullptr, prm, sh,
+                                              threadIdx.x, tn, &hn);
+    if (tn < 0) break;
+    h = hn;
+    t = tn;
+  }
 }
 
 // Deterministic compensated sums of the tiles' partials by one block of NT threads:
@@ -168,6 +195,34 @@ int check_launch(const char *what) {
 
 Params params_of(const p1e_mesh *m, double eps) { return Params{m->C1, m->D1, m->p, eps}; }
 
+// Blocks of a persistent grid over n tiles: as many as the device holds at once (occupancy
+// query, once per kernel and device), at most n, rounded up to a multiple of the XCD count.
+template <typename F>
+int persistent_grid(F kernel, int nt, int64_t n) {
+  static int cached_dev = -1, resident = 0;  // per kernel instantiation
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev != cached_dev) {
+    int per_cu = 0, cus = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    resident = std::max(1, per_cu) * std::max(1, cus);
+    cached_dev = dev;
+  }
+  constexpr int X = P1E_XCD_COUNT;
+  const int64_t nb = std::min<int64_t>(n, resident);
+  return (int)((nb + X - 1) / X * X);
+}
+
+template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
+void launch_tile_kernel(p1e_mesh *m, const T *geo, const double *vhat, double *g, double eps,
+                        hipStream_t s) {
+  constexpr int NT = tile_threads<T, MODE>();
+  auto kern = k_tile<DIM, D, KIND, T, MODE, CLS>;
+  const int nb = tile_persistent<T>() ? persistent_grid(kern, NT, m->ntiles) : (int)m->ntiles;
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(NT), 0, s, m->dev, geo, vhat, g, params_of(m, eps));
+}
+
 template <int DIM, int D, int KIND, typename T, int MODE>
 int launch_tile(p1e_mesh *m, const T *geo, const double *vhat, double *g, double eps,
                 hipStream_t s) {
@@ -176,13 +231,10 @@ int launch_tile(p1e_mesh *m, const T *geo, const double *vhat, double *g, double
                      : MODE == MODE_FORCE ? "k_tile_force"
                                           : "k_tile_fd";
   prof_begin(name, s);
-  constexpr int NT = tile_threads<T, MODE>();
   if (m->dev.geo_cls != nullptr)
-    hipLaunchKernelGGL((k_tile<DIM, D, KIND, T, MODE, true>), dim3(m->ntiles), dim3(NT), 0, s,
-                       m->dev, geo, vhat, g, params_of(m, eps));
+    launch_tile_kernel<DIM, D, KIND, T, MODE, true>(m, geo, vhat, g, eps, s);
   else
-    hipLaunchKernelGGL((k_tile<DIM, D, KIND, T, MODE, false>), dim3(m->ntiles), dim3(NT), 0, s,
-                       m->dev, geo, vhat, g, params_of(m, eps));
+    launch_tile_kernel<DIM, D, KIND, T, MODE, false>(m, geo, vhat, g, eps, s);
   prof_end(s);
   return check_launch(name);
 }
