@@ -2,8 +2,9 @@
 
 One step = one energy-and-gradient evaluation through the autograd hook
 (``p1_energy(vhat).backward()``: element tiles with energy, forces and in-tile patch sums,
-halo rows, compensated finalize, scaled gradient) on the 460x46x46-cube Kuhn box (5,840,160 tets), mixed precision, inputs resident in
-HBM. Prints ONE JSON line. Extra fields report the FP64 path, the patch central-difference
+halo rows, compensated finalize; the backward scales the forward's gradient buffer in place,
+which writes nothing for dJ/dJ = 1) on the 460x46x46-cube Kuhn box (5,840,160 tets), mixed
+precision, inputs resident in HBM. Prints ONE JSON line. Extra fields report the FP64 path, the patch central-difference
 gradient on the same mesh, the serving benchmark (256 minimization requests, Poisson arrivals,
 continuous batching vs one-at-a-time FP64 solves: req/s, p50/p99 latency), the dominant kernel against the HBM roofline (HIP events around
 each kernel over a second pass of the same K steps) and the FP64 oracle timed on the host CPU.
@@ -51,7 +52,8 @@ def algorithmic_bytes(info, prec, classed):
     g written (rows complete in one tile); per free row its row info 4 B; the halo partial
     sums 8d B per slot written. k_halo: per halo row 8 B of row index and pointer, its row
     info 4 B, b read and g written (8d B each); per slot its index 4 B and partial 8d B
-    read. k_scale: the kept gradient read and g written."""
+    read. k_scale_inplace: the incoming gradient is 1 here, so the kernel reads its 8-byte
+    scale and writes nothing (with another scale: 16 B per free DOF)."""
     ne, nn, nf, nfd, nnz = (info["ne"], info["nn"], info["n_free_nodes"], info["n_free_dofs"],
                             info["nnz"])
     dim, d = info["dim"], info["ncomp"]
@@ -62,8 +64,7 @@ def algorithmic_bytes(info, prec, classed):
     tile = (ne * 2 * (dim + 1) + geo + 2 * nnz + 14 * tn + nn * (4 + 8 * d) + 16 * nfd
             + 4 * nf + 8 * complete_dofs + 8 * d * ns)
     halo = nh * (12 + 16 * d) + ns * (4 + 8 * d)
-    scale = 16 * nfd
-    return {"k_tile_force": tile, "k_halo": halo, "k_scale": scale}
+    return {"k_tile_force": tile, "k_halo": halo, "k_scale_inplace": 0}
 
 
 def kernel_source_hash():

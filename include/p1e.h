@@ -164,6 +164,13 @@ int p1e_energy_forces(p1e_mesh *mesh, const double *vhat, int prec, double *out3
                       int32_t *flag, void *stream);
 int p1e_grad_gather(p1e_mesh *mesh, int prec, const double *scale, double *g, void *stream);
 
+/* The backward pass of a differentiation hook whose forward pass wrote the exact gradient
+ * (p1e_grad_exact, Section 6.2) into a buffer of its own: g[n] *= s in place for the
+ * mesh's n_free_dofs entries, s = *scale (a device double, not NULL). When s == 1 the kernel
+ * writes nothing (every product would return g[n] bitwise). g: device, caller-owned. Stream
+ * ordered. P1E_ESTATE if the mesh is not bound. */
+int p1e_grad_scale(p1e_mesh *mesh, const double *scale, double *g, void *stream);
+
 /* Patch central differences (Section 6.1, eqs. CD, CDS, sumpatch), FP64 throughout:
  * g[n] = [sum_{T in T^(n)} |T| W(F_T(v + eps e_n)) - sum |T| W(F_T(v - eps e_n))]/(2 eps) - b_n
  * with an absolute step eps > 0 for every DOF. Only the perturbed row of F_T changes

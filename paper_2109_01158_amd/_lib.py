@@ -123,6 +123,7 @@ def lib():
         "p1e_grad_patch_fd": ([vp, vp, dbl, vp, vp, vp], ctypes.c_int),
         "p1e_energy_forces": ([vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "p1e_grad_gather": ([vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
+        "p1e_grad_scale": ([vp, vp, vp, vp], ctypes.c_int),
         "p1e_last_error": ([], ctypes.c_char_p),
         "p1e_minimize_workspace_bytes": ([vp, ctypes.POINTER(LbfgsOpts)], u64),
         "p1e_minimize": ([vp, vp, ctypes.POINTER(LbfgsOpts), vp, u64, ctypes.POINTER(MinReport),

@@ -106,6 +106,13 @@ def grad_gather(handle, prec, scale, g, stream=None):
                                   _stream_ptr(stream, g.device)))
 
 
+def grad_scale(handle, scale, g, stream=None):
+    """p1e_grad_scale: g *= scale in place (a device 1-element f64 tensor); no write when the
+    scale is 1."""
+    check(L.lib().p1e_grad_scale(ctypes.c_void_p(handle), _dptr(scale), _dptr(g),
+                                 _stream_ptr(stream, g.device)))
+
+
 def grad_patch_fd(handle, vhat, eps, g, flag, stream=None):
     """p1e_grad_patch_fd on device tensors."""
     check(L.lib().p1e_grad_patch_fd(ctypes.c_void_p(handle), _dptr(vhat), float(eps), _dptr(g),
@@ -227,6 +234,15 @@ class Mesh:
         """g = scale * (the gradient kept by the last energy_forces call)."""
         g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device) if g is None else g
         grad_gather(self.handle, prec, scale, g, stream)
+        return g
+
+    def grad_scale(self, g, scale, stream=None):
+        """g *= scale in place (scale: device f64 tensor of one element); returns g."""
+        if g.dtype != torch.float64 or not g.is_contiguous() or g.numel() != self.n_free_dofs:
+            raise ValueError("g must be a contiguous float64 tensor of n_free_dofs entries")
+        if scale.dtype != torch.float64 or scale.numel() != 1 or scale.device != g.device:
+            raise ValueError("scale must be one float64 value on the device of g")
+        grad_scale(self.handle, scale, g, stream)
         return g
 
     def grad_patch_fd(self, vhat, eps, stream=None):

@@ -3,11 +3,11 @@
 ``P1Energy.apply(vhat, mesh, prec)`` returns the 0-d energy J(vhat) on the device.
 
 When ``vhat`` requires grad, the forward pass computes the energy and the exact gradient in
-one pass over the mesh (``p1e_energy_forces``, which keeps the gradient on the device), and
-the backward pass scales the kept gradient by the incoming gradient, a device-side scalar
-(``p1e_grad_gather``). If another call rewrote the kept gradient between the two passes,
-backward recomputes it at the saved input. The bad-element count of the forward pass is kept
-on ``mesh.last_flag``.
+one pass over the mesh (``p1e_grad_exact``) into a fresh device buffer held by the autograd
+context, and the backward pass hands that buffer back scaled in place by the incoming
+gradient, a device-side scalar (``p1e_grad_scale``, which writes nothing when the scale is 1).
+A second backward through the same graph (``retain_graph=True``) recomputes the gradient at
+the saved input. The bad-element count of the forward pass is kept on ``mesh.last_flag``.
 """
 
 import torch
@@ -17,9 +17,9 @@ class P1Energy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vhat, mesh, prec="mixed"):
         if vhat.requires_grad:
-            out3, flag, gen = mesh.energy_forces(vhat.detach(), prec)
+            g, out3, flag = mesh.grad_exact(vhat.detach(), prec)
             ctx.save_for_backward(vhat)
-            ctx.gen = gen
+            ctx.g = g
         else:
             out3, flag = mesh.energy(vhat, prec)
         ctx.mesh, ctx.prec = mesh, prec
@@ -31,12 +31,10 @@ class P1Energy(torch.autograd.Function):
         (vhat,) = ctx.saved_tensors
         mesh = ctx.mesh
         scale = grad_j.reshape(1).to(torch.float64).contiguous()
-        if mesh.forces_gen == ctx.gen:
-            g = mesh.grad_gather(ctx.prec, scale=scale)
-        else:
-            mesh.energy_forces(vhat, ctx.prec)
-            g = mesh.grad_gather(ctx.prec, scale=scale)
-        return g, None, None
+        g, ctx.g = ctx.g, None  # handed over: autograd may keep it as vhat.grad
+        if g is None:
+            g, _, _ = mesh.grad_exact(vhat.detach(), ctx.prec)
+        return mesh.grad_scale(g, scale), None, None
 
 
 def p1_energy(vhat, mesh, prec="mixed"):

@@ -71,8 +71,8 @@ void prof_end(hipStream_t s) {
 static uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  uint64_t wref, bhat, conn_loc, geo64, geo32, geo_cls, ttile, trec, tlent, hrec, hpart, gw,
-      part, badp, total;
+  uint64_t wref, bhat, conn_loc, geo64, geo32, geo_cls, ttile, trec, tprec, tlent, hrec, hpart,
+      gw, part, badp, total;
 };
 
 static Layout make_layout(const p1e_mesh *m, int modes) {
@@ -94,6 +94,7 @@ static Layout make_layout(const p1e_mesh *m, int modes) {
   L.geo_cls = take(m->nclass ? (uint64_t)m->ne : 0);
   L.ttile = take(4ull * m->ttile.size());
   L.trec = take(4ull * m->trec.size());
+  L.tprec = take(4ull * m->tprec.size());
   L.tlent = take(2ull * m->tlent.size());
   L.hrec = take(4ull * m->hrec.size());
   L.hpart = take(8ull * m->nslots * m->d);
@@ -556,6 +557,7 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
             up(L.geo_cls, m->geo_cls.data(), m->geo_cls.size()) &&
             up(L.ttile, m->ttile.data(), 4 * m->ttile.size()) &&
             up(L.trec, m->trec.data(), 4 * m->trec.size()) &&
+            up(L.tprec, m->tprec.data(), 4 * m->tprec.size()) &&
             up(L.tlent, m->tlent.data(), 2 * m->tlent.size()) &&
             up(L.hrec, m->hrec.data(), 4 * m->hrec.size());
   hipError_t se = hipStreamSynchronize(s);
@@ -577,6 +579,7 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
   D.nclass = m->nclass;
   D.ttile = (const int4 *)(base + L.ttile);
   D.trec = (const int4 *)(base + L.trec);
+  D.tprec = (const int4 *)(base + L.tprec);
   D.tlent = (const uint16_t *)(base + L.tlent);
   D.hrec = (const int4 *)(base + L.hrec);
   D.hpart = (double *)(base + L.hpart);
@@ -636,6 +639,14 @@ int p1e_grad_gather(p1e_mesh *m, int prec, const double *scale, double *g, void 
     return fail(P1E_ESTATE, "no gradient of this precision: call p1e_energy_forces first");
   if (!g && m->nfd > 0) return fail(P1E_EINVAL, "null output pointer");
   return run_scale(m, scale, g, (hipStream_t)stream);
+}
+
+int p1e_grad_scale(p1e_mesh *m, const double *scale, double *g, void *stream) {
+  if (!m) return fail(P1E_EINVAL, "null mesh");
+  if (!m->bound_modes) return fail(P1E_ESTATE, "mesh is not bound");
+  if (!scale) return fail(P1E_EINVAL, "null scale");
+  if (!g && m->nfd > 0) return fail(P1E_EINVAL, "null output pointer");
+  return run_scale_inplace(m, scale, g, (hipStream_t)stream);
 }
 
 int p1e_grad_patch_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t *flag,

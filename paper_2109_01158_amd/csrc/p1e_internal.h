@@ -55,7 +55,8 @@ struct TileMesh {
   // tiles
   const int4 *ttile = nullptr;  // [ntiles+1] {first element, first node record, first patch
                                 //  entry, 0}; the last one closes the ranges
-  const int4 *trec = nullptr;   // [sum nloc] tile node records
+  const int4 *trec = nullptr;   // [sum nloc] tile node records (staging order)
+  const int4 *tprec = nullptr;  // [sum nloc] the same nodes' patch records, longest row first
   const uint16_t *tlent = nullptr;  // local patch entries: offset (l kTileElems + e) d of the
                                     // element result in the tile's LDS, per node ascending e
   const int4 *hrec = nullptr;   // [nhalo] halo row records
@@ -86,6 +87,7 @@ struct p1e_mesh {
   std::vector<uint16_t> conn_loc;  // [k][ne]
   std::vector<int32_t> ttile;      // [ntiles+1][4]
   std::vector<int32_t> trec;       // [sum nloc][4]
+  std::vector<int32_t> tprec;      // [sum nloc][4]
   std::vector<uint16_t> tlent;
   std::vector<int32_t> hrec;       // [nhalo][4]
   int64_t ntiles = 0, nhalo = 0, nslots = 0, ntnodes = 0;
@@ -121,6 +123,7 @@ int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t 
 int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
                       hipStream_t s);
 int run_scale(p1e_mesh *m, const double *scale, double *g, hipStream_t s);
+int run_scale_inplace(p1e_mesh *m, const double *scale, double *g, hipStream_t s);
 
 }  // namespace p1e
 

@@ -186,6 +186,26 @@ __global__ __launch_bounds__(kBlock) void k_scale(int n, const double *__restric
   }
 }
 
+// g *= s in place, s = *scale read by every block; nothing to do (and nothing written) when
+// s == 1, where the product would return every g bitwise. Grid-stride over pairs of DOFs.
+__global__ __launch_bounds__(kBlock) void k_scale_inplace(int n, const double *__restrict__ scale,
+                                                          double *__restrict__ g) {
+  const double sc = *scale;
+  if (sc == 1.0) return;
+  const bool vec = (reinterpret_cast<uintptr_t>(g) & 15) == 0;
+  for (int64_t i = 2 * ((int64_t)blockIdx.x * kBlock + threadIdx.x); i < n;
+       i += 2 * (int64_t)kBlock * gridDim.x) {
+    if (vec && i + 1 < n) {
+      double2 *p = reinterpret_cast<double2 *>(g + i);
+      const double2 w = *p;
+      *p = make_double2(sc * w.x, sc * w.y);
+    } else {
+      g[i] *= sc;
+      if (i + 1 < n) g[i + 1] *= sc;
+    }
+  }
+}
+
 // ----------------------------------------------------------------------- launchers
 int check_launch(const char *what) {
   hipError_t e = hipGetLastError();
@@ -304,6 +324,15 @@ int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t 
 int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
                       hipStream_t s) {
   return run_grad_exact(m, vhat, prec, m->dev.gw, out3, flag, s);
+}
+
+int run_scale_inplace(p1e_mesh *m, const double *scale, double *g, hipStream_t s) {
+  if (m->nfd == 0) return P1E_OK;
+  prof_begin("k_scale_inplace", s);
+  const int nb = (int)std::min<int64_t>(nblocks((m->nfd + 1) / 2), 512);
+  hipLaunchKernelGGL(k_scale_inplace, dim3(nb), dim3(kBlock), 0, s, (int)m->nfd, scale, g);
+  prof_end(s);
+  return check_launch("k_scale_inplace");
 }
 
 int run_scale(p1e_mesh *m, const double *scale, double *g, hipStream_t s) {

@@ -1,7 +1,7 @@
 """The differentiation hook: torch.autograd.Function with the exact gradient as backward,
 checked by gradcheck (FP64), against the oracle gradient and against the patch
-central-difference gradient, including a scaled incoming gradient and the case where the
-gradient kept by the forward pass was overwritten before backward."""
+central-difference gradient, including a scaled incoming gradient, interleaved forwards and
+backwards, a second backward through a retained graph, and the in-place scaling call."""
 
 import numpy as np
 import pytest
@@ -60,7 +60,7 @@ def test_scaled_incoming_gradient_and_stale_forces(P, oracle_mod):
     (3.0 * P.p1_energy(v1, mesh, "fp64")).backward()
     g1 = O.grad_exact(prob.v)
     assert np.allclose(v1.grad.cpu().numpy(), 3.0 * g1, rtol=1e-12, atol=1e-12 * np.abs(g1).max())
-    # two forwards, then the first backward: its kept gradient was overwritten -> recomputed
+    # two forwards, then their backwards: each keeps its own gradient
     v2 = v1.detach().clone().requires_grad_(True)
     v3 = (v1.detach() * 1.0001).requires_grad_(True)
     J2 = P.p1_energy(v2, mesh, "fp64")
@@ -86,3 +86,38 @@ def test_grad_gather_requires_forces(P):
     g = mesh.grad_gather("mixed")
     g2, _, _ = mesh.grad_exact(v, "mixed")
     assert torch.equal(g, g2)
+
+
+def test_retained_graph_second_backward(P, oracle_mod):
+    prob = S.neohooke_beam_2d(20, 5, 2.0, 0.4, seed=6)
+    O = oracle_mod.Oracle(prob)
+    g1 = O.grad_exact(prob.v)
+    mesh = _mesh(P, prob)
+    v = torch.tensor(prob.vhat(), device="cuda", requires_grad=True)
+    J = P.p1_energy(v, mesh, "fp64")
+    J.backward(retain_graph=True)
+    first = v.grad.clone()
+    (2.0 * J).backward()  # recomputed at the saved input, scaled by 2, accumulated
+    tol = 1e-12 * np.abs(g1).max()
+    assert np.allclose(first.cpu().numpy(), g1, rtol=1e-12, atol=tol)
+    assert np.allclose(v.grad.cpu().numpy(), 3.0 * g1, rtol=1e-12, atol=3 * tol)
+
+
+def test_grad_scale_in_place(P):
+    prob = S.plaplace_square(n=10, p=3.0, seed=3)  # 81 free DOFs
+    mesh = _mesh(P, prob)
+    v = torch.tensor(prob.vhat(), device="cuda")
+    g, _, _ = mesh.grad_exact(v, "fp64")
+    ref = g.clone()
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+    mesh.grad_scale(g, one)
+    assert torch.equal(g, ref)  # scale 1: untouched, bitwise
+    s = torch.full((1,), -2.5, dtype=torch.float64, device="cuda")
+    mesh.grad_scale(g, s)
+    assert torch.equal(g, ref * -2.5)  # one IEEE product per entry
+    # an odd length and a buffer 8 bytes off a 16-byte boundary take the scalar path
+    buf = torch.empty(mesh.n_free_dofs + 1, dtype=torch.float64, device="cuda")
+    h = buf[1:]
+    h.copy_(ref)
+    mesh.grad_scale(h, s)
+    assert torch.equal(h, ref * -2.5)
