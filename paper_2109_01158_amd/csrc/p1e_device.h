@@ -591,10 +591,8 @@ struct alignas(16) TileShared {
 // rounds of 4 whose LDS reads are issued together; absent slots read a zero record) and
 // combine their sums, so every lane holds the same value. A node whose whole patch lies in
 // the tile writes g = scale * (sum - b) in free-DOF order; the others write the sum to their
-// halo slot. The nodes come in the order of their patch records (longest row first, so that
-// the lanes of a wavefront run similar numbers of rounds). The record of a lane's first node
-// comes from the caller (loaded before the element pass, so its latency is hidden); b is
-// loaded before the LDS sums.
+// halo slot. The record of a lane's first node comes from the caller (loaded before the
+// element pass, so its latency is hidden); b is loaded before the LDS sums.
 template <class SH>
 struct DIM_OF_SH {
   static constexpr int K = SH::K;
@@ -607,7 +605,7 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
   static_assert(3 * GL <= kEntAlign, "reads past a row stay within the entry slack");
   const int sub = tid % GL;
   for (int a = tid / GL; a < nloc; a += NT / GL) {
-    const int4 rec = a < NT / GL ? rec0 : M.tprec[r0 + a];  // rec0: loaded by the caller
+    const int4 rec = a < NT / GL ? rec0 : M.trec[r0 + a];  // rec0: loaded by the caller
     if (rec.w == 0) continue;  // no free DOF (uniform over the node's lanes)
     const int mask = rec.y & 7, fb = rec.y >> 3;
     const bool complete = rec.z & 1;
@@ -822,7 +820,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
   int4 prec = make_int4(0, 0, 0, 0);
   if constexpr (MODE != MODE_ENERGY) {
     const int a = nloc <= NT / 2 ? tid / 2 : tid;
-    if (a < nloc) prec = M.tprec[r0 + a];
+    if (a < nloc) prec = M.trec[r0 + a];
   }
   // 2. elements
   double s = 0.0, c = 0.0;

@@ -55,8 +55,7 @@ struct TileMesh {
   // tiles
   const int4 *ttile = nullptr;  // [ntiles+1] {first element, first node record, first patch
                                 //  entry, 0}; the last one closes the ranges
-  const int4 *trec = nullptr;   // [sum nloc] tile node records (staging order)
-  const int4 *tprec = nullptr;  // [sum nloc] the same nodes' patch records, longest row first
+  const int4 *trec = nullptr;   // [sum nloc] tile node records
   const uint16_t *tlent = nullptr;  // local patch entries: offset (l kTileElems + e) d of the
                                     // element result in the tile's LDS, per node ascending e
   const int4 *hrec = nullptr;   // [nhalo] halo row records
@@ -87,7 +86,6 @@ struct p1e_mesh {
   std::vector<uint16_t> conn_loc;  // [k][ne]
   std::vector<int32_t> ttile;      // [ntiles+1][4]
   std::vector<int32_t> trec;       // [sum nloc][4]
-  std::vector<int32_t> tprec;      // [sum nloc][4]
   std::vector<uint16_t> tlent;
   std::vector<int32_t> hrec;       // [nhalo][4]
   int64_t ntiles = 0, nhalo = 0, nslots = 0, ntnodes = 0;

@@ -83,14 +83,12 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
   // ---- per tile: node records, local connectivity, local patch rows
   m->ttile.clear();
   m->trec.clear();
-  m->tprec.clear();
   m->tlent.clear();
   m->ttile.reserve(4 * (nt + 1));
   m->trec.reserve(4 * (size_t)std::accumulate(ntile_of.begin(), ntile_of.end(), int64_t(0)));
-  m->tprec.reserve(m->trec.capacity());
   m->tlent.reserve((size_t)k * ne + kEntAlign * nt);
   m->conn_loc.assign((size_t)k * ne, 0);
-  std::vector<int32_t> loc(nn, -1), cnt, pos, fill, nodes, order, seen_tiles(nn, 0);
+  std::vector<int32_t> loc(nn, -1), cnt, pos, fill, nodes, seen_tiles(nn, 0);
   nodes.reserve(kTileNodes);
   for (int64_t t = 0; t < nt; ++t) {
     const int64_t e0 = tile_e[t], e1 = tile_e[t + 1];
@@ -131,7 +129,6 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
         if (is_free(nodes[a]))  // LDS offset of the entry's result: (l kTileElems + e) d
           m->tlent[ent0 + fill[a]++] = (uint16_t)((l * kTileElems + (e - e0)) * m->d);
       }
-    const size_t rec0 = m->trec.size();
     for (int a = 0; a < nloc; ++a) {
       const int32_t v = nodes[a];
       const bool fr = is_free(v);
@@ -147,17 +144,6 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
       seen_tiles[v] += 1;
       loc[v] = -1;
     }
-    // the patch-sum records of the same nodes, longest local patch row first (rows of nodes
-    // without free DOFs count as empty); ties keep the node order
-    order.resize(nloc);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-      const int na = m->trec[rec0 + 4 * a + 3] >> 16, nb = m->trec[rec0 + 4 * b + 3] >> 16;
-      return na > nb;
-    });
-    for (int a : order)
-      m->tprec.insert(m->tprec.end(), m->trec.begin() + rec0 + 4 * a,
-                      m->trec.begin() + rec0 + 4 * a + 4);
   }
   m->ttile.insert(m->ttile.end(),
                   {(int32_t)ne, (int32_t)(m->trec.size() / 4), (int32_t)m->tlent.size(), 0});
