@@ -494,10 +494,14 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
   bool bad = false;
   double W;
   T P[D][DIM];
+  NhInv<DIM, T> nv;  // (Neo-Hookean patch differences) the invariants, kept for the steps
   if constexpr (MODE == MODE_FORCE && KIND == P1E_NEOHOOKE) {
     W = nh_energy_stress<DIM, T>(G, prm.C1, prm.D1, vol, bad, P);  // P = |T| dW/dF
   } else if constexpr (MODE == MODE_FORCE) {
     W = pl_energy_stress<DIM, T>(G[0], prm.p, vol, bad, P[0]);
+  } else if constexpr (MODE == MODE_FD && KIND == P1E_NEOHOOKE) {
+    nv = nh_invariants<DIM, T>(G);
+    W = nh_density<DIM, T>(nv, prm.C1, prm.D1, bad);
   } else {
     W = density<DIM, D, KIND, T>(G, prm, bad);
   }
@@ -523,6 +527,19 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
     // patch sums happen in the tile's node phase and the halo rows.
     const double inv2e = 1.0 / (2.0 * prm.eps);
     T out[K * D];
+    // (Neo-Hookean) det F - 1 and cof F = (1 + tr G) I - G^T (+ cof G in 3D), dDet F / dF
+    double delta = 0.0;
+    T cf[DIM][DIM];
+    if constexpr (KIND == P1E_NEOHOOKE) {
+      delta = (double)nv.tr + (double)nv.s2 + (double)nv.dG;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j)
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+          const T t = (j == m ? T(1) + nv.tr : T(0)) - G[m][j];
+          cf[j][m] = DIM == 3 ? t + nv.cg[j][m] : t;
+        }
+    }
 #pragma unroll
     for (int l = 0; l < K; ++l) {
       T a[DIM];
@@ -536,6 +553,34 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
         } else {
           a[m] = Bi[l - 1][m];
         }
+      }
+      if constexpr (KIND == P1E_NEOHOOKE) {
+        // F -> F +- eps e_j a^T changes det F by +- eps c with c = (cof F)_j . a (det F is
+        // linear in each row) and |F|^2 by +- 2 eps F_j . a + eps^2 |a|^2, so
+        //   W+ - W- = C1 (4 eps F_j . a - 2 log(det F+ / det F-)) + 4 D1 eps c (det F - 1),
+        // with log(det F+ / det F-) = log1p(x), x = 2 eps c / det F-, taken as
+        // x - log_excess(x): the same difference as two density evaluations, without their
+        // cancellation and with one logarithm instead of two.
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          double c = 0.0, fa = (double)a[j];
+#pragma unroll
+          for (int m = 0; m < DIM; ++m) {
+            c = fma((double)cf[j][m], (double)a[m], c);
+            fa = fma((double)G[j][m], (double)a[m], fa);
+          }
+          const double dm = delta - prm.eps * c;  // det F- - 1
+          const double x = 2.0 * prm.eps * c / (1.0 + dm);
+          const bool ok = dm > -1.0 && x > -1.0;
+          if (!ok) bad = true;
+          const double xs = ok ? x : 0.0;
+          const double lg = xs - log_excess(xs);
+          const double dW = prm.C1 * (4.0 * prm.eps * fa - 2.0 * lg) +
+                            4.0 * prm.D1 * prm.eps * c * delta;
+          if (!isfinite(dW)) bad = true;
+          out[l * D + j] = (T)((double)vol * dW * inv2e);
+        }
+        continue;
       }
 #pragma unroll
       for (int j = 0; j < D; ++j) {
