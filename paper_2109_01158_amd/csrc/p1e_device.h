@@ -267,6 +267,20 @@ __device__ __forceinline__ double log_excess(double d) {
   return k0 ? q0 : qk;
 }
 
+// log(1 + x) for the small relative changes of det F under a difference step: when every lane
+// of the wavefront has |x| < 1/64, by the alternating series x - x^2/2 + x^3/3 - ... to the
+// tenth power (the omitted terms are below 1e-19 of the sum), without division; otherwise as
+// x - log_excess(x). The branch is uniform over the wavefront.
+__device__ __forceinline__ double log1p_step(double x) {
+  if (__all(fabs(x) < 0.015625)) {
+    double t = scalar_const(-1.0 / 10.0);
+#pragma unroll
+    for (int i = 9; i >= 1; --i) t = fma(t, x, scalar_const((i & 1 ? 1.0 : -1.0) / i));
+    return t * x;
+  }
+  return x - log_excess(x);
+}
+
 // Invariants of G = F - I used by the Neo-Hookean density and stress, in T: tr G, s2 (sum of
 // the principal 2x2 minors, 0 in 2D), det G, |G|^2, and (3D) cof G. det F = 1 + tr + s2 + det G.
 template <int DIM, typename T>
@@ -558,9 +572,9 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
         // F -> F +- eps e_j a^T changes det F by +- eps c with c = (cof F)_j . a (det F is
         // linear in each row) and |F|^2 by +- 2 eps F_j . a + eps^2 |a|^2, so
         //   W+ - W- = C1 (4 eps F_j . a - 2 log(det F+ / det F-)) + 4 D1 eps c (det F - 1),
-        // with log(det F+ / det F-) = log1p(x), x = 2 eps c / det F-, taken as
-        // x - log_excess(x): the same difference as two density evaluations, without their
-        // cancellation and with one logarithm instead of two.
+        // with log(det F+ / det F-) = log1p(x), x = 2 eps c / det F- (log1p_step): the same
+        // difference as two density evaluations, without their cancellation and with one
+        // logarithm instead of two.
 #pragma unroll
         for (int j = 0; j < D; ++j) {
           double c = 0.0, fa = (double)a[j];
@@ -573,8 +587,7 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
           const double x = 2.0 * prm.eps * c / (1.0 + dm);
           const bool ok = dm > -1.0 && x > -1.0;
           if (!ok) bad = true;
-          const double xs = ok ? x : 0.0;
-          const double lg = xs - log_excess(xs);
+          const double lg = log1p_step(ok ? x : 0.0);
           const double dW = prm.C1 * (4.0 * prm.eps * fa - 2.0 * lg) +
                             4.0 * prm.D1 * prm.eps * c * delta;
           if (!isfinite(dW)) bad = true;
