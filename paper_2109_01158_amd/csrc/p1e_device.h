@@ -219,6 +219,25 @@ struct NodeVec<T, 1> {
 };
 
 // ----------------------------------------------------------------------- densities
+// A double constant handed to the arithmetic as a scalar register: the FMAs then read it as a
+// uniform operand instead of materialising it in vector registers (two vector moves each).
+__device__ __forceinline__ double scalar_const(double c) {
+  double r;
+  asm("s_mov_b64 %0, %1" : "=s"(r) : "s"(c));
+  return r;
+}
+
+// num / den for a normal den of moderate size (no scaling is done): the hardware reciprocal
+// refined by two Newton steps, then one residual correction of the quotient (Markstein's
+// scheme), within 1 ulp; cheaper than the correctly rounded division.
+__device__ __forceinline__ double quotient(double num, double den) {
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  const double q = num * r;
+  return fma(r, fma(-den, q, num), q);
+}
+
 // q(d) = d - log(1 + d) >= 0 for d > -1, in double, without the cancellation of the plain
 // difference near d = 0 (where q ~ d^2 / 2). Binary exponent reduction 1 + d = 2^k m with
 // m in [1/sqrt 2, sqrt 2), then log m = 2 atanh s = 2 s + 2 s^3 S(s^2), s = (m - 1)/(m + 1),
@@ -230,13 +249,6 @@ struct NodeVec<T, 1> {
 //  k != 0: q = d - k log 2 - 2 s - 2 s^3 S - (1 + d - t)/t with t = fl(1 + d); the last term
 //         undoes the rounding of t (d - (t - 1) is exact here), q >= 0.06 so no cancellation.
 // About 40 double instructions, against over 100 for a general-purpose log1p.
-// A double constant handed to the arithmetic as a scalar register: the FMAs then read it as a
-// uniform operand instead of materialising it in vector registers (two vector moves each).
-__device__ __forceinline__ double scalar_const(double c) {
-  double r;
-  asm("s_mov_b64 %0, %1" : "=s"(r) : "s"(c));
-  return r;
-}
 __device__ __forceinline__ double log_excess(double d) {
   const double t = 1.0 + d;
   int k;
@@ -245,14 +257,7 @@ __device__ __forceinline__ double log_excess(double d) {
   m = lo ? 2.0 * m : m;
   k = lo ? k - 1 : k;
   const bool k0 = k == 0;
-  // s = num / den with den in [1.7, 2.5]: the hardware reciprocal refined by two Newton steps,
-  // then one residual correction of the quotient (Markstein's scheme; within 1 ulp)
-  const double num = k0 ? d : m - 1.0, den = k0 ? 2.0 + d : m + 1.0;
-  double r = __builtin_amdgcn_rcp(den);
-  r = fma(r, fma(-den, r, 1.0), r);
-  r = fma(r, fma(-den, r, 1.0), r);
-  double s = num * r;
-  s = fma(r, fma(-den, s, num), s);
+  const double s = quotient(k0 ? d : m - 1.0, k0 ? 2.0 + d : m + 1.0);  // den in [1.7, 2.5]
   const double w = s * s;
   double S = 1.0 / 21.0;  // S(w) = sum w^i / (2i + 3), i = 9 .. 0 by Horner
 #pragma unroll
@@ -584,7 +589,7 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
             fa = fma((double)G[j][m], (double)a[m], fa);
           }
           const double dm = delta - prm.eps * c;  // det F- - 1
-          const double x = 2.0 * prm.eps * c / (1.0 + dm);
+          const double x = quotient(2.0 * prm.eps * c, 1.0 + dm);
           const bool ok = dm > -1.0 && x > -1.0;
           if (!ok) bad = true;
           const double lg = log1p_step(ok ? x : 0.0);
