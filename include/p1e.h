@@ -58,6 +58,11 @@ extern "C" {
 #define P1E_PLAPLACE 1 /* W(g) = |g|^p / p, scalar field (d = 1), p > 1 (eq. pLaplacian) */
 #define P1E_NEOHOOKE 2 /* W(F) = C1 (|F|^2 - dim - 2 log det F) + D1 (det F - 1)^2,
                           vector field (d = dim) (eq. neoHook) */
+#define P1E_SVK 3      /* St. Venant-Kirchhoff, the extension Section 2 names after eq. neoHook:
+                          W(F) = C1 |E|^2 + D1 (tr E)^2 with E = (F^T F - I) / 2, i.e.
+                          C1 = mu and D1 = lambda / 2 (Lame constants); vector field (d = dim),
+                          finite for every F (no bad elements but non-finite values). Energy,
+                          exact gradient and patch differences; not served by p1e_server. */
 
 /* ------------------------------------------------------------------ precision modes */
 /* Each compute call names one mode; p1e_mesh_bind takes a bit mask of the modes to prepare. */
@@ -77,7 +82,7 @@ extern "C" {
 #define P1E_INPUT_ORDER 1
 /* P1E_FULL_GEOMETRY: always store B^-1 and |T| per element. By default, element records
  * (B^-1, |T|) that agree to 2^-40 of each component's largest magnitude share one class, and
- * a mesh with at most 256 classes (uniformly refined structured meshes have a few) stores one
+ * a mesh with at most 64 classes (uniformly refined structured meshes have a few) stores one
  * record per class and a one-byte class per element; the elements of a class then use its
  * first record, which differs from their own only by the rounding of node coordinates. */
 #define P1E_FULL_GEOMETRY 4
@@ -87,8 +92,8 @@ typedef struct p1e_mesh p1e_mesh;
 /* Mesh and problem description (all arrays are host memory, row-major, 0-based). */
 typedef struct p1e_mesh_desc {
   int32_t dim;   /* 2 (triangles) or 3 (tetrahedra) */
-  int32_t ncomp; /* d: 1 for P1E_PLAPLACE, dim for P1E_NEOHOOKE */
-  int32_t kind;  /* P1E_PLAPLACE or P1E_NEOHOOKE */
+  int32_t ncomp; /* d: 1 for P1E_PLAPLACE, dim for P1E_NEOHOOKE and P1E_SVK */
+  int32_t kind;  /* P1E_PLAPLACE, P1E_NEOHOOKE or P1E_SVK */
   int32_t flags; /* 0 or P1E_INPUT_ORDER | P1E_FULL_GEOMETRY */
   int64_t nn; /* number of nodes, 1 <= nn < 2^28 */
   int64_t ne; /* number of elements, 0 <= ne < 2^29 */
@@ -98,7 +103,8 @@ typedef struct p1e_mesh_desc {
   const double *dirichlet_values; /* [nn][ncomp] values of prescribed DOFs; NULL = 0 */
   const double *load;        /* [nn][ncomp] nodal values of the P1 load f; NULL = 0 */
   double p;                  /* p-Laplacian exponent, p > 1 */
-  double C1, D1;             /* Neo-Hookean constants (C1 = mu/2, D1 = K/2 in Benchmark 2) */
+  double C1, D1;             /* Neo-Hookean constants (C1 = mu/2, D1 = K/2 in Benchmark 2);
+                                St. Venant-Kirchhoff: C1 = mu, D1 = lambda/2 */
 } p1e_mesh_desc;
 
 typedef struct p1e_mesh_info {
@@ -212,7 +218,8 @@ uint64_t p1e_minimize_workspace_bytes(const p1e_mesh *mesh, const p1e_lbfgs_opts
 /* Minimize from vhat (device, in/out) on a mesh bound for opts->prec. ws: caller-owned device
  * buffer (256-byte aligned, p1e_minimize_workspace_bytes). Synchronous on stream. Overwrites
  * the mesh's scratch arrays (a following p1e_grad_gather returns P1E_ESTATE). P1E_EDOMAIN if
- * the start point has bad elements. */
+ * the start point has bad elements; P1E_EINVAL for a P1E_SVK mesh (the minimizer and the
+ * server cover the paper's two densities). */
 int p1e_minimize(p1e_mesh *mesh, double *vhat, const p1e_lbfgs_opts *opts, void *ws,
                  uint64_t ws_bytes, p1e_min_report *report, void *stream);
 

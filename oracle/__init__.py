@@ -26,7 +26,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "p1e_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-PLAPLACE, NEOHOOKE = 1, 2
+PLAPLACE, NEOHOOKE, SVK = 1, 2, 3
+_KINDS = {"plaplace": PLAPLACE, "neohooke": NEOHOOKE, "svk": SVK}
 
 
 def build(force=True):
@@ -88,6 +89,14 @@ def neohooke_constants(E, nu):
     return mu / 2.0, K / 2.0
 
 
+def svk_constants(E, nu):
+    """St. Venant-Kirchhoff W = C1 |E|^2 + D1 (tr E)^2: C1 = mu, D1 = lambda/2 with the Lame
+    constants mu = E/(2(1+nu)), lambda = E nu/((1+nu)(1-2nu))."""
+    mu = E / (2.0 * (1.0 + nu))
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    return mu, lam / 2.0
+
+
 class Oracle:
     """Oracle bound to one mesh/problem. ``prob`` needs the attributes of
     ``p1e_synth.Problem`` (dim, ncomp, kind, coords, conn, dirichlet, dirichlet_values,
@@ -105,15 +114,16 @@ class Oracle:
         self.free = np.ascontiguousarray(prob.dirichlet.reshape(-1) == 0)
         self.free_dofs = np.flatnonzero(self.free).astype(np.int64)
         self.vD = np.ascontiguousarray(prob.dirichlet_values, dtype=np.float64).reshape(-1)
-        if self.kind == "neohooke":
-            c1, d1 = neohooke_constants(prob.E, prob.nu)
+        if self.kind in ("neohooke", "svk"):
+            c1, d1 = (neohooke_constants if self.kind == "neohooke" else svk_constants)(
+                prob.E, prob.nu)
             self.C1 = c1 if C1 is None else C1
             self.D1 = d1 if D1 is None else D1
             self.p = 0.0
         else:
             self.C1 = self.D1 = 0.0
             self.p = float(prob.p)
-        self._P = _Problem(self.dim, self.d, NEOHOOKE if self.kind == "neohooke" else PLAPLACE, 0,
+        self._P = _Problem(self.dim, self.d, _KINDS[self.kind], 0,
                            self.nn, self.ne, _ptr(self.conn).value, _ptr(self.coords).value,
                            self.p, self.C1, self.D1)
         k = self.dim + 1

@@ -13,7 +13,10 @@
  *                l >= 1, grad phi_0 = -sum of the others).
  *   F_T          eq. (Dv): F_T[j][m] = sum_l v[I(T,l)][j] * d phi_{T,l} / d x_m.
  *   densities    eq. (neoHook): W = C1 (|F|^2 - dim - 2 log det F) + D1 (det F - 1)^2;
- *                eq. (pLaplacian): W = |grad v|^p / p.
+ *                eq. (pLaplacian): W = |grad v|^p / p;
+ *                St. Venant-Kirchhoff, the extension Section 2 names after eq. (neoHook)
+ *                (the paper gives no formula; the textbook one): W = C1 |E|^2 + D1 (tr E)^2
+ *                with the Green-Lagrange strain E = (F^T F - I) / 2, C1 = mu, D1 = lambda / 2.
  *   J_grad       eq. (Denergy): sum over elements of |T| W(F_T), element order,
  *                Neumaier-compensated.
  *   b = M f      Section 3.2, eqs. (mass2D), (linearTerm2): consistent P1 mass matrix with
@@ -25,8 +28,8 @@
  *                of the nodal patch T^i and difference the two patch sums of |T| W.
  *
  * Conventions (readings of the paper): J = J_grad - b.v (the linear part enters with a minus
- * sign); det F <= 0 or a non-finite density makes the element "bad": the energy is +Inf and
- * the bad elements are counted. For the p-Laplacian the gradient of |g|^p/p at g = 0 is 0.
+ * sign); (Neo-Hookean) det F <= 0 or a non-finite density makes the element "bad": the energy
+ * is +Inf and the bad elements are counted (St. Venant-Kirchhoff is finite for every F). For the p-Laplacian the gradient of |g|^p/p at g = 0 is 0.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no OpenMP: single-threaded on purpose).
  */
@@ -35,12 +38,12 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_PLAPLACE = 1, ORC_NEOHOOKE = 2 };
+enum { ORC_PLAPLACE = 1, ORC_NEOHOOKE = 2, ORC_SVK = 3 };
 
 typedef struct {
   int32_t dim;    /* 2 or 3 */
   int32_t ncomp;  /* d: 1 (scalar) or dim (vector) */
-  int32_t kind;   /* ORC_PLAPLACE or ORC_NEOHOOKE */
+  int32_t kind;   /* ORC_PLAPLACE, ORC_NEOHOOKE or ORC_SVK */
   int32_t pad_;
   int64_t nn, ne;
   const int32_t *conn;   /* [ne][dim+1] */
@@ -141,11 +144,29 @@ static void element_F(const orc_problem *P, const double *v, const int32_t *T,
         F[j][m] += v[(int64_t)T[l] * d + j] * dphi_e[l * dim + m];
 }
 
-/* W(F); sets *bad when det F <= 0 or the value is not finite */
+/* Green-Lagrange strain E = (F^T F - I) / 2 */
+static void green_strain(int dim, double F[3][3], double E[3][3]) {
+  for (int j = 0; j < dim; ++j)
+    for (int m = 0; m < dim; ++m) {
+      double c = 0.0;
+      for (int q = 0; q < dim; ++q) c += F[q][j] * F[q][m];
+      E[j][m] = 0.5 * (c - (j == m ? 1.0 : 0.0));
+    }
+}
+
+/* W(F); sets *bad when (Neo-Hookean) det F <= 0 or the value is not finite */
 static double density(const orc_problem *P, double F[3][3], int *bad) {
   const int dim = P->dim;
   double W;
-  if (P->kind == ORC_NEOHOOKE) {
+  if (P->kind == ORC_SVK) {
+    double E[3][3], tr = 0.0, ee = 0.0;
+    green_strain(dim, F, E);
+    for (int j = 0; j < dim; ++j) {
+      tr += E[j][j];
+      for (int m = 0; m < dim; ++m) ee += E[j][m] * E[j][m];
+    }
+    W = P->C1 * ee + P->D1 * tr * tr;
+  } else if (P->kind == ORC_NEOHOOKE) {
     double I1 = 0.0;
     for (int j = 0; j < dim; ++j)
       for (int m = 0; m < dim; ++m) I1 += F[j][m] * F[j][m];
@@ -166,7 +187,18 @@ static void density_dF(const orc_problem *P, double F[3][3], double D[3][3], int
   const int dim = P->dim;
   for (int j = 0; j < 3; ++j)
     for (int m = 0; m < 3; ++m) D[j][m] = 0.0;
-  if (P->kind == ORC_NEOHOOKE) {
+  if (P->kind == ORC_SVK) {
+    /* dW/dF = F S with S = dW/dE = 2 C1 E + 2 D1 (tr E) I (second Piola-Kirchhoff stress) */
+    double E[3][3], S2[3][3], tr = 0.0;
+    green_strain(dim, F, E);
+    for (int j = 0; j < dim; ++j) tr += E[j][j];
+    for (int j = 0; j < dim; ++j)
+      for (int m = 0; m < dim; ++m)
+        S2[j][m] = 2.0 * P->C1 * E[j][m] + (j == m ? 2.0 * P->D1 * tr : 0.0);
+    for (int j = 0; j < dim; ++j)
+      for (int m = 0; m < dim; ++m)
+        for (int q = 0; q < dim; ++q) D[j][m] += F[j][q] * S2[q][m];
+  } else if (P->kind == ORC_NEOHOOKE) {
     double det = det_mat(dim, F);
     if (!(det > 0.0)) { *bad = 1; return; }
     double cof[3][3];
@@ -288,6 +320,22 @@ void orc_patches(const orc_problem *P, int64_t *patch_ptr, int64_t *patch_elem) 
 /* ---------------------------------------------------------------- patch central differences */
 /* |W|_abs: the sum of the magnitudes of the density's terms (rounding scale of W) */
 static double density_abs(const orc_problem *P, double F[3][3], double W) {
+  if (P->kind == ORC_SVK) {
+    /* E_jm = ((F^T F)_jm - delta_jm) / 2 carries a rounding of about dim u ((|F|^T |F|)_jm
+     * + delta_jm) / 2; W moves by |dW/dE_jm| = |S_jm| times that */
+    const int dim = P->dim;
+    double E[3][3], tr = 0.0, sc = 0.0;
+    green_strain(dim, F, E);
+    for (int j = 0; j < dim; ++j) tr += E[j][j];
+    for (int j = 0; j < dim; ++j)
+      for (int m = 0; m < dim; ++m) {
+        double c = 0.0;
+        for (int q = 0; q < dim; ++q) c += fabs(F[q][j]) * fabs(F[q][m]);
+        const double S = fabs(2.0 * P->C1 * E[j][m] + (j == m ? 2.0 * P->D1 * tr : 0.0));
+        sc += S * 0.5 * dim * (c + (j == m ? 1.0 : 0.0));
+      }
+    return fabs(W) + sc;
+  }
   if (P->kind != ORC_NEOHOOKE) return fabs(W);
   const int dim = P->dim;
   double I1 = 0.0;

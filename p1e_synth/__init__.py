@@ -19,6 +19,8 @@ from .problems import (  # noqa: F401
     plaplace_square,
     neohooke_beam_2d,
     neohooke_box_3d,
+    svk_beam_2d,
+    svk_box_3d,
     twisted_bar,
     plaplace_lshape,
     config_problem,

@@ -12,7 +12,7 @@ For axis-aligned right triangles and Kuhn tetrahedra every displacement-gradient
 difference of two nodal values over h, hence bounded by 0.3, which keeps det F > 0.
 """
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -24,7 +24,7 @@ class Problem:
     name: str
     dim: int
     ncomp: int
-    kind: str                 # "plaplace" or "neohooke"
+    kind: str                 # "plaplace", "neohooke" or "svk" (St. Venant-Kirchhoff)
     coords: np.ndarray        # f64 [nn, dim]
     conn: np.ndarray          # i32 [ne, dim+1]
     dirichlet: np.ndarray     # u8  [nn, ncomp], 1 = prescribed
@@ -118,6 +118,19 @@ def neohooke_box_3d(nx=460, ny=46, nz=46, lx=1.0, ly=0.1, lz=0.1, seed=0, eps=1e
     dmask = _dirichlet_on(coords, 3, lambda X: X[:, 0] < 0.5 * h)
     return _neohooke_random(coords, conn, 3, dmask, (0.0, -3.5e7, 0.0), seed, h, eps,
                             f"neohooke_box_{nx}x{ny}x{nz}", amp)
+
+
+def svk_beam_2d(nx=60, ny=13, lx=2.0, ly=0.4, seed=0, eps=1e-6, amp=None):
+    """The beam of neohooke_beam_2d (same mesh, clamp, load, E, nu and displacement draw)
+    with the St. Venant-Kirchhoff density."""
+    pb = neohooke_beam_2d(nx, ny, lx, ly, seed, eps, amp)
+    return replace(pb, kind="svk", name=f"svk_beam_{nx}x{ny}")
+
+
+def svk_box_3d(nx=13, ny=7, nz=5, lx=1.0, ly=0.5, lz=0.4, seed=0, eps=1e-6, amp=None):
+    """The box of neohooke_box_3d with the St. Venant-Kirchhoff density."""
+    pb = neohooke_box_3d(nx, ny, nz, lx, ly, lz, seed, eps, amp)
+    return replace(pb, kind="svk", name=f"svk_box_{nx}x{ny}x{nz}")
 
 
 def twisted_bar(level, alpha=2.0 * np.pi, lx=0.4, ly=0.01, lz=0.01):

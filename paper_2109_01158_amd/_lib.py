@@ -24,6 +24,7 @@ P1E_ESTATE = -7
 
 P1E_PLAPLACE = 1
 P1E_NEOHOOKE = 2
+P1E_SVK = 3
 
 P1E_FP64 = 1
 P1E_MIXED = 2

@@ -12,7 +12,10 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import P1E_FD, P1E_FP64, P1E_MIXED, P1E_NEOHOOKE, P1E_PLAPLACE, check
+from ._lib import P1E_FD, P1E_FP64, P1E_MIXED, P1E_NEOHOOKE, P1E_PLAPLACE, P1E_SVK, check
+
+_KINDS = {"plaplace": P1E_PLAPLACE, "neohooke": P1E_NEOHOOKE, "svk": P1E_SVK,
+          P1E_PLAPLACE: P1E_PLAPLACE, P1E_NEOHOOKE: P1E_NEOHOOKE, P1E_SVK: P1E_SVK}
 
 PREC = {"fp64": P1E_FP64, "mixed": P1E_MIXED, P1E_FP64: P1E_FP64, P1E_MIXED: P1E_MIXED}
 
@@ -37,13 +40,20 @@ def neohooke_constants(E, nu):
     return mu / 2.0, K / 2.0
 
 
+def svk_constants(E, nu):
+    """St. Venant-Kirchhoff: C1 = mu, D1 = lambda/2 with the Lame constants of (E, nu)."""
+    mu = E / (2.0 * (1.0 + nu))
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    return mu, lam / 2.0
+
+
 # ------------------------------------------------------------------ 1:1 entry points
 def mesh_create(dim, kind, conn, coords, dirichlet=None, dirichlet_values=None, load=None,
                 p=2.0, C1=0.0, D1=0.0, flags=0):
-    """p1e_mesh_create. kind: "plaplace" | "neohooke". Arrays are host numpy; returns an
-    opaque handle (int). flags: 0 or P1E_INPUT_ORDER | P1E_FULL_GEOMETRY."""
-    k = P1E_NEOHOOKE if kind in ("neohooke", P1E_NEOHOOKE) else P1E_PLAPLACE
-    ncomp = dim if k == P1E_NEOHOOKE else 1
+    """p1e_mesh_create. kind: "plaplace" | "neohooke" | "svk". Arrays are host numpy;
+    returns an opaque handle (int). flags: 0 or P1E_INPUT_ORDER | P1E_FULL_GEOMETRY."""
+    k = _KINDS[kind]
+    ncomp = 1 if k == P1E_PLAPLACE else dim
     conn = np.ascontiguousarray(conn, dtype=np.int32)
     coords = np.ascontiguousarray(coords, dtype=np.float64)
     dmask = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
@@ -174,8 +184,9 @@ class Mesh:
     def from_problem(cls, prob, modes=P1E_FP64 | P1E_MIXED, device="cuda", stream=None,
                      flags=0):
         """Build from an object with the fields of ``p1e_synth.Problem``."""
-        if prob.kind == "neohooke":
-            C1, D1 = neohooke_constants(prob.E, prob.nu)
+        if prob.kind in ("neohooke", "svk"):
+            C1, D1 = (neohooke_constants if prob.kind == "neohooke" else svk_constants)(
+                prob.E, prob.nu)
             p = 2.0
         else:
             C1 = D1 = 0.0
@@ -290,12 +301,13 @@ def mesh_minimize(mesh, vhat, history=5, max_iters=200, prec="fp64", stream=None
 # ------------------------------------------------------------------ serving
 def _desc_of(prob, flags=0):
     """A MeshDesc for a p1e_synth.Problem-like object; returns (desc, arrays kept alive)."""
-    if prob.kind == "neohooke":
-        C1, D1 = neohooke_constants(prob.E, prob.nu)
-        k, p = P1E_NEOHOOKE, 2.0
+    k = _KINDS[prob.kind]
+    if k != P1E_PLAPLACE:
+        C1, D1 = (neohooke_constants if k == P1E_NEOHOOKE else svk_constants)(prob.E, prob.nu)
+        p = 2.0
     else:
         C1 = D1 = 0.0
-        k, p = P1E_PLAPLACE, prob.p
+        p = prob.p
     conn = np.ascontiguousarray(prob.conn, dtype=np.int32)
     coords = np.ascontiguousarray(prob.coords, dtype=np.float64)
     dm = np.ascontiguousarray(prob.dirichlet, dtype=np.uint8)

@@ -388,9 +388,9 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   m->nfd = nfd;
 
   // ---- nodes in internal order: DOF map, and the values the kernels turn into the nodal
-  // field u (u = v - x for Neo-Hookean, u = v for the p-Laplacian): for a free component
+  // field u (u = v - x for the deformations, u = v for the p-Laplacian): for a free component
   // the subtrahend (x or 0), for a prescribed one u itself
-  const bool nh = m->kind == P1E_NEOHOOKE;
+  const bool nh = m->kind == P1E_NEOHOOKE || m->kind == P1E_SVK;
   m->ninfo.resize(nn);
   m->wref.assign((size_t)nn * d, 0.0);
   int64_t nf = 0;
@@ -462,8 +462,8 @@ int p1e_mesh_create(const p1e_mesh_desc *D, p1e_mesh **out) {
   if (!D || !out) return fail(P1E_EINVAL, "null argument");
   *out = nullptr;
   if (D->dim != 2 && D->dim != 3) return fail(P1E_EINVAL, "dim must be 2 or 3");
-  if (D->kind == P1E_NEOHOOKE) {
-    if (D->ncomp != D->dim) return fail(P1E_EINVAL, "Neo-Hookean needs ncomp == dim");
+  if (D->kind == P1E_NEOHOOKE || D->kind == P1E_SVK) {
+    if (D->ncomp != D->dim) return fail(P1E_EINVAL, "a deformation needs ncomp == dim");
     if (!std::isfinite(D->C1) || !std::isfinite(D->D1))
       return fail(P1E_EINVAL, "C1 and D1 must be finite");
   } else if (D->kind == P1E_PLAPLACE) {

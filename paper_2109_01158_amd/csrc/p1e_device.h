@@ -383,6 +383,73 @@ __device__ __forceinline__ double nh_energy_stress(const T G[DIM][DIM], double C
   return W;
 }
 
+// St. Venant-Kirchhoff, the extension Section 2 names after eq. neoHook, in its textbook form
+// W = C1 |E|^2 + D1 (tr E)^2 (C1 = mu, D1 = lambda / 2) with the Green-Lagrange strain taken
+// from G = F - I without the cancellation of F^T F - I: E = (G + G^T + G^T G) / 2, in T.
+template <int DIM, typename T>
+__device__ __forceinline__ void svk_strain(const T G[DIM][DIM], T E[DIM][DIM]) {
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+#pragma unroll
+    for (int m = j; m < DIM; ++m) {
+      T acc = G[j][m] + G[m][j];
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) acc = mad(G[q][j], G[q][m], acc);
+      E[j][m] = T(0.5) * acc;
+      E[m][j] = E[j][m];
+    }
+}
+// the density from E, in double
+template <int DIM, typename T>
+__device__ __forceinline__ double svk_density(const T E[DIM][DIM], double C1, double D1,
+                                              bool &bad) {
+  double tr = 0.0, ee = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    tr += (double)E[j][j];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) ee = fma((double)E[j][m], (double)E[j][m], ee);
+  }
+  const double W = C1 * ee + D1 * tr * tr;
+  if (!isfinite(W)) bad = true;
+  return W;
+}
+template <int DIM, typename T>
+__device__ __forceinline__ double svk_energy(const T G[DIM][DIM], double C1, double D1,
+                                             bool &bad) {
+  T E[DIM][DIM];
+  svk_strain<DIM, T>(G, E);
+  return svk_density<DIM, T>(E, C1, D1, bad);
+}
+// the density and vol dW/dF = vol F S with S = dW/dE = 2 C1 E + 2 D1 (tr E) I (second
+// Piola-Kirchhoff stress), F = I + G; the density is bitwise the one of svk_energy
+template <int DIM, typename T>
+__device__ __forceinline__ double svk_energy_stress(const T G[DIM][DIM], double C1, double D1,
+                                                    T vol, bool &bad, T P[DIM][DIM]) {
+  T E[DIM][DIM];
+  svk_strain<DIM, T>(G, E);
+  const double W = svk_density<DIM, T>(E, C1, D1, bad);
+  T tr = T(0);
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) tr += E[j][j];
+  const T a = T(2) * (T)C1 * vol, b = T(2) * (T)D1 * vol * tr;
+  T Sv[DIM][DIM];  // vol S
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) Sv[j][m] = j == m ? mad(a, E[j][m], b) : a * E[j][m];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+      T acc = Sv[j][m];
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) acc = mad(G[j][q], Sv[q][m], acc);
+      P[j][m] = acc;
+    }
+  return W;
+}
+
 // s^(p/2) for s >= 0, in double. When 2p is an integer k <= 64 (the benchmarks use p = 1.5,
 // 3, 5): s^(k/4) = s^floor(k/4) (s^(1/4))^(k mod 4) by products and square roots only (an
 // error of a few ulps); otherwise pow. The branch depends on p alone (uniform per mesh).
@@ -443,6 +510,8 @@ template <int DIM, int D, int KIND, typename T>
 __device__ __forceinline__ double density(const T G[D][DIM], const Params &prm, bool &bad) {
   if constexpr (KIND == P1E_NEOHOOKE) {
     return nh_energy<DIM, T>(G, prm.C1, prm.D1, bad);
+  } else if constexpr (KIND == P1E_SVK) {
+    return svk_energy<DIM, T>(G, prm.C1, prm.D1, bad);
   } else {
     return pl_energy<DIM, T>(G[0], prm.p, bad);
   }
@@ -516,6 +585,8 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
   NhInv<DIM, T> nv;  // (Neo-Hookean patch differences) the invariants, kept for the steps
   if constexpr (MODE == MODE_FORCE && KIND == P1E_NEOHOOKE) {
     W = nh_energy_stress<DIM, T>(G, prm.C1, prm.D1, vol, bad, P);  // P = |T| dW/dF
+  } else if constexpr (MODE == MODE_FORCE && KIND == P1E_SVK) {
+    W = svk_energy_stress<DIM, T>(G, prm.C1, prm.D1, vol, bad, P);
   } else if constexpr (MODE == MODE_FORCE) {
     W = pl_energy_stress<DIM, T>(G[0], prm.p, vol, bad, P[0]);
   } else if constexpr (MODE == MODE_FD && KIND == P1E_NEOHOOKE) {

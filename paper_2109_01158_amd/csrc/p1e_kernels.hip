@@ -296,6 +296,10 @@ int dispatch(p1e_mesh *m, const double *vhat, const T *geo, double eps, double *
     if (m->dim == 3) return pipeline<3, 3, P1E_NEOHOOKE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
     return pipeline<2, 2, P1E_NEOHOOKE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
   }
+  if (m->kind == P1E_SVK) {
+    if (m->dim == 3) return pipeline<3, 3, P1E_SVK, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
+    return pipeline<2, 2, P1E_SVK, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
+  }
   if (m->dim == 3) return pipeline<3, 1, P1E_PLAPLACE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
   return pipeline<2, 1, P1E_PLAPLACE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
 }

@@ -482,6 +482,8 @@ int p1e_server_submit_at(p1e_server *s, const p1e_mesh_desc *d, const double *vh
                          int64_t n0, double t_arrival, int64_t *id) {
   if (!s || !d || !id) return fail(P1E_EINVAL, "null argument");
   if (d->dim != 2 && d->dim != 3) return fail(P1E_EINVAL, "dim must be 2 or 3");
+  if (d->kind != P1E_PLAPLACE && d->kind != P1E_NEOHOOKE)
+    return fail(P1E_EINVAL, "the server covers the p-Laplacian and Neo-Hookean kinds");
   if (d->nn < 1 || d->ne < 0 || !d->coords || (d->ne > 0 && !d->conn))
     return fail(P1E_EINVAL, "bad mesh description");
   const int k = d->dim + 1;
@@ -694,6 +696,8 @@ int p1e_minimize(p1e_mesh *m, double *vhat, const p1e_lbfgs_opts *o, void *ws, u
   if (o->history < 1 || o->history > kMaxHistory || o->max_iters < 0)
     return fail(P1E_EINVAL, "bad L-BFGS options");
   if (o->prec != P1E_FP64 && o->prec != P1E_MIXED) return fail(P1E_EINVAL, "prec");
+  if (m->kind != P1E_PLAPLACE && m->kind != P1E_NEOHOOKE)
+    return fail(P1E_EINVAL, "the minimizer covers the p-Laplacian and Neo-Hookean kinds");
   if (!(m->bound_modes & o->prec)) return fail(P1E_ESTATE, "mesh not bound for the requested precision");
   if ((uintptr_t)ws % kAlign) return fail(P1E_EINVAL, "workspace must be 256-byte aligned");
   const uint64_t need = p1e_minimize_workspace_bytes(m, o);

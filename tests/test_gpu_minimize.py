@@ -144,3 +144,20 @@ def test_server_memory_admission(P):
     for (a, va), (b, vb) in zip(full, tight):
         assert a["J"] == b["J"] and np.array_equal(va, vb)
         assert b["t_admit"] >= b["t_submit"] and b["t_done"] >= b["t_admit"]
+
+
+def test_svk_is_not_served_or_minimized(P):
+    """The minimizer and the server cover the p-Laplacian and Neo-Hookean kinds; a St.
+    Venant-Kirchhoff mesh is refused with EINVAL before anything runs."""
+    prob = S.svk_beam_2d(8, 3, 1.0, 0.4, seed=2)
+    mesh = P.Mesh.from_problem(prob, modes=P.P1E_FP64)
+    v = torch.tensor(prob.vhat(), device="cuda")
+    with pytest.raises(P.P1EError) as ei:
+        P.mesh_minimize(mesh, v, history=5, max_iters=5, prec="fp64")
+    assert ei.value.status == -1
+    srv = P.Server(64 << 20, max_slots=2, history=5, max_iters=5, prec="fp64", use_graph=False,
+                   setup_threads=1)
+    with pytest.raises(P.P1EError) as ei:
+        srv.submit(prob, vhat0=prob.vhat())
+    assert ei.value.status == -1
+    srv.close()

@@ -44,6 +44,10 @@ def _cases():
         "plap_lshape_16": lambda: S.plaplace_lshape(16, p=3.0, seed=5),
         "nh2d_beam_60x13": lambda: S.neohooke_beam_2d(60, 13, 2.0, 13 * 2.0 / 60, seed=6),
         "nh3d_box_13x7x5": lambda: S.neohooke_box_3d(13, 7, 5, 1.0, 7 / 13, 5 / 13, seed=7),
+        # St. Venant-Kirchhoff (the extension named after eq. neoHook): energy, exact
+        # gradient and patch differences through the same tiles
+        "svk2d_beam_60x13": lambda: S.svk_beam_2d(60, 13, 2.0, 13 * 2.0 / 60, seed=12),
+        "svk3d_box_13x7x5": lambda: S.svk_box_3d(13, 7, 5, 1.0, 7 / 13, 5 / 13, seed=13),
         "twisted_bar_L1": lambda: S.twisted_bar(1),
         "twisted_bar_L2": lambda: S.twisted_bar(2),
     }

@@ -203,6 +203,58 @@ def test_neohooke_nonnegative_and_bad_elements(oracle_mod):
     assert r["nbad"] == P.ne and r["J"] == np.inf
 
 
+# ----------------------------------------------------------------------------- St. Venant-Kirchhoff
+def _svk(dim, amp=0.05, seed=13):
+    return (S.svk_beam_2d(6, 4, 1.0, 0.5, amp=amp, seed=seed) if dim == 2
+            else S.svk_box_3d(4, 3, 3, 1.0, 0.7, 0.6, amp=amp, seed=seed))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_svk_rigid_motions_and_homogeneous_closed_forms(oracle_mod, dim):
+    """W(I) = 0 and W(Q) = 0 for rotations (E = 0); J_grad(Qv + c) = J_grad(v); for
+    affine fields v = A x: J_grad = |Omega| W(A) with W from the closed forms of a uniaxial
+    stretch, (C1 + D1)(s + s^2/2)^2, and a simple shear, C1 (g^2/2 + g^4/4) + D1 g^4/4."""
+    rng = np.random.default_rng(17)
+    P = _svk(dim)
+    O = oracle_mod.Oracle(P)
+    vol = O.vol.sum()
+    assert abs(O.energy(P.coords)["Jgrad"]) < 1e-25 * O.C1 * vol
+    Q = _rand_rotation(rng, dim)
+    c = rng.standard_normal(dim)
+    assert abs(O.energy(P.coords @ Q.T + c)["Jgrad"]) < 1e-20 * O.C1 * vol
+    j0 = O.energy(P.v)["Jgrad"]
+    assert j0 > 0
+    assert O.energy(P.v @ Q.T + c)["Jgrad"] == pytest.approx(j0, rel=1e-9)
+    s, g = 0.07, 0.11
+    A = np.eye(dim)
+    A[0, 0] += s
+    want = (O.C1 + O.D1) * (s + s * s / 2) ** 2
+    assert O.energy(P.coords @ A.T)["Jgrad"] == pytest.approx(vol * want, rel=1e-12)
+    A = np.eye(dim)
+    A[0, 1] = g
+    want = O.C1 * (g**2 / 2 + g**4 / 4) + O.D1 * g**4 / 4
+    assert O.energy(P.coords @ A.T)["Jgrad"] == pytest.approx(vol * want, rel=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_svk_small_strain_limit(oracle_mod, dim):
+    """For F = I + s H, W / s^2 -> mu |sym H|^2 + (lambda/2) (tr H)^2, linear elasticity with
+    the Lame constants of (E, nu) computed here: pins E = (F^T F - I)/2 and both constants."""
+    rng = np.random.default_rng(23)
+    P = S.svk_beam_2d(2, 2, 1.0, 1.0) if dim == 2 else S.svk_box_3d(1, 1, 1)
+    O = oracle_mod.Oracle(P)
+    mu = P.E / (2 * (1 + P.nu))
+    lam = P.E * P.nu / ((1 + P.nu) * (1 - 2 * P.nu))
+    for _ in range(3):
+        H = rng.standard_normal((dim, dim))
+        sym = 0.5 * (H + H.T)
+        lin = mu * np.sum(sym * sym) + 0.5 * lam * np.trace(H) ** 2
+        for s in (1e-3, 5e-4):
+            v = P.coords @ (np.eye(dim) + s * H).T
+            W = O.densities(v)[0]
+            assert W / s**2 == pytest.approx(lin, rel=30 * s)
+
+
 # ----------------------------------------------------------------------------- p-Laplacian
 def _five_point(n):
     """Dirichlet 5-point Laplacian (4, -1) on the interior nodes of an n x n cell grid."""
@@ -270,10 +322,12 @@ def _tiny_problems():
         S.plaplace_square(n=4, p=1.5, seed=6),
         S.neohooke_beam_2d(4, 3, 1.0, 0.6, amp=0.05, seed=7),
         S.neohooke_box_3d(3, 2, 2, 1.0, 0.7, 0.6, amp=0.04, seed=9),
+        S.svk_beam_2d(4, 3, 1.0, 0.6, amp=0.05, seed=14),
+        S.svk_box_3d(3, 2, 2, 1.0, 0.7, 0.6, amp=0.04, seed=15),
     ]
 
 
-@pytest.mark.parametrize("idx", range(4))
+@pytest.mark.parametrize("idx", range(6))
 def test_exact_gradient_matches_brute_force(oracle_mod, idx):
     """Exact gradient vs central differences of the whole energy J; error ~ eps^2."""
     P = _tiny_problems()[idx]
@@ -288,10 +342,12 @@ def test_exact_gradient_matches_brute_force(oracle_mod, idx):
     assert 2.5 < errs[0] / errs[1] < 5.5, errs
 
 
-def test_gradient_translation_and_rotation_invariance(oracle_mod):
+@pytest.mark.parametrize("kind", ["neohooke", "svk"])
+def test_gradient_translation_and_rotation_invariance(oracle_mod, kind):
     """Over all nodes and with f = 0: sum_i g_ij = 0 (translation) and sum_i g_i (x) v_i is
-    symmetric (rotation invariance of the Neo-Hookean energy)."""
-    P = S.neohooke_box_3d(4, 3, 3, 1.0, 0.6, 0.6, amp=0.03, seed=12)
+    symmetric (rotation invariance of the energy)."""
+    box = S.neohooke_box_3d if kind == "neohooke" else S.svk_box_3d
+    P = box(4, 3, 3, 1.0, 0.6, 0.6, amp=0.03, seed=12)
     O = oracle_mod.Oracle(P)
     g, _ = O.grad_exact_full(P.v)
     g = g.reshape(-1, 3)
@@ -301,7 +357,7 @@ def test_gradient_translation_and_rotation_invariance(oracle_mod):
     assert np.abs(M - M.T).max() < 1e-11 * np.abs(M).max()
 
 
-@pytest.mark.parametrize("idx", range(4))
+@pytest.mark.parametrize("idx", range(6))
 def test_patch_fd_equals_brute_force_fd(oracle_mod, idx):
     """Section 6.1: the patch sums reproduce the full-energy central difference. With a
     dyadic field and step the perturbed values are exact, so only rounding separates them."""
