@@ -184,7 +184,8 @@ def main():
         flag = torch.empty(1, dtype=torch.int32, device=dev)
         for name, fn in (("fp64_jgrad", lambda: mesh.grad_exact(vhat0, "fp64", g=g, out3=out3,
                                                                   flag=flag)),
-                         ("patch_fd_fp64", lambda: mesh.grad_patch_fd(vhat0, prob.eps))):
+                         ("patch_fd_fp64", lambda: mesh.grad_patch_fd(vhat0, prob.eps)),
+                         ("patch_fd4_fp64", lambda: mesh.grad_patch_fd4(vhat0, prob.eps))):
             for _ in range(2):
                 fn()
             torch.cuda.synchronize()

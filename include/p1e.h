@@ -184,6 +184,14 @@ int p1e_grad_scale(p1e_mesh *mesh, const double *scale, double *g, void *stream)
 int p1e_grad_patch_fd(p1e_mesh *mesh, const double *vhat, double eps, double *g,
                       int32_t *flag, void *stream);
 
+/* The fourth-order central-difference scheme, the higher-accuracy generalisation Section 6.1
+ * mentions after eq. CD, on the same patches and under the same contract as
+ * p1e_grad_patch_fd:
+ * g[n] = [8 (S_n(eps) - S_n(-eps)) - (S_n(2 eps) - S_n(-2 eps))] / (12 eps) - b_n with
+ * S_n(h) = sum_{T in T^(n)} |T| W(F_T(v + h e_n)); truncation error O(eps^4). */
+int p1e_grad_patch_fd4(p1e_mesh *mesh, const double *vhat, double eps, double *g,
+                       int32_t *flag, void *stream);
+
 /* ------------------------------------------------------------------ minimization
  * A first-order minimization of J over vhat with the exact gradient, as the paper feeds J and
  * grad J to an optimizer (Section 7; the paper uses a trust-region method, this library

@@ -74,6 +74,8 @@ def _load():
         lib.orc_patches.restype = None
         lib.orc_grad_patch_fd.argtypes = [P, vp, vp, vp, vp, vp, dbl, i64, vp, vp, vp, vp]
         lib.orc_grad_patch_fd.restype = i64
+        lib.orc_grad_patch_fd4.argtypes = [P, vp, vp, vp, vp, vp, dbl, i64, vp, vp, vp, vp]
+        lib.orc_grad_patch_fd4.restype = i64
         _lib = lib
     return _lib
 
@@ -187,10 +189,11 @@ class Oracle:
             self._patch = (ptr, ent)
         return self._patch
 
-    def grad_patch_fd(self, v, eps, sample=None, with_cond=False):
+    def grad_patch_fd(self, v, eps, sample=None, with_cond=False, order=2):
         """Patch central differences on free DOFs (or on free-DOF positions ``sample``),
-        minus b. With ``with_cond`` also returns the per-DOF rounding scales
-        (cond = sum |T|(|W+|_abs + |W-|_abs), gabs = sum |T||W+ - W-|/(2 eps))."""
+        minus b; order 2 (+-eps) or 4 (+-eps, +-2 eps). With ``with_cond`` also returns the
+        per-DOF rounding scales (order 2: cond = sum |T|(|W+|_abs + |W-|_abs),
+        gabs = sum |T||W+ - W-|/(2 eps); order 4: see orc_grad_patch_fd4)."""
         v = self._full(v).copy()
         ptr, ent = self.patches()
         pos = np.arange(self.free_dofs.size) if sample is None else np.asarray(sample, np.int64)
@@ -198,23 +201,29 @@ class Oracle:
         g = np.zeros(dofs.size)
         cond = np.zeros(dofs.size)
         gabs = np.zeros(dofs.size)
-        self.lib.orc_grad_patch_fd(ctypes.byref(self._P), _ptr(v), _ptr(self.vol),
-                                   _ptr(self.dphi), _ptr(ptr), _ptr(ent), float(eps),
-                                   dofs.size, _ptr(dofs), _ptr(g), _ptr(cond), _ptr(gabs))
+        fn = self.lib.orc_grad_patch_fd if order == 2 else self.lib.orc_grad_patch_fd4
+        fn(ctypes.byref(self._P), _ptr(v), _ptr(self.vol), _ptr(self.dphi), _ptr(ptr),
+           _ptr(ent), float(eps), dofs.size, _ptr(dofs), _ptr(g), _ptr(cond), _ptr(gabs))
         g = g - self.b[dofs]
         return (g, cond, gabs) if with_cond else g
 
-    def grad_brute_fd(self, v, eps):
-        """Central differences of the full energy J (all elements re-evaluated): tiny
-        meshes only."""
+    def grad_brute_fd(self, v, eps, order=2):
+        """Central differences of the full energy J (all elements re-evaluated), order 2 or
+        4: tiny meshes only."""
         v = self._full(v).copy()
         g = np.zeros(self.free_dofs.size)
+
+        def J_at(n, v0, h):
+            v[n] = v0 + h
+            return self.energy(v)["J"]
+
         for q, n in enumerate(self.free_dofs):
             v0 = v[n]
-            v[n] = v0 + eps
-            jp = self.energy(v)["J"]
-            v[n] = v0 - eps
-            jm = self.energy(v)["J"]
+            if order == 2:
+                g[q] = (J_at(n, v0, eps) - J_at(n, v0, -eps)) / (2.0 * eps)
+            else:
+                d1 = J_at(n, v0, eps) - J_at(n, v0, -eps)
+                d2 = J_at(n, v0, 2 * eps) - J_at(n, v0, -2 * eps)
+                g[q] = (8.0 * d1 - d2) / (12.0 * eps)
             v[n] = v0
-            g[q] = (jp - jm) / (2.0 * eps)
         return g

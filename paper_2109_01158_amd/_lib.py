@@ -122,6 +122,7 @@ def lib():
         "p1e_energy": ([vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "p1e_grad_exact": ([vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "p1e_grad_patch_fd": ([vp, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "p1e_grad_patch_fd4": ([vp, vp, dbl, vp, vp, vp], ctypes.c_int),
         "p1e_energy_forces": ([vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "p1e_grad_gather": ([vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "p1e_grad_scale": ([vp, vp, vp, vp], ctypes.c_int),

@@ -116,6 +116,12 @@ def grad_gather(handle, prec, scale, g, stream=None):
                                   _stream_ptr(stream, g.device)))
 
 
+def grad_patch_fd4(handle, vhat, eps, g, flag, stream=None):
+    """p1e_grad_patch_fd4 (fourth-order scheme) on device tensors."""
+    check(L.lib().p1e_grad_patch_fd4(ctypes.c_void_p(handle), _dptr(vhat), float(eps),
+                                     _dptr(g), _dptr(flag), _stream_ptr(stream, flag.device)))
+
+
 def grad_scale(handle, scale, g, stream=None):
     """p1e_grad_scale: g *= scale in place (a device 1-element f64 tensor); no write when the
     scale is 1."""
@@ -246,6 +252,14 @@ class Mesh:
         g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device) if g is None else g
         grad_gather(self.handle, prec, scale, g, stream)
         return g
+
+    def grad_patch_fd4(self, vhat, eps, stream=None):
+        """Returns (g, flag): fourth-order patch central-difference gradient (FP64)."""
+        self._check_vhat(vhat)
+        g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device)
+        flag = torch.empty(1, dtype=torch.int32, device=self.device)
+        grad_patch_fd4(self.handle, vhat, eps, g, flag, stream)
+        return g, flag
 
     def grad_scale(self, g, scale, stream=None):
         """g *= scale in place (scale: device f64 tensor of one element); returns g."""

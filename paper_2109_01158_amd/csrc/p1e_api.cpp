@@ -652,7 +652,16 @@ int p1e_grad_patch_fd(p1e_mesh *m, const double *vhat, double eps, double *g, in
   if (rc) return rc;
   if (!(eps > 0.0) || !std::isfinite(eps)) return fail(P1E_EINVAL, "eps must be > 0");
   if ((!g && m->nfd > 0) || !flag) return fail(P1E_EINVAL, "null output pointer");
-  return run_grad_fd(m, vhat, eps, g, flag, (hipStream_t)stream);
+  return run_grad_fd(m, vhat, eps, 2, g, flag, (hipStream_t)stream);
+}
+
+int p1e_grad_patch_fd4(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t *flag,
+                       void *stream) {
+  int rc = check_call(m, vhat, P1E_FD);
+  if (rc) return rc;
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(P1E_EINVAL, "eps must be > 0");
+  if ((!g && m->nfd > 0) || !flag) return fail(P1E_EINVAL, "null output pointer");
+  return run_grad_fd(m, vhat, eps, 4, g, flag, (hipStream_t)stream);
 }
 
 int p1e_prof_enable(int on) {

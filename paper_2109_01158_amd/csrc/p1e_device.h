@@ -518,7 +518,10 @@ __device__ __forceinline__ double density(const T G[D][DIM], const Params &prm, 
 }
 
 
-enum { MODE_ENERGY = 0, MODE_FORCE = 1, MODE_FD = 2 };
+// MODE_FD: second-order central differences on +-eps; MODE_FD4: the fourth-order scheme on
+// +-eps and +-2 eps, [8 (S(eps) - S(-eps)) - (S(2eps) - S(-2eps))] / (12 eps)
+enum { MODE_ENERGY = 0, MODE_FORCE = 1, MODE_FD = 2, MODE_FD4 = 3 };
+constexpr bool is_fd(int mode) { return mode == MODE_FD || mode == MODE_FD4; }
 
 // one force-record entry: D words of T, loaded and stored as a single vector access
 template <typename T, int D>
@@ -589,7 +592,7 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
     W = svk_energy_stress<DIM, T>(G, prm.C1, prm.D1, vol, bad, P);
   } else if constexpr (MODE == MODE_FORCE) {
     W = pl_energy_stress<DIM, T>(G[0], prm.p, vol, bad, P[0]);
-  } else if constexpr (MODE == MODE_FD && KIND == P1E_NEOHOOKE) {
+  } else if constexpr (is_fd(MODE) && KIND == P1E_NEOHOOKE) {
     nv = nh_invariants<DIM, T>(G);
     W = nh_density<DIM, T>(nv, prm.C1, prm.D1, bad);
   } else {
@@ -611,11 +614,17 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
       }
     store_entries<T, D, K>(r, nep, er, out);
   }
-  if constexpr (MODE == MODE_FD) {
-    // Central differences of |T| W under v_n +- eps for every DOF n of this element: only
-    // row j of F changes, by +-eps grad phi_l (Section 6.1). Differenced per element; the
-    // patch sums happen in the tile's node phase and the halo rows.
-    const double inv2e = 1.0 / (2.0 * prm.eps);
+  if constexpr (is_fd(MODE)) {
+    // Central differences of |T| W under v_n +- h for every DOF n of this element: only
+    // row j of F changes, by +-h grad phi_l (Section 6.1). Differenced per element (h = eps,
+    // and in the fourth-order scheme also 2 eps); the patch sums happen in the tile's node
+    // phase and the halo rows.
+    const double eps = prm.eps;
+    // the scheme's combination of the differences W(+h) - W(-h) at h = eps and 2 eps
+    const double inv2e = 1.0 / (2.0 * eps), inv12e = 1.0 / (12.0 * eps);
+    auto scheme = [=](double d1, double d2) {
+      return MODE == MODE_FD ? d1 * inv2e : (8.0 * d1 - d2) * inv12e;
+    };
     T out[K * D];
     // (Neo-Hookean) det F - 1 and cof F = (1 + tr G) I - G^T (+ cof G in 3D), dDet F / dF
     double delta = 0.0;
@@ -659,36 +668,43 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
             c = fma((double)cf[j][m], (double)a[m], c);
             fa = fma((double)G[j][m], (double)a[m], fa);
           }
-          const double dm = delta - prm.eps * c;  // det F- - 1
-          const double x = quotient(2.0 * prm.eps * c, 1.0 + dm);
-          const bool ok = dm > -1.0 && x > -1.0;
-          if (!ok) bad = true;
-          const double lg = log1p_step(ok ? x : 0.0);
-          const double dW = prm.C1 * (4.0 * prm.eps * fa - 2.0 * lg) +
-                            4.0 * prm.D1 * prm.eps * c * delta;
-          if (!isfinite(dW)) bad = true;
-          out[l * D + j] = (T)((double)vol * dW * inv2e);
+          double dW[2];  // W(+h) - W(-h) for h = eps and (fourth order) 2 eps
+#pragma unroll
+          for (int u = 0; u < (MODE == MODE_FD4 ? 2 : 1); ++u) {
+            const double h = u == 0 ? eps : 2.0 * eps;
+            const double dm = delta - h * c;  // det F- - 1
+            const double x = quotient(2.0 * h * c, 1.0 + dm);
+            const bool ok = dm > -1.0 && x > -1.0;
+            if (!ok) bad = true;
+            const double lg = log1p_step(ok ? x : 0.0);
+            dW[u] = prm.C1 * (4.0 * h * fa - 2.0 * lg) + 4.0 * prm.D1 * h * c * delta;
+          }
+          const double q = (double)vol * scheme(dW[0], MODE == MODE_FD4 ? dW[1] : 0.0);
+          if (!isfinite(q)) bad = true;
+          out[l * D + j] = (T)q;
         }
         continue;
       }
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        T Gp[D][DIM], Gm[D][DIM];
+        auto dW = [&](double h) {  // W(+h) - W(-h): two density evaluations
+          T Gp[D][DIM], Gm[D][DIM];
 #pragma unroll
-        for (int jj = 0; jj < D; ++jj)
+          for (int jj = 0; jj < D; ++jj)
+#pragma unroll
+            for (int m = 0; m < DIM; ++m) {
+              Gp[jj][m] = G[jj][m];
+              Gm[jj][m] = G[jj][m];
+            }
 #pragma unroll
           for (int m = 0; m < DIM; ++m) {
-            Gp[jj][m] = G[jj][m];
-            Gm[jj][m] = G[jj][m];
+            Gp[j][m] = mad((T)h, a[m], G[j][m]);
+            Gm[j][m] = mad(-(T)h, a[m], G[j][m]);
           }
-#pragma unroll
-        for (int m = 0; m < DIM; ++m) {
-          Gp[j][m] = mad((T)prm.eps, a[m], G[j][m]);
-          Gm[j][m] = mad(-(T)prm.eps, a[m], G[j][m]);
-        }
-        const double Wp = density<DIM, D, KIND, T>(Gp, prm, bad);
-        const double Wm = density<DIM, D, KIND, T>(Gm, prm, bad);
-        out[l * D + j] = (T)((double)vol * (Wp - Wm) * inv2e);
+          return density<DIM, D, KIND, T>(Gp, prm, bad) - density<DIM, D, KIND, T>(Gm, prm, bad);
+        };
+        const double d1 = dW(eps), d2 = MODE == MODE_FD4 ? dW(2.0 * eps) : 0.0;
+        out[l * D + j] = (T)((double)vol * scheme(d1, d2));
       }
     }
     store_entries<T, D, K>(r, nep, er, out);

@@ -116,8 +116,8 @@ int run_energy(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t 
                hipStream_t s);
 int run_grad_exact(p1e_mesh *m, const double *vhat, int prec, double *g, double *out3,
                    int32_t *flag, hipStream_t s);
-int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t *flag,
-                hipStream_t s);
+int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, int order, double *g,
+                int32_t *flag, hipStream_t s);
 int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
                       hipStream_t s);
 int run_scale(p1e_mesh *m, const double *scale, double *g, hipStream_t s);

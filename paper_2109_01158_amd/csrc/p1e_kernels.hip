@@ -41,7 +41,7 @@ using namespace dev;
 #endif
 template <typename T, int MODE>
 constexpr int tile_threads() {
-  return MODE == MODE_FD ? (kTileElems >= 1024 ? kTileElems / 2 : kTileElems)
+  return is_fd(MODE) ? (kTileElems >= 1024 ? kTileElems / 2 : kTileElems)
                          : (kTileElems > P1E_TILE_THREADS ? P1E_TILE_THREADS : kTileElems);
 }
 // waves per SIMD to keep registers for: two FP32 tiles fit in LDS (160 KiB), so two
@@ -249,7 +249,8 @@ int launch_tile(p1e_mesh *m, const T *geo, const double *vhat, double *g, double
   if (m->ntiles == 0) return P1E_OK;
   const char *name = MODE == MODE_ENERGY ? "k_tile_energy"
                      : MODE == MODE_FORCE ? "k_tile_force"
-                                          : "k_tile_fd";
+                     : MODE == MODE_FD    ? "k_tile_fd"
+                                          : "k_tile_fd4";
   prof_begin(name, s);
   if (m->dev.geo_cls != nullptr)
     launch_tile_kernel<DIM, D, KIND, T, MODE, true>(m, geo, vhat, g, eps, s);
@@ -320,8 +321,10 @@ int run_grad_exact(p1e_mesh *m, const double *vhat, int prec, double *g, double 
   return dispatch<double, MODE_FORCE>(m, vhat, m->dev.geo64, 0.0, g, out3, flag, s);
 }
 
-int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, double *g, int32_t *flag,
-                hipStream_t s) {
+int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, int order, double *g,
+                int32_t *flag, hipStream_t s) {
+  if (order == 4)
+    return dispatch<double, MODE_FD4>(m, vhat, m->dev.geo64, eps, g, nullptr, flag, s);
   return dispatch<double, MODE_FD>(m, vhat, m->dev.geo64, eps, g, nullptr, flag, s);
 }
 

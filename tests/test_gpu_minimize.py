@@ -65,6 +65,20 @@ def test_p3_minimum_matches_scipy_lbfgs_on_the_oracle(P, oracle_mod):
     assert abs(O.energy(v)["J"] - rep["J"]) <= 1e-12 * abs(rep["J"])
 
 
+def test_lshape_p3_minimum_matches_scipy_lbfgs_on_the_oracle(P, oracle_mod):
+    """Benchmark 6's problem (p = 3, f = -10 on the L-shape of three unit squares, zero
+    boundary values) on a coarse level: the library's minimizer reaches the minimum that
+    scipy's L-BFGS finds on the oracle (a convex problem, so the minimum is unique)."""
+    prob = S.plaplace_lshape(6, p=3.0, f=-10.0, seed=1, amp=0.0)
+    O = oracle_mod.Oracle(prob)
+    fun = lambda x: (O.energy(x)["J"], O.grad_exact(x))
+    res = so.minimize(fun, prob.vhat(), jac=True, method="L-BFGS-B",
+                      options=dict(maxiter=5000, ftol=1e-15, gtol=1e-12, maxcor=10))
+    rep, v, _ = _minimize(P, prob, 600)
+    assert abs(rep["J"] - res.fun) <= 1e-10 * abs(res.fun)
+    assert abs(O.energy(v)["J"] - rep["J"]) <= 1e-12 * abs(rep["J"])
+
+
 def test_neohooke_minimization_decreases_energy(P, oracle_mod):
     prob = S.neohooke_beam_2d(40, 8, 2.0, 0.4, seed=0, amp=0.0)
     O = oracle_mod.Oracle(prob)

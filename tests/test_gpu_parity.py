@@ -161,6 +161,35 @@ def test_patch_fd_gradient(P, oracle_mod, name):
     assert _rel2(g, gex) <= 1e-6
 
 
+FD4_CASES = ["plap_p1.5_45", "plap_p5_37", "nh2d_beam_60x13", "nh3d_box_13x7x5",
+             "svk2d_beam_60x13", "svk3d_box_13x7x5"]
+
+
+@pytest.mark.parametrize("name", FD4_CASES)
+def test_fourth_order_patch_fd_gradient(P, oracle_mod, name):
+    """The fourth-order scheme against the oracle's, per DOF, with its rounding scales (the
+    oracle's cond and gabs for this scheme), and (deformations, whose second-order error is
+    truncation at this step) closer to the exact gradient than the second-order scheme."""
+    _note(f"[parity fd4] {name}")
+    prob = _get(name)
+    eps = prob.eps
+    O = oracle_mod.Oracle(prob)
+    gref, cond, gabs = O.grad_patch_fd(prob.v, eps, with_cond=True, order=4)
+    mesh, vhat = _setup(P, prob, P.P1E_FD)
+    g, flag = mesh.grad_patch_fd4(vhat, eps)
+    g2, _ = mesh.grad_patch_fd(vhat, eps)
+    torch.cuda.synchronize()
+    assert int(flag.item()) == 0
+    g, g2 = g.cpu().numpy(), g2.cpu().numpy()
+    v = prob.vhat()
+    tol = 32 * U * cond / (2 * eps) + 4 * U * (np.abs(v) + 2 * eps) / eps * gabs + 1e-12 * np.abs(gref)
+    bad = np.flatnonzero(np.abs(g - gref) > tol)
+    assert bad.size == 0, (bad[:5], g[bad[:5]], gref[bad[:5]], tol[bad[:5]])
+    if prob.kind != "plaplace":  # (the p-Laplacian differences are rounding-limited here)
+        gex = O.grad_exact(prob.v)
+        assert _rel2(g, gex) <= _rel2(g2, gex)
+
+
 def test_determinism_bitwise(P):
     prob = S.neohooke_box_3d(11, 9, 6, seed=2)
     mesh, vhat = _setup(P, prob, P.P1E_FP64 | P.P1E_MIXED | P.P1E_FD)

@@ -382,3 +382,33 @@ def test_patch_fd_sampled_positions(oracle_mod):
     full = O.grad_patch_fd(P.v, 1e-6)
     pos = np.array([0, 5, 17, len(full) - 1])
     assert np.array_equal(O.grad_patch_fd(P.v, 1e-6, sample=pos), full[pos])
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_fourth_order_patch_fd_equals_brute_force_and_converges(oracle_mod, idx):
+    """The fourth-order scheme on patches reproduces the same stencil applied to the whole
+    energy (dyadic field and steps: only rounding separates them). Its distance to the
+    exact gradient falls as eps^4 (ratio about 16 when eps halves) for smooth densities,
+    where the second-order scheme's falls as eps^2; St. Venant-Kirchhoff is a quartic in the
+    step, so there the scheme is exact up to rounding. (p = 3 is left out of the rate: an
+    element with a vanishing gradient makes |g|^3 only twice differentiable.)"""
+    P = _tiny_problems()[idx]
+    v = np.round(P.v * 2.0**30) / 2.0**30
+    O = oracle_mod.Oracle(P)
+    eps = 2.0 ** -12
+    gp, cond, _ = O.grad_patch_fd(v, eps, with_cond=True, order=4)
+    gb = O.grad_brute_fd(v, eps, order=4)
+    Jabs = O.energy(v)["Jgrad"] + np.abs(O.b).sum()
+    tol = 64 * 2.0**-53 * (cond + 4 * Jabs) / (2 * eps) + 1e-12 * np.abs(gb)
+    assert np.all(np.abs(gp - gb) <= tol)
+    ge = O.grad_exact(v)
+    scale = np.abs(ge).max()
+    hs = (0.05 * P.h, 0.025 * P.h)
+    e4 = [np.abs(O.grad_patch_fd(v, h, order=4) - ge).max() / scale for h in hs]
+    e2 = [np.abs(O.grad_patch_fd(v, h) - ge).max() / scale for h in hs]
+    assert 3.5 < e2[0] / e2[1] < 4.5, e2
+    if P.kind == "svk":
+        assert max(e4) < 1e-12
+    elif idx != 0:
+        assert e4[0] < e2[0]
+        assert 14 < e4[0] / e4[1] < 18, e4
