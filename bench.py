@@ -112,7 +112,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print(json.dumps({"error": "single-GPU build: bench.py measures one MI355X only; "
-                          "multi-GPU sharding is described in DESIGN.md, not implemented",
+                          "sharding across GPUs is not implemented",
                           "n_gpus": a.gpus}))
         sys.exit(2)
 
