@@ -76,8 +76,8 @@ def _tri():
     return coords, conn
 
 
-@pytest.mark.parametrize("case", ["dim", "kind_nh_ncomp", "index", "repeat", "degenerate",
-                                  "p", "nan_coord"])
+@pytest.mark.parametrize("case", ["dim", "kind_nh_ncomp", "kind_svk_ncomp", "kind_unknown",
+                                  "index", "repeat", "degenerate", "p", "nan_coord"])
 def test_mesh_create_rejects_bad_input(p1e, case):
     coords, conn = _tri()
     kw = dict(dim=2, kind="plaplace", conn=conn, coords=coords, p=3.0)
@@ -85,14 +85,16 @@ def test_mesh_create_rejects_bad_input(p1e, case):
     status = -1
     if case == "dim":
         kw["dim"] = 4
-    elif case == "kind_nh_ncomp":
+    elif case in ("kind_nh_ncomp", "kind_svk_ncomp", "kind_unknown"):
         # ncomp is derived from kind in the binding; force a mismatch through the raw ABI
         from paper_2109_01158_amd import _lib as L
-        desc = L.MeshDesc(2, 1, L.P1E_NEOHOOKE, 0, 4, 2,
+        kind = {"kind_nh_ncomp": L.P1E_NEOHOOKE, "kind_svk_ncomp": L.P1E_SVK,
+                "kind_unknown": 9}[case]
+        desc = L.MeshDesc(2, 1, kind, 0, 4, 2,
                           conn.ctypes.data, coords.ctypes.data, None, None, None, 2.0, 1.0, 1.0)
         h = ctypes.c_void_p()
         assert L.lib().p1e_mesh_create(ctypes.byref(desc), ctypes.byref(h)) == -1
-        assert b"ncomp" in L.lib().p1e_last_error()
+        assert (b"kind" if case == "kind_unknown" else b"ncomp") in L.lib().p1e_last_error()
         return
     elif case == "index":
         kw["conn"] = np.array([[0, 1, 7]], dtype=np.int32)

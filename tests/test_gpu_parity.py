@@ -255,16 +255,44 @@ def test_empty_and_all_prescribed(P):
     assert J == pytest.approx(1.0, rel=1e-14)
 
 
+def test_svk_is_finite_for_inverted_elements(P, oracle_mod):
+    """St. Venant-Kirchhoff has no barrier at det F = 0: a reflected box (det F = -1 in every
+    element) gives a finite energy and gradient equal to the oracle's, with no bad elements;
+    a NaN in vhat is still flagged."""
+    prob = S.svk_box_3d(5, 4, 3, 1.0, 0.8, 0.6, seed=3)
+    v = prob.v.copy()
+    v[:, 0] *= -1.0
+    vh = torch.tensor(v.reshape(-1)[prob.free_mask], device="cuda")
+    O = oracle_mod.Oracle(prob)
+    ref = O.energy(v)
+    assert ref["nbad"] == 0 and np.isfinite(ref["J"])
+    mesh = P.Mesh.from_problem(prob, modes=P.P1E_FP64 | P.P1E_FD)
+    g, out3, flag = mesh.grad_exact(vh, "fp64")
+    torch.cuda.synchronize()
+    assert int(flag.item()) == 0
+    assert _rel(out3[0].item(), ref["J"]) <= 1e-12
+    assert _rel2(g.cpu().numpy(), O.grad_exact(v)) <= 1e-12
+    vnan = vh.clone()
+    vnan[3] = float("nan")
+    out3, flag = mesh.energy(vnan, "fp64")
+    assert int(flag.item()) > 0 and np.isinf(out3[0].item())
+
+
 def test_abi_errors_on_device(P):
     prob = S.plaplace_square(n=4)
     mesh, vhat = _setup(P, prob, P.P1E_FP64)
     with pytest.raises(P.P1EError) as ei:
         mesh.energy(vhat, "mixed")  # not bound for mixed
     assert ei.value.status == -7
-    m2, _ = _setup(P, prob, P.P1E_FD)
     with pytest.raises(P.P1EError) as ei:
-        m2.grad_patch_fd(vhat, 0.0)
-    assert ei.value.status == -1
+        mesh.grad_patch_fd4(vhat, 1e-6)  # not bound for the differences
+    assert ei.value.status == -7
+    m2, _ = _setup(P, prob, P.P1E_FD)
+    for fd in (m2.grad_patch_fd, m2.grad_patch_fd4):
+        for eps in (0.0, -1e-6, float("nan")):
+            with pytest.raises(P.P1EError) as ei:
+                fd(vhat, eps)
+            assert ei.value.status == -1
     buf = torch.empty(64, dtype=torch.uint8, device="cuda")
     h = P.mesh_create(2, "plaplace", prob.conn, prob.coords, prob.dirichlet, p=3.0)
     try:
