@@ -1,21 +1,22 @@
 // p1e_device.h -- device-side building blocks shared by the single-mesh kernels
 // (p1e_kernels.hip) and the batched multi-request kernels (p1e_batch.hip): compensated sums,
-// block reductions, nodal field access, the densities and their stresses, and the bodies of
-// the element-tile pass and of the halo-row pass. Not part of the public ABI.
+// block reductions, nodal field access, the densities and their stresses (Neo-Hookean,
+// p-Laplacian, St. Venant-Kirchhoff), and the bodies of the element-tile pass and of the
+// halo-row pass. Not part of the public ABI.
 //
 // Precision. P1E_FP64 runs everything in double. P1E_MIXED evaluates the element algebra in
 // float on the displacement gradient G = F - I, with the cancellation-free forms
 //   |F|^2 - dim = 2 tr G + |G|^2,  det F - 1 = tr G + s2(G) + det G  (s2: sum of principal
 //   2x2 minors, absent in 2D),  (det F - 1) - log det F  by log_excess (double),
 //   F - F^-T = [(s2 + det G) I + (det F) G + G^T - cof G] / det F  (2D: cof terms reduce),
-// and accumulates energies and forces in double.
+// and accumulates the energies and the patch sums of the element forces in double.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <type_traits>
 #include <cstdint>
+#include <type_traits>
 
 #include "p1e_internal.h"
 
