@@ -273,17 +273,21 @@ __device__ __forceinline__ double log_excess(double d) {
   return k0 ? q0 : qk;
 }
 
-// log(1 + x) for the small relative changes of det F under a difference step: when every lane
-// of the wavefront has |x| < 1/64, by the alternating series x - x^2/2 + x^3/3 - ... to the
-// tenth power (the omitted terms are below 1e-19 of the sum), without division; otherwise as
-// x - log_excess(x). The branch is uniform over the wavefront.
-__device__ __forceinline__ double log1p_step(double x) {
-  if (__all(fabs(x) < 0.015625)) {
-    double t = scalar_const(-1.0 / 10.0);
+// log((1 + y) / (1 - y)) = 2 atanh y for |y| < 1: the log of the det F ratio of a difference
+// step. When every lane of the wavefront has |y| < 1/64, by the odd series
+// 2 (y + y^3/3 + ... + y^9/9) (the omitted terms are below 1e-19 of the sum), without
+// division; otherwise as x - log_excess(x) = log1p(x) with x = 2y / (1 - y). The branch is
+// uniform over the wavefront.
+__device__ __forceinline__ double log_ratio_step(double y) {
+  if (__all(fabs(y) < 0.015625)) {
+    const double w = y * y;
+    double t = scalar_const(1.0 / 9.0);
 #pragma unroll
-    for (int i = 9; i >= 1; --i) t = fma(t, x, scalar_const((i & 1 ? 1.0 : -1.0) / i));
-    return t * x;
+    for (int i = 7; i >= 3; i -= 2) t = fma(t, w, scalar_const(1.0 / i));
+    t = fma(t, w, 1.0);
+    return 2.0 * y * t;
   }
+  const double x = quotient(2.0 * y, 1.0 - y);
   return x - log_excess(x);
 }
 
@@ -627,11 +631,13 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
       return MODE == MODE_FD ? d1 * inv2e : (8.0 * d1 - d2) * inv12e;
     };
     T out[K * D];
-    // (Neo-Hookean) det F - 1 and cof F = (1 + tr G) I - G^T (+ cof G in 3D), dDet F / dF
-    double delta = 0.0;
+    // (Neo-Hookean) det F - 1, 1 / det F and cof F = (1 + tr G) I - G^T (+ cof G in 3D),
+    // dDet F / dF
+    double delta = 0.0, rdet = 0.0;
     T cf[DIM][DIM];
     if constexpr (KIND == P1E_NEOHOOKE) {
       delta = (double)nv.tr + (double)nv.s2 + (double)nv.dG;
+      rdet = 1.0 + delta > 0.0 ? quotient(1.0, 1.0 + delta) : -1.0;
 #pragma unroll
       for (int j = 0; j < DIM; ++j)
 #pragma unroll
@@ -655,12 +661,12 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
         }
       }
       if constexpr (KIND == P1E_NEOHOOKE) {
-        // F -> F +- eps e_j a^T changes det F by +- eps c with c = (cof F)_j . a (det F is
-        // linear in each row) and |F|^2 by +- 2 eps F_j . a + eps^2 |a|^2, so
-        //   W+ - W- = C1 (4 eps F_j . a - 2 log(det F+ / det F-)) + 4 D1 eps c (det F - 1),
-        // with log(det F+ / det F-) = log1p(x), x = 2 eps c / det F- (log1p_step): the same
-        // difference as two density evaluations, without their cancellation and with one
-        // logarithm instead of two.
+        // F -> F +- h e_j a^T changes det F by +- h c with c = (cof F)_j . a (det F is
+        // linear in each row) and |F|^2 by +- 2 h F_j . a + h^2 |a|^2, so
+        //   W+ - W- = C1 (4 h F_j . a - 2 log(det F+ / det F-)) + 4 D1 h c (det F - 1),
+        // with det F+ / det F- = (1 + y) / (1 - y), y = h c / det F (log_ratio_step): the
+        // same difference as two density evaluations, without their cancellation, with one
+        // logarithm instead of two and one division per element.
 #pragma unroll
         for (int j = 0; j < D; ++j) {
           double c = 0.0, fa = (double)a[j];
@@ -673,11 +679,10 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
 #pragma unroll
           for (int u = 0; u < (MODE == MODE_FD4 ? 2 : 1); ++u) {
             const double h = u == 0 ? eps : 2.0 * eps;
-            const double dm = delta - h * c;  // det F- - 1
-            const double x = quotient(2.0 * h * c, 1.0 + dm);
-            const bool ok = dm > -1.0 && x > -1.0;
+            const double y = h * c * rdet;
+            const bool ok = rdet > 0.0 && fabs(y) < 1.0;  // det F+ > 0 and det F- > 0
             if (!ok) bad = true;
-            const double lg = log1p_step(ok ? x : 0.0);
+            const double lg = log_ratio_step(ok ? y : 0.0);
             dW[u] = prm.C1 * (4.0 * h * fa - 2.0 * lg) + 4.0 * prm.D1 * h * c * delta;
           }
           const double q = (double)vol * scheme(dW[0], MODE == MODE_FD4 ? dW[1] : 0.0);
