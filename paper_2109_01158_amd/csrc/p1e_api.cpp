@@ -71,8 +71,8 @@ void prof_end(hipStream_t s) {
 static uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  uint64_t wref, bhat, conn_loc, geo64, geo32, geo_cls, ttile, trec, tlent, hrec, hpart, gw,
-      part, badp, total;
+  uint64_t wref, bhat, conn_loc, geo64, geo32, geo_cls, ttile, trec, tslot, tlent, hrec, hpart,
+      gw, part, badp, total;
 };
 
 static Layout make_layout(const p1e_mesh *m, int modes) {
@@ -94,6 +94,7 @@ static Layout make_layout(const p1e_mesh *m, int modes) {
   L.geo_cls = take(m->nclass ? (uint64_t)m->ne : 0);
   L.ttile = take(4ull * m->ttile.size());
   L.trec = take(4ull * m->trec.size());
+  L.tslot = take(2ull * m->tslot.size());
   L.tlent = take(2ull * m->tlent.size());
   L.hrec = take(4ull * m->hrec.size());
   L.hpart = take(8ull * m->nslots * m->d);
@@ -556,6 +557,7 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
             up(L.geo_cls, m->geo_cls.data(), m->geo_cls.size()) &&
             up(L.ttile, m->ttile.data(), 4 * m->ttile.size()) &&
             up(L.trec, m->trec.data(), 4 * m->trec.size()) &&
+            up(L.tslot, m->tslot.data(), 2 * m->tslot.size()) &&
             up(L.tlent, m->tlent.data(), 2 * m->tlent.size()) &&
             up(L.hrec, m->hrec.data(), 4 * m->hrec.size());
   hipError_t se = hipStreamSynchronize(s);
@@ -577,6 +579,7 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
   D.nclass = m->nclass;
   D.ttile = (const int4 *)(base + L.ttile);
   D.trec = (const int4 *)(base + L.trec);
+  D.tslot = (const uint16_t *)(base + L.tslot);
   D.tlent = (const uint16_t *)(base + L.tlent);
   D.hrec = (const int4 *)(base + L.hrec);
   D.hpart = (double *)(base + L.hpart);

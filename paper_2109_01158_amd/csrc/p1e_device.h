@@ -839,6 +839,7 @@ struct TileHead {
   int t;
   int4 ta, tb;  // ttile[t], ttile[t + 1]
   int4 rec[NPT];
+  int slot[NPT];  // LDS slot of the node's nodal value (tslot)
 };
 
 // records past the tile's nodes are zero
@@ -852,6 +853,7 @@ __device__ __forceinline__ void tile_head(const TileMesh &M, int t, TileHead<NPT
   for (int k = 0; k < NPT; ++k) {
     const int a = k * NT + tid;
     h.rec[k] = a < nloc ? M.trec[r0 + a] : make_int4(0, 0, 0, 0);
+    h.slot[k] = a < nloc ? (int)M.tslot[r0 + a] : 0;
   }
 }
 
@@ -950,7 +952,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
         o[j] = (T)(fr ? vj[j] - w[j] : w[j]);
         if (fr) bvn = fma(bj[j], vj[j], bvn);
       }
-      NodeVec<T, D>::store(sh.us, a, o);
+      NodeVec<T, D>::store(sh.us, h.slot[k], o);
       if ((rec[k].z >> 1) & 1) {  // owner
         if (NPT == 1) {
           sb = bvn;

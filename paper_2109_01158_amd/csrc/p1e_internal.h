@@ -45,7 +45,8 @@ struct TileMesh {
                                  // Neo-Hookean, 0 for the p-Laplacian), prescribed -> u
   const double *bhat = nullptr;  // [nfd] b = M f on the free DOFs
   // elements (internal order)
-  const uint16_t *conn_loc = nullptr;  // [dim+1][ne] vertex -> node index within the tile
+  const uint16_t *conn_loc = nullptr;  // [dim+1][ne] vertex -> LDS slot of its nodal value
+                                       // within the tile (tslot of the node)
   // element geometry: B^-1 entries (row l-1 = grad phi_l) and |T|, either per element as
   // [dim*dim+1][ne], or (geometry classes) as a table [nclass][dim*dim+1] indexed by geo_cls
   const double *geo64 = nullptr;    // FP64
@@ -56,6 +57,7 @@ struct TileMesh {
   const int4 *ttile = nullptr;  // [ntiles+1] {first element, first node record, first patch
                                 //  entry, 0}; the last one closes the ranges
   const int4 *trec = nullptr;   // [sum nloc] tile node records
+  const uint16_t *tslot = nullptr;  // [sum nloc] LDS slot of each tile node's nodal value
   const uint16_t *tlent = nullptr;  // local patch entries: offset (l kTileElems + e) d of the
                                     // element result in the tile's LDS, per node ascending e
   const int4 *hrec = nullptr;   // [nhalo] halo row records
@@ -86,6 +88,7 @@ struct p1e_mesh {
   std::vector<uint16_t> conn_loc;  // [k][ne]
   std::vector<int32_t> ttile;      // [ntiles+1][4]
   std::vector<int32_t> trec;       // [sum nloc][4]
+  std::vector<uint16_t> tslot;     // [sum nloc]
   std::vector<uint16_t> tlent;
   std::vector<int32_t> hrec;       // [nhalo][4]
   int64_t ntiles = 0, nhalo = 0, nslots = 0, ntnodes = 0;

@@ -19,6 +19,82 @@
 
 namespace p1e {
 
+// LDS slots for a tile's nodal values (a permutation of 0 .. nloc-1). The element pass reads
+// the values of each element's vertices, one element per lane; the reads of R neighbouring
+// lanes are served together, and two different nodes whose slots agree modulo R fall in the
+// same LDS banks and are served one after the other. Greedy colouring into the R residues:
+// the nodes at one vertex position in one group of R lanes (a "set") want different
+// residues; the nodes with the most partners choose first, each taking the residue (with
+// room left) that the fewest already placed members of its sets use. lv: [net][k] local
+// vertex indices in lane order.
+struct SlotScratch {
+  std::vector<int32_t> deg, mstart, mem, order, color, cap, next, setn, setcnt;
+};
+
+static void assign_slots(int nloc, int net, int k, int R, const std::vector<int32_t> &lv,
+                         std::vector<int32_t> &slot, SlotScratch &w) {
+  const int nsets = (net + R - 1) / R * k;
+  // the sets: for each group of R lanes and vertex position, its distinct nodes
+  w.setn.assign((size_t)nsets * R, 0);  // members of set s at [s R, s R + size)
+  std::vector<int32_t> &size = w.deg;   // reused below as the degree
+  size.assign(nsets, 0);
+  for (int g0 = 0, s0 = 0; g0 < net; g0 += R, s0 += k) {
+    const int g1 = std::min(net, g0 + R);
+    for (int l = 0; l < k; ++l) {
+      int32_t *m = &w.setn[(size_t)(s0 + l) * R];
+      int n = 0;
+      for (int le = g0; le < g1; ++le) {
+        const int a = lv[(size_t)le * k + l];
+        bool seen = false;
+        for (int q = 0; q < n; ++q) seen = seen || m[q] == a;
+        if (!seen) m[n++] = a;
+      }
+      size[s0 + l] = n;
+    }
+  }
+  // memberships of each node (node -> sets), and its number of partners
+  w.mstart.assign(nloc + 1, 0);
+  for (int s = 0; s < nsets; ++s)
+    for (int q = 0; q < size[s]; ++q) w.mstart[w.setn[(size_t)s * R + q] + 1] += 1;
+  for (int a = 0; a < nloc; ++a) w.mstart[a + 1] += w.mstart[a];
+  w.mem.resize(w.mstart[nloc]);
+  w.order.assign(nloc, 0);  // fill cursor for now
+  std::vector<int32_t> part(nloc, 0);
+  for (int s = 0; s < nsets; ++s)
+    for (int q = 0; q < size[s]; ++q) {
+      const int a = w.setn[(size_t)s * R + q];
+      w.mem[w.mstart[a] + w.order[a]++] = s;
+      part[a] += size[s] - 1;
+    }
+  // greedy colouring, most partners first
+  std::iota(w.order.begin(), w.order.end(), 0);
+  std::stable_sort(w.order.begin(), w.order.end(),
+                   [&](int x, int y) { return part[x] > part[y]; });
+  w.setcnt.assign((size_t)nsets * R, 0);  // placed members of set s with residue r
+  w.cap.assign(R, 0);
+  w.next.resize(R);
+  for (int s = 0; s < nloc; ++s) w.cap[s % R] += 1;
+  for (int r = 0; r < R; ++r) w.next[r] = r;
+  slot.assign(nloc, 0);
+  int cost[64];
+  for (int a : w.order) {
+    for (int r = 0; r < R; ++r) cost[r] = 0;
+    for (int i = w.mstart[a]; i < w.mstart[a + 1]; ++i) {
+      const int32_t *c = &w.setcnt[(size_t)w.mem[i] * R];
+      for (int r = 0; r < R; ++r) cost[r] += c[r];
+    }
+    int best = -1;
+    for (int r = 0; r < R; ++r)
+      if (w.cap[r] > 0 && (best < 0 || cost[r] < cost[best] ||
+                           (cost[r] == cost[best] && w.cap[r] > w.cap[best])))
+        best = r;
+    for (int i = w.mstart[a]; i < w.mstart[a + 1]; ++i) w.setcnt[(size_t)w.mem[i] * R + best] += 1;
+    w.cap[best] -= 1;
+    slot[a] = w.next[best];
+    w.next[best] += R;
+  }
+}
+
 // conn: [k][ne] internal node of each element vertex (internal element order). Uses
 // m->ninfo (internal nodes: first free DOF << 3 | free mask).
 int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
@@ -83,13 +159,18 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
   // ---- per tile: node records, local connectivity, local patch rows
   m->ttile.clear();
   m->trec.clear();
+  m->tslot.clear();
   m->tlent.clear();
   m->ttile.reserve(4 * (nt + 1));
   m->trec.reserve(4 * (size_t)std::accumulate(ntile_of.begin(), ntile_of.end(), int64_t(0)));
   m->tlent.reserve((size_t)k * ne + kEntAlign * nt);
   m->conn_loc.assign((size_t)k * ne, 0);
-  std::vector<int32_t> loc(nn, -1), cnt, pos, fill, nodes, seen_tiles(nn, 0);
+  std::vector<int32_t> loc(nn, -1), cnt, pos, fill, nodes, seen_tiles(nn, 0), lv, slot;
+  SlotScratch sw;
   nodes.reserve(kTileNodes);
+  // lanes whose vertex reads are served together: 128 bytes of nodal values (float x 4 per
+  // node for d = 3, x 2 for d = 2, x 1 for d = 1)
+  const int R = m->d == 3 ? 8 : m->d == 2 ? 16 : 32;
   for (int64_t t = 0; t < nt; ++t) {
     const int64_t e0 = tile_e[t], e1 = tile_e[t + 1];
     nodes.clear();
@@ -105,12 +186,17 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
     const int nloc = (int)nodes.size();
     for (int a = 0; a < nloc; ++a) loc[nodes[a]] = a;
     cnt.assign(nloc, 0);
+    lv.resize((size_t)(e1 - e0) * k);
     for (int64_t e = e0; e < e1; ++e)
       for (int l = 0; l < k; ++l) {
         const int a = loc[conn[(size_t)l * ne + e]];
-        m->conn_loc[(size_t)l * ne + e] = (uint16_t)a;
+        lv[(size_t)(e - e0) * k + l] = a;
         cnt[a] += 1;
       }
+    assign_slots(nloc, (int)(e1 - e0), k, R, lv, slot, sw);
+    for (int64_t e = e0; e < e1; ++e)
+      for (int l = 0; l < k; ++l)
+        m->conn_loc[(size_t)l * ne + e] = (uint16_t)slot[lv[(size_t)(e - e0) * k + l]];
     // local patch rows of the tile's free nodes, entries in ascending element
     const int64_t ent0 = (int64_t)m->tlent.size();
     m->ttile.insert(m->ttile.end(),
@@ -141,6 +227,7 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
       }
       const int32_t w = fr ? (pos[a] | (cnt[a] << 16)) : 0;
       m->trec.insert(m->trec.end(), {v, m->ninfo[v], z, w});
+      m->tslot.push_back((uint16_t)slot[a]);
       seen_tiles[v] += 1;
       loc[v] = -1;
     }
