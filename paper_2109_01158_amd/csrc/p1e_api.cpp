@@ -537,6 +537,7 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
                                 " bytes, got " + std::to_string(bytes));
   hipStream_t s = (hipStream_t)stream;
   char *base = (char *)buf;
+  if (mask & P1E_MIXED) colour_slots(m);  // host, once per mesh
   auto up = [&](uint64_t off, const void *src, size_t n) -> bool {
     if (n == 0) return true;
     return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s) == hipSuccess;

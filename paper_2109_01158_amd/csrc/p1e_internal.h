@@ -89,6 +89,7 @@ struct p1e_mesh {
   std::vector<int32_t> ttile;      // [ntiles+1][4]
   std::vector<int32_t> trec;       // [sum nloc][4]
   std::vector<uint16_t> tslot;     // [sum nloc]
+  bool slots_coloured = false;     // tslot / conn_loc hold coloured LDS slots (colour_slots)
   std::vector<uint16_t> tlent;
   std::vector<int32_t> hrec;       // [nhalo][4]
   int64_t ntiles = 0, nhalo = 0, nslots = 0, ntnodes = 0;
@@ -113,6 +114,7 @@ inline int64_t nblocks(int64_t n, int per = kBlock) { return (n + per - 1) / per
 
 // host setup of the element tiles, node order and halo rows (p1e_tiles.cpp)
 int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn);
+void colour_slots(p1e_mesh *m);
 
 // launchers (p1e_kernels.hip). All enqueue on stream and return P1E_OK or a status.
 int run_energy(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,

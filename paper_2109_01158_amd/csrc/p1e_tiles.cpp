@@ -165,12 +165,8 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
   m->trec.reserve(4 * (size_t)std::accumulate(ntile_of.begin(), ntile_of.end(), int64_t(0)));
   m->tlent.reserve((size_t)k * ne + kEntAlign * nt);
   m->conn_loc.assign((size_t)k * ne, 0);
-  std::vector<int32_t> loc(nn, -1), cnt, pos, fill, nodes, seen_tiles(nn, 0), lv, slot;
-  SlotScratch sw;
+  std::vector<int32_t> loc(nn, -1), cnt, pos, fill, nodes, seen_tiles(nn, 0);
   nodes.reserve(kTileNodes);
-  // lanes whose vertex reads are served together: 128 bytes of nodal values (float x 4 per
-  // node for d = 3, x 2 for d = 2, x 1 for d = 1)
-  const int R = m->d == 3 ? 8 : m->d == 2 ? 16 : 32;
   for (int64_t t = 0; t < nt; ++t) {
     const int64_t e0 = tile_e[t], e1 = tile_e[t + 1];
     nodes.clear();
@@ -186,17 +182,12 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
     const int nloc = (int)nodes.size();
     for (int a = 0; a < nloc; ++a) loc[nodes[a]] = a;
     cnt.assign(nloc, 0);
-    lv.resize((size_t)(e1 - e0) * k);
     for (int64_t e = e0; e < e1; ++e)
       for (int l = 0; l < k; ++l) {
         const int a = loc[conn[(size_t)l * ne + e]];
-        lv[(size_t)(e - e0) * k + l] = a;
+        m->conn_loc[(size_t)l * ne + e] = (uint16_t)a;  // slot = local index until coloured
         cnt[a] += 1;
       }
-    assign_slots(nloc, (int)(e1 - e0), k, R, lv, slot, sw);
-    for (int64_t e = e0; e < e1; ++e)
-      for (int l = 0; l < k; ++l)
-        m->conn_loc[(size_t)l * ne + e] = (uint16_t)slot[lv[(size_t)(e - e0) * k + l]];
     // local patch rows of the tile's free nodes, entries in ascending element
     const int64_t ent0 = (int64_t)m->tlent.size();
     m->ttile.insert(m->ttile.end(),
@@ -227,7 +218,7 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
       }
       const int32_t w = fr ? (pos[a] | (cnt[a] << 16)) : 0;
       m->trec.insert(m->trec.end(), {v, m->ninfo[v], z, w});
-      m->tslot.push_back((uint16_t)slot[a]);
+      m->tslot.push_back((uint16_t)a);
       seen_tiles[v] += 1;
       loc[v] = -1;
     }
@@ -235,8 +226,38 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
   m->ttile.insert(m->ttile.end(),
                   {(int32_t)ne, (int32_t)(m->trec.size() / 4), (int32_t)m->tlent.size(), 0});
   m->ntnodes = (int64_t)m->trec.size() / 4;
+  m->slots_coloured = false;
   if (m->tlent.size() >= (size_t(1) << 31)) return fail(P1E_EINVAL, "mesh too large for tiles");
   return P1E_OK;
+}
+
+// Replace the identity slots of build_tiles by coloured ones (assign_slots) in every tile:
+// conn_loc and tslot are rewritten together; results do not change (only where the nodal
+// values sit in LDS). Done once, when a mesh is first bound for mixed precision, whose
+// 16-byte float nodal values it is tuned for.
+void colour_slots(p1e_mesh *m) {
+  if (m->slots_coloured) return;
+  const int k = m->k;
+  const int64_t ne = m->ne;
+  // lanes whose vertex reads are served together: 128 bytes of nodal values (float x 4 per
+  // node for d = 3, x 2 for d = 2, x 1 for d = 1)
+  const int R = m->d == 3 ? 8 : m->d == 2 ? 16 : 32;
+  std::vector<int32_t> lv, slot;
+  SlotScratch sw;
+  for (int64_t t = 0; t < m->ntiles; ++t) {
+    const int64_t e0 = m->ttile[4 * t], e1 = m->ttile[4 * (t + 1)];
+    const int64_t r0 = m->ttile[4 * t + 1], nloc = m->ttile[4 * (t + 1) + 1] - r0;
+    lv.resize((size_t)(e1 - e0) * k);
+    for (int64_t e = e0; e < e1; ++e)
+      for (int l = 0; l < k; ++l)
+        lv[(size_t)(e - e0) * k + l] = m->conn_loc[(size_t)l * ne + e];
+    assign_slots((int)nloc, (int)(e1 - e0), k, R, lv, slot, sw);
+    for (int64_t e = e0; e < e1; ++e)
+      for (int l = 0; l < k; ++l)
+        m->conn_loc[(size_t)l * ne + e] = (uint16_t)slot[lv[(size_t)(e - e0) * k + l]];
+    for (int64_t a = 0; a < nloc; ++a) m->tslot[r0 + a] = (uint16_t)slot[a];
+  }
+  m->slots_coloured = true;
 }
 
 }  // namespace p1e
