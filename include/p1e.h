@@ -141,7 +141,10 @@ uint64_t p1e_workspace_bytes(const p1e_mesh *mesh, int mode_mask);
 
 /* Lay the mesh arrays and scratch out in the caller-owned device buffer dev_buf (aligned to
  * info.alignment, at least p1e_workspace_bytes(mesh, mode_mask) bytes) and upload them on
- * stream. Synchronises stream before returning. P1E_ENOMEM if bytes is too small. */
+ * stream. Synchronises stream before returning. P1E_ENOMEM if bytes is too small. The
+ * first bind whose mask holds P1E_MIXED also reorders, on the host and once per handle, where
+ * each tile keeps its nodal values in LDS (fewer LDS bank conflicts for 16-byte float reads);
+ * results do not depend on it. Not thread-safe against other calls on the same handle. */
 int p1e_mesh_bind(p1e_mesh *mesh, void *dev_buf, uint64_t bytes, int mode_mask, void *stream);
 
 /* Energy (Section 5). vhat: [n_free_dofs] FP64. out3: 3 doubles {J, J_grad, b.v}.
