@@ -319,6 +319,23 @@ def test_internal_order_does_not_change_results(P, oracle_mod):
     assert np.linalg.norm(f0 - f1) <= 1e-9 * np.linalg.norm(f0)
 
 
+@pytest.mark.parametrize("name", ["nh3d_box_13x7x5", "plap_square_33", "nh2d_beam_60x13",
+                                  "plap3d_box"])
+def test_lds_slot_colouring_changes_nothing(P, name):
+    """Binding for mixed precision recolours where each tile keeps its nodal values in LDS;
+    FP64 results must be bitwise those of the same mesh bound without it (identity slots)."""
+    prob = _plap3d() if name == "plap3d_box" else _cases()[name]()
+    v = torch.tensor(prob.vhat(), device="cuda")
+    outs = []
+    for modes in (P.P1E_FP64 | P.P1E_FD, P.P1E_FP64 | P.P1E_FD | P.P1E_MIXED):
+        m = P.Mesh.from_problem(prob, modes=modes)
+        g, o, _ = m.grad_exact(v, "fp64")
+        f, _ = m.grad_patch_fd(v, 1e-6)
+        outs.append((g.clone(), o.clone(), f.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("name", ["nh3d_box_13x7x5", "plap_square_33", "nh2d_beam_60x13"])
 def test_geometry_classes_match_per_element_geometry(P, name):
     """Classed geometry (one record per class of elements whose records agree to 2^-40)
