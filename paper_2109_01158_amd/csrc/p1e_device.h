@@ -906,14 +906,15 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
     for (int i = 0; i < TQ; ++i)
       if (i * NT + tid < ntq) tq[i] = geo[i * NT + tid];
   }
-  // 1. nodal field of the tile; b.v of the nodes this tile owns. Per node all loads first
-  // (one memory round trip), then the arithmetic; component j's DOF is the node's first free
-  // DOF plus the free components before j.
+  // 1. nodal field of the tile; b.v of the nodes this tile owns (only the owner reads b).
+  // Per node all loads first (one memory round trip), then the arithmetic; component j's DOF
+  // is the node's first free DOF plus the free components before j.
   double sb = 0.0, cb = 0.0;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int a = k * NT + tid;
     const int mask = rec[k].y & 7;
+    const bool own = (rec[k].z >> 1) & 1;
     double w[D], vj[D], bj[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) w[j] = 0.0, vj[j] = 0.0, bj[j] = 0.0;
@@ -926,7 +927,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
         if ((mask >> j) & 1) {
           const int f = fb + __popc(mask & ((1 << j) - 1));
           vj[j] = vhat[f];
-          bj[j] = M.bhat[f];
+          if (own) bj[j] = M.bhat[f];
         }
     }
     if (k == 0) {  // registers -> LDS while the nodal loads are in flight
@@ -953,7 +954,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
         if (fr) bvn = fma(bj[j], vj[j], bvn);
       }
       NodeVec<T, D>::store(sh.us, h.slot[k], o);
-      if ((rec[k].z >> 1) & 1) {  // owner
+      if (own) {
         if (NPT == 1) {
           sb = bvn;
         } else {
