@@ -21,14 +21,15 @@
 #include "p1e_internal.h"
 
 #ifndef P1E_STREAM_NT
-#define P1E_STREAM_NT 0
+#define P1E_STREAM_NT 1
 #endif
 namespace p1e {
 namespace dev {
 
 // Loads of arrays that one pass reads exactly once (connectivity, geometry, patch entries).
-// With P1E_STREAM_NT they are marked non-temporal, leaving cache capacity to the data that
-// is re-read (nodal values shared by neighbouring tiles).
+// With P1E_STREAM_NT (the default) they are marked non-temporal, leaving cache capacity to
+// the data that is re-read (nodal values shared by neighbouring tiles, the halo partials
+// that the halo kernel reads next).
 template <typename T>
 __device__ __forceinline__ T stream_load(const T *p) {
 #if P1E_STREAM_NT
