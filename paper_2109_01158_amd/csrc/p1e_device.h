@@ -1053,16 +1053,18 @@ __device__ __forceinline__ void halo_row(const TileMesh &M, int h, double *__res
   for (int j = 0; j < D; ++j) acc[j] = 0.0;
   const double *hp = M.hpart + (int64_t)hr.x * D;
   // slots in rounds of 4 whose loads are issued together; the sum stays sequential in tile
-  // order (absent slots re-read the last one and add zero)
+  // order (absent slots load nothing and add zero)
   for (int q = 0; q < hr.y; q += 4) {
     double x[4][D];
     bool ok[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       ok[u] = q + u < hr.y;
-      const int qq = ok[u] ? q + u : hr.y - 1;
 #pragma unroll
-      for (int j = 0; j < D; ++j) x[u][j] = hp[qq * D + j];
+      for (int j = 0; j < D; ++j) x[u][j] = 0.0;
+      if (ok[u])
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[u][j] = hp[(q + u) * D + j];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
