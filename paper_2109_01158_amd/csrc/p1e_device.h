@@ -26,7 +26,8 @@
 namespace p1e {
 namespace dev {
 
-// Loads of arrays that one pass reads exactly once (connectivity, geometry, patch entries).
+// Loads of arrays that one pass reads exactly once (connectivity, geometry, patch entries,
+// LDS slots).
 // With P1E_STREAM_NT (the default) they are marked non-temporal, leaving cache capacity to
 // the data that is re-read (nodal values shared by neighbouring tiles, the halo partials
 // that the halo kernel reads next).
@@ -854,7 +855,7 @@ __device__ __forceinline__ void tile_head(const TileMesh &M, int t, TileHead<NPT
   for (int k = 0; k < NPT; ++k) {
     const int a = k * NT + tid;
     h.rec[k] = a < nloc ? M.trec[r0 + a] : make_int4(0, 0, 0, 0);
-    h.slot[k] = a < nloc ? (int)M.tslot[r0 + a] : 0;
+    h.slot[k] = a < nloc ? (int)stream_load(M.tslot + r0 + a) : 0;  // read once
   }
 }
 
