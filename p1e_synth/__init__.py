@@ -13,6 +13,7 @@ from .meshes import (  # noqa: F401
     kuhn_box_mesh,
     kuhn_bar_level,
     lshape_tri_mesh,
+    jitter_interior,
 )
 from .problems import (  # noqa: F401
     Problem,
@@ -24,5 +25,6 @@ from .problems import (  # noqa: F401
     twisted_bar,
     plaplace_lshape,
     config_problem,
+    with_load,
     CONFIGS,
 )

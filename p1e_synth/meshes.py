@@ -67,6 +67,26 @@ def kuhn_bar_level(level, lx=0.4, ly=0.01, lz=0.01):
     return kuhn_box_mesh(80 * r, 2 * r, 2 * r, 0.0, lx, -ly / 2, ly / 2, -lz / 2, lz / 2)
 
 
+def jitter_interior(coords, h, frac=0.2, seed=0):
+    """A copy of ``coords`` whose nodes strictly inside the bounding box are moved by
+    independent offsets drawn from U[-frac h, frac h] per coordinate (seeded); nodes on the
+    bounding box stay, so the domain, its boundary faces and the clamped faces are unchanged.
+
+    On the right-triangle and Kuhn meshes above every element height is at least h / sqrt(2)
+    and a vertex moves by at most frac h sqrt(2) along any face normal of the form
+    (e_a - e_b) / sqrt(2) or e_a, so no element degenerates or flips for frac < 0.25. The moved
+    meshes have as many element shapes as elements (an unstructured mesh for the kernels).
+    """
+    coords = np.array(coords, dtype=np.float64, copy=True)
+    lo, hi = coords.min(axis=0), coords.max(axis=0)
+    tol = 1e-9 * max(1.0, float(np.abs(coords).max()))
+    inside = np.all((coords > lo + tol) & (coords < hi - tol), axis=1)
+    rng = np.random.default_rng(seed)
+    off = rng.uniform(-frac * h, frac * h, size=coords.shape)
+    coords[inside] += off[inside]
+    return coords
+
+
 def lshape_tri_mesh(n):
     """L-shaped domain [-1,1]^2 minus (0,1]x[-1,0) as three unit squares, n cells per unit.
 

@@ -16,7 +16,8 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-from .meshes import kuhn_bar_level, kuhn_box_mesh, lshape_tri_mesh, rect_tri_mesh
+from .meshes import (jitter_interior, kuhn_bar_level, kuhn_box_mesh, lshape_tri_mesh,
+                     rect_tri_mesh)
 
 
 @dataclass
@@ -69,10 +70,13 @@ def _dirichlet_on(coords, ncomp, pred):
     return mask
 
 
-def plaplace_square(n=32, p=3.0, f=-10.0, seed=0, eps=1e-6, amp=1.0):
+def plaplace_square(n=32, p=3.0, f=-10.0, seed=0, eps=1e-6, amp=1.0, jitter=0.0):
     """Unit square, (n+1)^2 nodes, 2n^2 right triangles, zero Dirichlet boundary,
-    interior v ~ amp*U[-1,1]."""
+    interior v ~ amp*U[-1,1]. jitter > 0: interior nodes moved by up to jitter/n per
+    coordinate (jitter_interior, seed + 1000)."""
     coords, conn = rect_tri_mesh(n, n)
+    if jitter > 0.0:
+        coords = jitter_interior(coords, 1.0 / n, jitter, seed + 1000)
     tol = 0.5 / n
     dmask = _dirichlet_on(
         coords, 1,
@@ -102,34 +106,43 @@ def _neohooke_random(coords, conn, dim, dmask, load_vec, seed, h, eps, name, amp
         E=2e8, nu=0.3, eps=eps, h=h, amp=amp)
 
 
-def neohooke_beam_2d(nx=2240, ny=224, lx=2.0, ly=0.2, seed=0, eps=1e-6, amp=None):
-    """Beam [0,lx]x[0,ly], left edge clamped (v = x), f = (0, -3.5e7)."""
+def neohooke_beam_2d(nx=2240, ny=224, lx=2.0, ly=0.2, seed=0, eps=1e-6, amp=None, jitter=0.0):
+    """Beam [0,lx]x[0,ly], left edge clamped (v = x), f = (0, -3.5e7). jitter > 0: interior
+    nodes moved by up to jitter*h per coordinate (jitter_interior, seed + 1000)."""
     coords, conn = rect_tri_mesh(nx, ny, 0.0, lx, 0.0, ly)
     h = lx / nx
+    if jitter > 0.0:
+        coords = jitter_interior(coords, min(h, ly / ny), jitter, seed + 1000)
     dmask = _dirichlet_on(coords, 2, lambda X: X[:, 0] < 0.5 * h)
     return _neohooke_random(coords, conn, 2, dmask, (0.0, -3.5e7), seed, h, eps,
                             f"neohooke_beam_{nx}x{ny}", amp)
 
 
-def neohooke_box_3d(nx=460, ny=46, nz=46, lx=1.0, ly=0.1, lz=0.1, seed=0, eps=1e-6, amp=None):
-    """Box [0,lx]x[0,ly]x[0,lz], Kuhn tets, face x = 0 clamped (v = x), f = (0,-3.5e7,0)."""
+def neohooke_box_3d(nx=460, ny=46, nz=46, lx=1.0, ly=0.1, lz=0.1, seed=0, eps=1e-6, amp=None,
+                    jitter=0.0):
+    """Box [0,lx]x[0,ly]x[0,lz], Kuhn tets, face x = 0 clamped (v = x), f = (0,-3.5e7,0).
+    jitter > 0: interior nodes moved by up to jitter*h per coordinate (jitter_interior,
+    seed + 1000)."""
     coords, conn = kuhn_box_mesh(nx, ny, nz, 0.0, lx, 0.0, ly, 0.0, lz)
     h = lx / nx
+    if jitter > 0.0:
+        coords = jitter_interior(coords, min(h, ly / ny, lz / nz), jitter, seed + 1000)
     dmask = _dirichlet_on(coords, 3, lambda X: X[:, 0] < 0.5 * h)
     return _neohooke_random(coords, conn, 3, dmask, (0.0, -3.5e7, 0.0), seed, h, eps,
                             f"neohooke_box_{nx}x{ny}x{nz}", amp)
 
 
-def svk_beam_2d(nx=60, ny=13, lx=2.0, ly=0.4, seed=0, eps=1e-6, amp=None):
+def svk_beam_2d(nx=60, ny=13, lx=2.0, ly=0.4, seed=0, eps=1e-6, amp=None, jitter=0.0):
     """The beam of neohooke_beam_2d (same mesh, clamp, load, E, nu and displacement draw)
     with the St. Venant-Kirchhoff density."""
-    pb = neohooke_beam_2d(nx, ny, lx, ly, seed, eps, amp)
+    pb = neohooke_beam_2d(nx, ny, lx, ly, seed, eps, amp, jitter)
     return replace(pb, kind="svk", name=f"svk_beam_{nx}x{ny}")
 
 
-def svk_box_3d(nx=13, ny=7, nz=5, lx=1.0, ly=0.5, lz=0.4, seed=0, eps=1e-6, amp=None):
+def svk_box_3d(nx=13, ny=7, nz=5, lx=1.0, ly=0.5, lz=0.4, seed=0, eps=1e-6, amp=None,
+               jitter=0.0):
     """The box of neohooke_box_3d with the St. Venant-Kirchhoff density."""
-    pb = neohooke_box_3d(nx, ny, nz, lx, ly, lz, seed, eps, amp)
+    pb = neohooke_box_3d(nx, ny, nz, lx, ly, lz, seed, eps, amp, jitter)
     return replace(pb, kind="svk", name=f"svk_box_{nx}x{ny}x{nz}")
 
 
@@ -167,6 +180,30 @@ def plaplace_lshape(n, p=3.0, f=-10.0, seed=0, amp=1.0, eps=1e-5):
         conn=conn, dirichlet=dmask, dirichlet_values=np.zeros((coords.shape[0], 1)),
         load=np.full((coords.shape[0], 1), float(f)), v=v, p=float(p), eps=eps, h=1.0 / n,
         amp=amp)
+
+
+def with_load(prob, kind, seed=0, scale=None):
+    """A copy of ``prob`` with another nodal load f (its P1 interpolant is the load):
+    "linear": f_j(x) = scale_j (1 + sum_m c_jm x_m / L) with fixed coefficients c in
+    [-1, 1] (L = the domain's largest extent); "random": f_j = scale_j * U[-1, 1] per node
+    (seeded). scale defaults to the magnitude of the problem's own constant load (per
+    component, 1 where it is zero)."""
+    X = prob.coords
+    d = prob.ncomp
+    if scale is None:
+        base = np.abs(prob.load).max(axis=0)
+        scale = np.where(base > 0, base, 1.0)
+    scale = np.broadcast_to(np.asarray(scale, dtype=np.float64), (d,))
+    if kind == "linear":
+        L = float((X.max(axis=0) - X.min(axis=0)).max())
+        c = np.array([[0.5, -0.75, 0.25], [-0.25, 1.0, -0.5], [0.75, 0.5, -1.0]])[:d, :prob.dim]
+        f = scale[None, :] * (1.0 + X @ c.T / L)
+    elif kind == "random":
+        rng = np.random.default_rng(seed)
+        f = scale[None, :] * rng.uniform(-1.0, 1.0, size=(prob.nn, d))
+    else:
+        raise ValueError(kind)
+    return replace(prob, load=np.ascontiguousarray(f), name=f"{prob.name}_{kind}load")
 
 
 # The five workloads: small p-Laplacian, 2D beam, 3D box (the headline), the serving mix

@@ -55,12 +55,21 @@ def test_counts_match_table1_and_patch_rows(p1e):
         p1e.mesh_destroy(h)
 
 
-def test_dirichlet_load_constant_matches_oracle(oracle_mod, p1e):
-    """The constant part of b.v (prescribed DOFs) equals the oracle's b = M f there."""
-    P = S.neohooke_beam_2d(9, 4, 1.0, 0.3, seed=3)
+@pytest.mark.parametrize("load", ["const", "linear", "random"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dirichlet_load_constant_matches_oracle(oracle_mod, p1e, load, dim):
+    """The constant part of b.v (prescribed DOFs) equals the oracle's b = M f there, for the
+    constant, a linear and a seeded random nodal load, on a structured (2D) and a jittered
+    (3D) mesh."""
+    if dim == 2:
+        P = S.neohooke_beam_2d(9, 4, 1.0, 0.3, seed=3)
+    else:
+        P = S.neohooke_box_3d(5, 4, 3, 1.0, 0.8, 0.6, seed=4, jitter=0.2)
+    if load != "const":
+        P = S.with_load(P, load, seed=8)
     O = oracle_mod.Oracle(P)
     want = float(np.sum((O.b * O.vD)[~O.free]))
-    h = p1e.mesh_create(2, "neohooke", P.conn, P.coords, P.dirichlet, P.dirichlet_values,
+    h = p1e.mesh_create(dim, "neohooke", P.conn, P.coords, P.dirichlet, P.dirichlet_values,
                         P.load, C1=1.0, D1=1.0)
     try:
         info = p1e.mesh_get_info(h)

@@ -295,9 +295,11 @@ def test_plaplace_homogeneity_and_euler(oracle_mod, p):
 
 # ----------------------------------------------------------------------------- load vector
 def test_load_vector_integrates_linear_loads(oracle_mod):
-    """sum_i (M f)_i = integral of the P1 load; exact for a linear f on a box."""
+    """Section 3.2: b = M f with the consistent P1 mass matrix. sum_i (M f)_i is the integral
+    of the P1 load (exact for a linear f on a box), and b . v is the L2 product of two P1
+    functions, which the consistent mass matrix integrates exactly: for f = v = x it is the
+    integral of x^2 (a lumped mass would be off by O(h^2), about 2e-2 here)."""
     P = S.neohooke_box_3d(5, 3, 4, 2.0, 0.6, 0.8)
-    O = oracle_mod.Oracle(P)
     X = P.coords
     f = np.stack([1.0 + X[:, 0], 2.0 - X[:, 1], 3.0 * X[:, 2]], axis=1)
     P.load = f
@@ -306,13 +308,91 @@ def test_load_vector_integrates_linear_loads(oracle_mod):
     want = [vol * (1 + 1.0), vol * (2 - 0.3), vol * 3 * 0.4]
     got = O2.b.reshape(-1, 3).sum(axis=0)
     assert np.allclose(got, want, rtol=1e-13)
-    # b . v is the L2 product of P1 functions: integral of x * x over the box for f = v = x
     P.load = np.stack([X[:, 0]] * 3, axis=1)
     O3 = oracle_mod.Oracle(P)
     v = np.stack([X[:, 0]] * 3, axis=1)
     exact = 3 * (2.0**3 / 3) * 0.6 * 0.8
-    h2 = (2.0 / 5) ** 2
-    assert O3.b @ v.reshape(-1) == pytest.approx(exact, rel=2 * h2)
+    assert O3.b @ v.reshape(-1) == pytest.approx(exact, rel=1e-13)
+
+
+def _simplex_volumes(coords, conn):
+    """|T| = |det [x_1 - x_0, ...]| / dim! with numpy's determinant (test-side geometry)."""
+    dim = coords.shape[1]
+    B = coords[conn[:, 1:]] - coords[conn[:, :1]]  # [ne, dim, dim], rows = edges
+    return np.abs(np.linalg.det(B)) / (2.0 if dim == 2 else 6.0)
+
+
+def _quadrature_l2(coords, conn, f, w):
+    """sum_T of the integral of f_h w_h over T (f_h, w_h the P1 interpolants, one component)
+    by quadrature rules exact for quadratics, written independently of any mass matrix:
+    2D: the three edge midpoints, weights |T|/3; 3D: the symmetric four-point rule with
+    barycentric points (a, b, b, b), a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20, weights |T|/4."""
+    vol = _simplex_volumes(coords, conn)
+    k = conn.shape[1]
+    fe, we = f[conn], w[conn]  # [ne, k]
+    if k == 3:
+        lam = np.array([[0.5, 0.5, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5]])
+    else:
+        a, b = (5 + 3 * np.sqrt(5)) / 20, (5 - np.sqrt(5)) / 20
+        lam = np.full((4, 4), b) + (a - b) * np.eye(4)
+    fq = fe @ lam.T  # values at the quadrature points
+    wq = we @ lam.T
+    return float(np.sum(vol * (fq * wq).mean(axis=1)))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_load_vector_is_the_p1_l2_product(oracle_mod, dim):
+    """b(f) . w = integral of f_h w_h for random nodal f and w on a jittered (unstructured)
+    mesh, against quadrature exact for the P1 x P1 product. A lumped or mis-weighted mass
+    matrix, a dropped diagonal term or a swapped vertex fails by far more than rounding."""
+    if dim == 2:
+        P = S.neohooke_beam_2d(9, 5, 1.0, 0.6, seed=3, jitter=0.2)
+    else:
+        P = S.neohooke_box_3d(5, 4, 3, 1.0, 0.8, 0.6, seed=4, jitter=0.2)
+    P = S.with_load(P, "random", seed=21)
+    O = oracle_mod.Oracle(P)
+    rng = np.random.default_rng(22)
+    w = rng.uniform(-1.0, 1.0, size=(P.nn, P.ncomp))
+    for j in range(P.ncomp):
+        got = O.b.reshape(-1, P.ncomp)[:, j] @ w[:, j]
+        want = _quadrature_l2(P.coords, P.conn, P.load[:, j], w[:, j])
+        assert got == pytest.approx(want, rel=1e-13, abs=1e-13 * np.abs(P.load).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_load_vector_entries_for_a_nodal_indicator(oracle_mod, dim):
+    """Entries of the element mass matrix |T| (1 + delta_ab)/((dim+1)(dim+2)) (Section 3.2):
+    for f = the indicator of one interior node i (one component), b_i = 2 area(T^i) /
+    ((dim+1)(dim+2)), b_j = (sum of |T| over the elements holding both i and j) /
+    ((dim+1)(dim+2)) for the neighbours j, and 0 elsewhere and in the other components;
+    areas from test-side geometry on a jittered mesh."""
+    if dim == 2:
+        P = S.neohooke_beam_2d(6, 5, 1.0, 0.8, seed=5, jitter=0.2)
+    else:
+        P = S.neohooke_box_3d(4, 4, 3, 1.0, 1.0, 0.75, seed=6, jitter=0.2)
+    X = P.coords
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    inner = np.flatnonzero(np.all((X > lo + 1e-9) & (X < hi - 1e-9), axis=1))
+    i = int(inner[len(inner) // 2])
+    comp = dim - 1
+    f = np.zeros((P.nn, P.ncomp))
+    f[i, comp] = 1.0
+    P.load = f
+    O = oracle_mod.Oracle(P)
+    b = O.b.reshape(-1, P.ncomp)
+    vol = _simplex_volumes(P.coords, P.conn)
+    den = (dim + 1) * (dim + 2)
+    holds = np.any(P.conn == i, axis=1)
+    want = np.zeros(P.nn)
+    want[i] = 2.0 * vol[holds].sum() / den
+    for e in np.flatnonzero(holds):
+        for j in P.conn[e]:
+            if j != i:
+                want[j] += vol[e] / den
+    scale = want[i]
+    assert np.abs(b[:, comp] - want).max() <= 1e-14 * scale
+    others = [c for c in range(P.ncomp) if c != comp]
+    assert np.all(b[:, others] == 0.0)
 
 
 # ----------------------------------------------------------------------------- gradients
