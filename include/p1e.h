@@ -82,12 +82,22 @@ extern "C" {
 #define P1E_INPUT_ORDER 1
 /* P1E_FULL_GEOMETRY: always store B^-1 and |T| per element. By default, element records
  * (B^-1, |T|) that agree to 2^-40 of each component's largest magnitude share one class, and
- * a mesh with at most 64 classes (uniformly refined structured meshes have a few) stores one
- * record per class and a one-byte class per element; the elements of a class then use its
- * first record, which differs from their own only by the rounding of node coordinates. */
+ * a mesh with at most 64 classes (uniformly refined structured meshes have a few) whose every
+ * record lies within 2^-42 of its class's first record (relative to each component's largest
+ * magnitude; the deviation is reported in p1e_mesh_info) stores one record per class and a
+ * one-byte class per element; the elements of a class then use its first record, which
+ * differs from their own only by the rounding of node coordinates. */
 #define P1E_FULL_GEOMETRY 4
 
 typedef struct p1e_mesh p1e_mesh;
+
+/* Material constants of a deformation density from Young's modulus E > 0 and Poisson's ratio
+ * -1 < nu < 1/2 (host only). kind = P1E_NEOHOOKE: the constants of Benchmark 2 (Section 7),
+ * C1 = mu / 2 and D1 = K / 2 with mu = E / (2 (1 + nu)) and the bulk modulus
+ * K = E / (3 (1 - 2 nu)), used unchanged in 2D; kind = P1E_SVK: C1 = mu and D1 = lambda / 2
+ * with lambda = E nu / ((1 + nu)(1 - 2 nu)). Writes *C1, *D1; P1E_EINVAL for another kind,
+ * null outputs or E, nu out of range. */
+int p1e_material_constants(int kind, double E, double nu, double *C1, double *D1);
 
 /* Mesh and problem description (all arrays are host memory, row-major, 0-based). */
 typedef struct p1e_mesh_desc {
@@ -122,6 +132,8 @@ typedef struct p1e_mesh_info {
   int64_t n_tile_nodes; /* sum over tiles of the distinct nodes of the tile */
   int64_t n_halo_rows;  /* free nodes whose patch spans several tiles (or no element) */
   int64_t n_halo_slots; /* partial patch sums of halo rows (one per tile and halo row) */
+  double geometry_class_deviation; /* largest |record - class record| of an element, relative
+                                      to the component's largest magnitude (0: no classes) */
 } p1e_mesh_info;
 
 /* Build a mesh handle: validates the description, computes element geometry (|T| and basis

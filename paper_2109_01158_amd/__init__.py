@@ -10,7 +10,7 @@ from ._lib import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     Mesh, Server, energy, energy_forces, grad_exact, grad_gather, grad_patch_fd, grad_patch_fd4,
-    grad_scale, mesh_bind, mesh_create, mesh_destroy, mesh_minimize, minimize,
+    grad_scale, material_constants, mesh_bind, mesh_create, mesh_destroy, mesh_minimize, minimize,
     minimize_workspace_bytes, mesh_get_info, neohooke_constants, prof_collect, prof_enable,
     prof_reset, svk_constants, workspace_bytes,
 )

@@ -58,7 +58,7 @@ class MeshInfo(ctypes.Structure):
         ("alignment", ctypes.c_uint64), ("geometry_classes", ctypes.c_int32),
         ("reserved", ctypes.c_int32), ("n_tiles", ctypes.c_int64),
         ("n_tile_nodes", ctypes.c_int64), ("n_halo_rows", ctypes.c_int64),
-        ("n_halo_slots", ctypes.c_int64),
+        ("n_halo_slots", ctypes.c_int64), ("geometry_class_deviation", ctypes.c_double),
     ]
 
 
@@ -116,6 +116,8 @@ def lib():
     sig = {
         "p1e_mesh_create": ([ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)], ctypes.c_int),
         "p1e_mesh_destroy": ([vp], None),
+        "p1e_material_constants": ([ctypes.c_int, dbl, dbl, ctypes.POINTER(dbl),
+                                    ctypes.POINTER(dbl)], ctypes.c_int),
         "p1e_mesh_get_info": ([vp, ctypes.POINTER(MeshInfo)], ctypes.c_int),
         "p1e_workspace_bytes": ([vp, ctypes.c_int], u64),
         "p1e_mesh_bind": ([vp, vp, u64, ctypes.c_int, vp], ctypes.c_int),

@@ -28,23 +28,35 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr()) if (t is not None and t.numel() > 0) else None
 
 
+def _check_buf(t, dtype, n, device, name):
+    """Raise ValueError unless t is a contiguous tensor of dtype with n entries on device: the
+    library reads and writes exactly that many entries through the raw pointer."""
+    if (not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device
+            or not t.is_contiguous() or t.numel() != n):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of {n} entries on {device}")
+
+
 def _stream_ptr(stream, device):
     s = torch.cuda.current_stream(device) if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def material_constants(kind, E, nu):
+    """p1e_material_constants: (C1, D1) of kind "neohooke" or "svk" from (E, nu)."""
+    c1, d1 = ctypes.c_double(), ctypes.c_double()
+    check(L.lib().p1e_material_constants(_KINDS[kind], float(E), float(nu), ctypes.byref(c1),
+                                         ctypes.byref(d1)))
+    return c1.value, d1.value
+
+
 def neohooke_constants(E, nu):
-    """Benchmark 2: C1 = mu/2, D1 = K/2, mu = E/(2(1+nu)), K = E/(3(1-2nu))."""
-    mu = E / (2.0 * (1.0 + nu))
-    K = E / (3.0 * (1.0 - 2.0 * nu))
-    return mu / 2.0, K / 2.0
+    """Benchmark 2's C1 = mu/2, D1 = K/2 (computed by the library)."""
+    return material_constants("neohooke", E, nu)
 
 
 def svk_constants(E, nu):
-    """St. Venant-Kirchhoff: C1 = mu, D1 = lambda/2 with the Lame constants of (E, nu)."""
-    mu = E / (2.0 * (1.0 + nu))
-    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
-    return mu, lam / 2.0
+    """St. Venant-Kirchhoff C1 = mu, D1 = lambda/2 (computed by the library)."""
+    return material_constants("svk", E, nu)
 
 
 # ------------------------------------------------------------------ 1:1 entry points
@@ -214,11 +226,14 @@ class Mesh:
             pass
 
     def _check_vhat(self, vhat):
-        if (not isinstance(vhat, torch.Tensor) or vhat.dtype != torch.float64
-                or vhat.device != self.device or not vhat.is_contiguous()
-                or vhat.numel() != self.n_free_dofs):
-            raise ValueError(f"vhat must be a contiguous float64 tensor of {self.n_free_dofs} "
-                             f"entries on {self.device}")
+        _check_buf(vhat, torch.float64, self.n_free_dofs, self.device, "vhat")
+
+    def _out(self, t, dtype, n, name):
+        """A caller-supplied output buffer after the same checks as vhat, or a new one."""
+        if t is None:
+            return torch.empty(n, dtype=dtype, device=self.device)
+        _check_buf(t, dtype, n, self.device, name)
+        return t
 
     def energy(self, vhat, prec="mixed", stream=None):
         """Returns (out3 = [J, J_grad, b.v] f64 tensor, flag i32[1]) -- asynchronous."""
@@ -231,9 +246,9 @@ class Mesh:
     def grad_exact(self, vhat, prec="mixed", stream=None, g=None, out3=None, flag=None):
         """Returns (g, out3, flag): exact dJ/dvhat, the energy of the same call, bad count."""
         self._check_vhat(vhat)
-        g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device) if g is None else g
-        out3 = torch.empty(3, dtype=torch.float64, device=self.device) if out3 is None else out3
-        flag = torch.empty(1, dtype=torch.int32, device=self.device) if flag is None else flag
+        g = self._out(g, torch.float64, self.n_free_dofs, "g")
+        out3 = self._out(out3, torch.float64, 3, "out3")
+        flag = self._out(flag, torch.int32, 1, "flag")
         grad_exact(self.handle, vhat, prec, g, out3, flag, stream)
         return g, out3, flag
 
@@ -241,15 +256,17 @@ class Mesh:
         """Energy plus the exact gradient kept for grad_gather; returns (out3, flag,
         generation)."""
         self._check_vhat(vhat)
-        out3 = torch.empty(3, dtype=torch.float64, device=self.device) if out3 is None else out3
-        flag = torch.empty(1, dtype=torch.int32, device=self.device) if flag is None else flag
+        out3 = self._out(out3, torch.float64, 3, "out3")
+        flag = self._out(flag, torch.int32, 1, "flag")
         energy_forces(self.handle, vhat, prec, out3, flag, stream)
         self.forces_gen += 1
         return out3, flag, self.forces_gen
 
     def grad_gather(self, prec="mixed", scale=None, stream=None, g=None):
         """g = scale * (the gradient kept by the last energy_forces call)."""
-        g = torch.empty(self.n_free_dofs, dtype=torch.float64, device=self.device) if g is None else g
+        g = self._out(g, torch.float64, self.n_free_dofs, "g")
+        if scale is not None:
+            _check_buf(scale, torch.float64, 1, self.device, "scale")
         grad_gather(self.handle, prec, scale, g, stream)
         return g
 
@@ -263,10 +280,8 @@ class Mesh:
 
     def grad_scale(self, g, scale, stream=None):
         """g *= scale in place (scale: device f64 tensor of one element); returns g."""
-        if g.dtype != torch.float64 or not g.is_contiguous() or g.numel() != self.n_free_dofs:
-            raise ValueError("g must be a contiguous float64 tensor of n_free_dofs entries")
-        if scale.dtype != torch.float64 or scale.numel() != 1 or scale.device != g.device:
-            raise ValueError("scale must be one float64 value on the device of g")
+        _check_buf(g, torch.float64, self.n_free_dofs, self.device, "g")
+        _check_buf(scale, torch.float64, 1, self.device, "scale")
         grad_scale(self.handle, scale, g, stream)
         return g
 
@@ -286,8 +301,14 @@ def minimize_workspace_bytes(handle, history=5, max_iters=200, prec="fp64"):
 
 
 def minimize(handle, vhat, history, max_iters, prec, ws, stream=None):
-    """p1e_minimize: vhat (device f64, in/out), ws a device uint8 tensor (256-byte aligned).
-    Returns the report as a dict."""
+    """p1e_minimize: vhat (device f64, in/out, n_free_dofs entries), ws a device uint8 tensor
+    (256-byte aligned, at least minimize_workspace_bytes). Returns the report as a dict."""
+    n = int(mesh_get_info(handle)["n_free_dofs"])
+    if not isinstance(ws, torch.Tensor) or ws.device.type != "cuda":
+        raise ValueError("ws must be a device tensor")
+    _check_buf(vhat, torch.float64, n, ws.device, "vhat")
+    if ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous uint8 tensor")
     o = L.LbfgsOpts(int(history), int(max_iters), PREC[prec], 0)
     rep = L.MinReport()
     check(L.lib().p1e_minimize(ctypes.c_void_p(handle), _dptr(vhat), ctypes.byref(o),
@@ -304,6 +325,7 @@ def _aligned_buffer(nbytes, device, align=256):
 
 def mesh_minimize(mesh, vhat, history=5, max_iters=200, prec="fp64", stream=None):
     """Minimize in place from vhat on a bound Mesh (allocates the workspace with torch)."""
+    mesh._check_vhat(vhat)
     nb = minimize_workspace_bytes(mesh.handle, history, max_iters, prec)
     raw, ws = _aligned_buffer(nb, mesh.device)
     rep = minimize(mesh.handle, vhat, history, max_iters, prec, ws, stream)

@@ -267,8 +267,11 @@ void internal_order(const p1e_mesh_desc *D, std::vector<int32_t> &nperm,
 // [B^-1, |T|] differ only by the rounding of the node coordinates. Each record component is
 // quantized to 2^-40 of that component's largest magnitude over the mesh; records with equal
 // quantized keys share one class, represented by the first such record (element order).
-// When there are at most kMaxGeoClasses classes, the mesh keeps one table entry per class
-// and a one-byte class per element instead of the per-element arrays.
+// When there are at most kMaxGeoClasses classes and every element's record lies within
+// kClassDeviation of its class's record (relative to each component's largest magnitude),
+// the mesh keeps one table entry per class and a one-byte class per element instead of the
+// per-element arrays. The bound keeps the substitution's effect on G, the stress and the
+// forces at a few times 2^-42 relative, far inside the 1e-12 budget of FP64 results.
 void classify_geometry(p1e_mesh *m) {
   const int dd = m->dim * m->dim + 1;
   const int64_t ne = m->ne;
@@ -310,6 +313,17 @@ void classify_geometry(p1e_mesh *m) {
     }
     cls[e] = (uint8_t)id;
   }
+  // the substituted record must stay within kClassDeviation of each element's own record
+  // (relative to the component's largest magnitude), else keep per-element records
+  double dev = 0.0;
+  for (int64_t e = 0; e < ne; ++e)
+    for (int q = 0; q < dd; ++q) {
+      const double own = m->geo64[(size_t)q * ne + e], rep = tab[(size_t)cls[e] * dd + q];
+      dev = std::max(dev, std::fabs(own - rep) * inv[q]);
+    }
+  dev = std::ldexp(dev, -40);  // inv[q] carries the 2^40 of the key
+  if (!(dev <= kClassDeviation)) return;
+  m->class_dev = dev;
   m->nclass = (int)(keys.size() / dd);
   m->geo_tab = std::move(tab);
   m->geo_cls = std::move(cls);
@@ -496,6 +510,25 @@ int p1e_mesh_create(const p1e_mesh_desc *D, p1e_mesh **out) {
 
 void p1e_mesh_destroy(p1e_mesh *m) { delete m; }
 
+int p1e_material_constants(int kind, double E, double nu, double *C1, double *D1) {
+  if (!C1 || !D1) return fail(P1E_EINVAL, "null output pointer");
+  if (!(E > 0.0) || !std::isfinite(E) || !(nu > -1.0 && nu < 0.5))
+    return fail(P1E_EINVAL, "need E > 0 and -1 < nu < 1/2");
+  const double mu = E / (2.0 * (1.0 + nu));
+  if (kind == P1E_NEOHOOKE) {
+    const double K = E / (3.0 * (1.0 - 2.0 * nu));  // bulk modulus
+    *C1 = mu / 2.0;
+    *D1 = K / 2.0;
+  } else if (kind == P1E_SVK) {
+    const double lambda = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    *C1 = mu;
+    *D1 = lambda / 2.0;
+  } else {
+    return fail(P1E_EINVAL, "material constants exist for P1E_NEOHOOKE and P1E_SVK only");
+  }
+  return P1E_OK;
+}
+
 int p1e_mesh_get_info(const p1e_mesh *m, p1e_mesh_info *o) {
   if (!m || !o) return fail(P1E_EINVAL, "null argument");
   std::memset(o, 0, sizeof(*o));
@@ -514,6 +547,7 @@ int p1e_mesh_get_info(const p1e_mesh *m, p1e_mesh_info *o) {
   o->dirichlet_bv = m->dirichlet_bv;
   o->alignment = kAlign;
   o->geometry_classes = m->nclass;
+  o->geometry_class_deviation = m->class_dev;
   o->n_tiles = m->ntiles;
   o->n_tile_nodes = m->ntnodes;
   o->n_halo_rows = m->nhalo;

@@ -27,6 +27,7 @@ static_assert((4 * kTileElems) * 3 < 65536, "patch entry offsets fit 16 bits");
 constexpr int kBlock = 256;        // threads per block of the halo-row and vector kernels
 constexpr uint64_t kAlign = 256;   // alignment of every sub-array in the bound buffer
 constexpr int kMaxGeoClasses = 64; // geometry classes kept as one-byte indices
+constexpr double kClassDeviation = 0x1p-42;  // largest relative record change of a class
 
 // Device view of a bound mesh (all arrays in the caller's buffer). Internal numbering: the
 // elements in tile order, the nodes in order of first use by the elements.
@@ -80,6 +81,7 @@ struct p1e_mesh {
   // host copies (kept so the mesh can be bound again)
   std::vector<double> geo64;       // [dim*dim+1][ne] (empty when classed)
   int nclass = 0;                  // distinct element geometries when <= kMaxGeoClasses, else 0
+  double class_dev = 0.0;          // largest relative change of a record by its class
   std::vector<uint8_t> geo_cls;    // [ne] class of each element
   std::vector<double> geo_tab;     // [nclass][dim*dim+1]
   std::vector<int32_t> ninfo;      // [nn] internal order

@@ -177,3 +177,45 @@ def test_geometry_classes(p1e):
     h = p1e.mesh_create(2, "plaplace", P3.conn, X, P3.dirichlet, p=3.0)
     assert p1e.mesh_get_info(h)["geometry_classes"] == 0
     p1e.mesh_destroy(h)
+
+
+@pytest.mark.parametrize("rel", [0.0, 1e-15, 3e-14, 1e-13, 3e-13, 1e-12])
+def test_geometry_class_deviation_bound(p1e, rel):
+    """Whenever a mesh keeps geometry classes, every element's own record lies within 2^-42
+    (relative to each component's largest magnitude) of the class record it is evaluated
+    with, as reported in the mesh info; coordinates perturbed by more than that fall back to
+    per-element records. The unperturbed structured meshes keep their classes."""
+    P = S.neohooke_box_3d(9, 5, 4, 1.0, 5 / 9, 4 / 9)
+    h0 = 1.0 / 9
+    X = P.coords + rel * h0 * np.random.default_rng(1).uniform(-1, 1, P.coords.shape)
+    h = p1e.mesh_create(3, "neohooke", P.conn, X, P.dirichlet, P.dirichlet_values, P.load,
+                        C1=1.0, D1=1.0)
+    try:
+        info = p1e.mesh_get_info(h)
+        if info["geometry_classes"] > 0:
+            assert 0.0 <= info["geometry_class_deviation"] <= 2.0 ** -42
+        else:
+            assert info["geometry_class_deviation"] == 0.0
+        if rel == 0.0:
+            assert info["geometry_classes"] == 6
+        if rel >= 1e-12:
+            assert info["geometry_classes"] == 0
+    finally:
+        p1e.mesh_destroy(h)
+
+
+def test_material_constants_match_the_oracle_and_table2(oracle_mod, p1e):
+    """p1e_material_constants (host only) gives the constants the oracle uses; the oracle's
+    Neo-Hookean pair is pinned by Table 2 (a wrong D1 moves the level-1 energy off its
+    printed digits). Invalid kinds and out-of-range E, nu are refused."""
+    for E, nu in ((2e8, 0.3), (1.0, 0.0), (7.5e3, -0.5), (3e9, 0.49)):
+        assert p1e.material_constants("neohooke", E, nu) == pytest.approx(
+            oracle_mod.neohooke_constants(E, nu), rel=1e-15)
+        assert p1e.material_constants("svk", E, nu) == pytest.approx(
+            oracle_mod.svk_constants(E, nu), rel=1e-15)
+    for kind, E, nu in (("plaplace", 2e8, 0.3), ("neohooke", -1.0, 0.3),
+                        ("neohooke", 2e8, 0.5), ("svk", 2e8, -1.0),
+                        ("neohooke", float("nan"), 0.3)):
+        with pytest.raises(p1e.P1EError) as ei:
+            p1e.material_constants(kind, E, nu)
+        assert ei.value.status == -1

@@ -105,8 +105,8 @@ def _mix():
     ]
 
 
-def _serve(P, probs, iters, max_slots, pool_bytes=256 << 20, use_graph=True):
-    srv = P.Server(pool_bytes, max_slots=max_slots, history=5, max_iters=iters, prec="fp64",
+def _serve(P, probs, iters, max_slots, pool_bytes=256 << 20, use_graph=True, prec="fp64"):
+    srv = P.Server(pool_bytes, max_slots=max_slots, history=5, max_iters=iters, prec=prec,
                    use_graph=use_graph, setup_threads=4)
     ids = [srv.submit(p, vhat0=p.vhat()) for p in probs]
     out, peak = {}, 0
@@ -141,6 +141,38 @@ def test_server_mix_equals_solo_bitwise(P):
         # the single-request minimizer runs the same kernels
         rep, vm, _ = _minimize(P, prob, iters)
         assert rep["J"] == r["J"] and np.array_equal(vm, v)
+
+
+def test_server_mixed_precision_against_the_oracle(P, oracle_mod):
+    """Serving in mixed precision (FP32 element algebra, FP64 log term, sums and L-BFGS
+    vectors): every request's reported final energy agrees with the oracle's FP64 energy at
+    the returned vhat to the mixed bar 1e-5, the mix equals each request run alone (bitwise)
+    and p1e_minimize in mixed precision (bitwise); the distance to the FP64 server's final
+    energy is reported, not asserted (the two runs take different iterates)."""
+    probs = _mix()
+    iters = 25
+    mixed, peak = _serve(P, probs, iters, max_slots=8, prec="mixed")
+    assert peak >= 4
+    fp64, _ = _serve(P, probs, iters, max_slots=8, prec="fp64")
+    for (r, v), (r64, _), prob in zip(mixed, fp64, probs):
+        assert r["status"] in (0, 1, 2), r
+        ref = oracle_mod.Oracle(prob).energy(_full(prob, v))
+        assert ref["nbad"] == 0
+        err = abs(r["J"] - ref["J"]) / abs(ref["J"])
+        print(f"[serve mixed] {prob.name}: J rel err vs oracle {err:.2e}, "
+              f"vs FP64 server {abs(r['J'] - r64['J']) / abs(r64['J']):.2e}", flush=True)
+        assert err <= 1e-5
+    for (r, v), prob in list(zip(mixed, probs))[:3]:
+        (rs, vs), = _serve(P, [prob], iters, max_slots=1, use_graph=False, prec="mixed")[0]
+        assert rs["J"] == r["J"] and np.array_equal(vs, v)
+        rep, vm, _ = _minimize(P, prob, iters, prec="mixed")
+        assert rep["J"] == r["J"] and np.array_equal(vm, v)
+
+
+def _full(prob, vhat):
+    v = prob.dirichlet_values.reshape(-1).copy()
+    v[prob.free_mask] = vhat
+    return v.reshape(prob.v.shape)
 
 
 def test_server_memory_admission(P):

@@ -50,7 +50,31 @@ def _cases():
         "svk3d_box_13x7x5": lambda: S.svk_box_3d(13, 7, 5, 1.0, 7 / 13, 5 / 13, seed=13),
         "twisted_bar_L1": lambda: S.twisted_bar(1),
         "twisted_bar_L2": lambda: S.twisted_bar(2),
+        # non-constant nodal loads (b = M f with the full consistent mass matrix): a linear
+        # load on the structured box (geometry classes) ...
+        "nh3d_box_13x7x5_linload": lambda: S.with_load(
+            S.neohooke_box_3d(13, 7, 5, 1.0, 7 / 13, 5 / 13, seed=18), "linear"),
+        # ... and jittered meshes (interior nodes moved by up to 0.2 h per coordinate: every
+        # element has its own shape, so the per-element geometry path runs and the Morton
+        # order sees irregular centroids) with random and linear loads
+        "nh3d_box_jit_randload": lambda: S.with_load(
+            S.neohooke_box_3d(13, 7, 5, 1.0, 7 / 13, 5 / 13, seed=14, jitter=0.2), "random",
+            seed=1),
+        "nh2d_beam_jit_linload": lambda: S.with_load(
+            S.neohooke_beam_2d(60, 13, 2.0, 13 * 2.0 / 60, seed=15, jitter=0.2), "linear"),
+        "plap_square_jit_randload": lambda: S.with_load(
+            S.plaplace_square(n=29, p=3.0, seed=16, jitter=0.2), "random", seed=2),
+        "svk3d_box_jit_linload": lambda: S.with_load(
+            S.svk_box_3d(13, 7, 5, 1.0, 7 / 13, 5 / 13, seed=17, jitter=0.2), "linear"),
+        # p = 1.5 with v = 0 on a sub-region: elements with grad v = 0 (gradient 0 there)
+        "plap_p1.5_flat": lambda: _flat(S.plaplace_square(n=31, p=1.5, seed=19)),
     }
+
+
+def _flat(prob, x_cut=0.4):
+    """v = 0 on the nodes with x < x_cut: the elements there have a zero gradient."""
+    prob.v[prob.coords[:, 0] < x_cut] = 0.0
+    return prob
 
 
 CASES = list(_cases().keys())
@@ -154,6 +178,7 @@ def test_patch_fd_gradient(P, oracle_mod, name):
     assert int(flag.item()) == 0
     g = g.cpu().numpy()
     tol = _fd_tol(prob, gref, cond, gabs, eps)
+    _note(f"[parity fd] {name}: worst |g - g_ref| / tol = {np.max(np.abs(g - gref) / tol):.3g}")
     bad = np.flatnonzero(np.abs(g - gref) > tol)
     assert bad.size == 0, (bad[:5], g[bad[:5]], gref[bad[:5]], tol[bad[:5]])
     # and the patch differences approximate the exact gradient to O(eps^2)
@@ -183,6 +208,7 @@ def test_fourth_order_patch_fd_gradient(P, oracle_mod, name):
     g, g2 = g.cpu().numpy(), g2.cpu().numpy()
     v = prob.vhat()
     tol = 32 * U * cond / (2 * eps) + 4 * U * (np.abs(v) + 2 * eps) / eps * gabs + 1e-12 * np.abs(gref)
+    _note(f"[parity fd4] {name}: worst |g - g_ref| / tol = {np.max(np.abs(g - gref) / tol):.3g}")
     bad = np.flatnonzero(np.abs(g - gref) > tol)
     assert bad.size == 0, (bad[:5], g[bad[:5]], gref[bad[:5]], tol[bad[:5]])
     if prob.kind != "plaplace":  # (the p-Laplacian differences are rounding-limited here)
@@ -408,3 +434,45 @@ def test_neohooke_log_term_over_wide_det_range(P, dim):
     _note(f"[log term dim {dim}] worst relative error {worst}")
     assert worst["fp64"] <= 1e-13
     assert worst["mixed"] <= 1e-5
+
+
+def test_binding_rejects_bad_buffers(P):
+    """The binding validates every buffer whose raw pointer it hands to the library (dtype,
+    device, contiguity, length) and raises ValueError before any kernel is launched."""
+    prob = S.plaplace_square(n=6, p=3.0, seed=1)
+    mesh, vhat = _setup(P, prob, P.P1E_FP64)
+    n = mesh.n_free_dofs
+    dev = vhat.device
+    bad_vhats = [vhat.float(), vhat[:-1], vhat.cpu(), torch.zeros(2 * n, dtype=torch.float64,
+                                                                  device=dev)[::2]]
+    for bv in bad_vhats:
+        for call in (lambda: mesh.energy(bv, "fp64"), lambda: mesh.grad_exact(bv, "fp64"),
+                     lambda: P.mesh_minimize(mesh, bv, history=3, max_iters=2, prec="fp64")):
+            with pytest.raises(ValueError):
+                call()
+    g_bad = [torch.empty(n, dtype=torch.float32, device=dev),
+             torch.empty(n - 1, dtype=torch.float64, device=dev),
+             torch.empty(n, dtype=torch.float64)]
+    for gb in g_bad:
+        with pytest.raises(ValueError):
+            mesh.grad_exact(vhat, "fp64", g=gb)
+        with pytest.raises(ValueError):
+            mesh.grad_gather("fp64", g=gb)
+    with pytest.raises(ValueError):
+        mesh.grad_exact(vhat, "fp64", out3=torch.empty(2, dtype=torch.float64, device=dev))
+    with pytest.raises(ValueError):
+        mesh.grad_exact(vhat, "fp64", flag=torch.empty(1, dtype=torch.int64, device=dev))
+    with pytest.raises(ValueError):
+        mesh.energy_forces(vhat, "fp64", out3=torch.empty(3, dtype=torch.float32, device=dev))
+    with pytest.raises(ValueError):
+        mesh.grad_scale(torch.empty(n, dtype=torch.float64, device=dev),
+                        torch.ones(2, dtype=torch.float64, device=dev))
+    ws = torch.empty(64, dtype=torch.uint8, device=dev)
+    with pytest.raises(ValueError):
+        P.minimize(mesh.handle, vhat[:-1], 3, 2, "fp64", ws)
+    with pytest.raises(ValueError):
+        P.minimize(mesh.handle, vhat, 3, 2, "fp64", ws.cpu())
+    # the mesh is untouched: a valid call still matches a fresh one bitwise
+    g1, o1, _ = mesh.grad_exact(vhat, "fp64")
+    g2, o2, _ = mesh.grad_exact(vhat, "fp64")
+    assert torch.equal(g1, g2) and torch.equal(o1, o2)
