@@ -27,7 +27,8 @@
  *     points only enqueue work on that stream and return without synchronising.
  *   - Memory: the library never allocates device memory. p1e_mesh_bind places the mesh and
  *     all scratch arrays in one caller-owned device buffer that the caller keeps alive until
- *     p1e_mesh_destroy (or a re-bind). Host arrays passed to p1e_mesh_create are copied.
+ *     p1e_mesh_destroy (or a re-bind). Host arrays passed to p1e_mesh_create are copied. The
+ *     one device array of its own is the fixed static scratch of p1e_grad_exact_static.
  *   - Threads: a mesh handle is not thread-safe, and two calls on the same mesh must not
  *     overlap on the device (they share its scratch arrays); distinct handles are independent.
  *   - Errors: entry points return P1E_OK (0) or a negative status; p1e_last_error() gives a
@@ -171,6 +172,20 @@ int p1e_energy(p1e_mesh *mesh, const double *vhat, int prec, double *out3, int32
  * in p1e_energy; flag receives the bad-element count. */
 int p1e_grad_exact(p1e_mesh *mesh, const double *vhat, int prec, double *g, double *out3,
                    int32_t *flag, void *stream);
+
+/* p1e_grad_exact with its scratch in a fixed array inside the library, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation). Same arguments, results and stream semantics as p1e_grad_exact (bitwise
+ * the same values); the call allocates nothing. Its scratch (tile partials [2][n_tiles] of
+ * 16 bytes, bad counts [n_tiles] of 4 bytes, halo partials [n_halo_slots][ncomp] of 8 bytes,
+ * each region rounded up to 256 bytes) lives in one static device array of
+ * P1E_STATIC_SCRATCH_BYTES per GPU, held from the library's first use of a device until the
+ * process ends; a mesh that needs more returns P1E_ENOMEM. Every call on one GPU shares that
+ * array: calls that overlap on the device (other streams, other threads) race and must be
+ * ordered by the caller. The mesh's own scratch region is not touched. */
+#define P1E_STATIC_SCRATCH_BYTES (64ull << 20)
+int p1e_grad_exact_static(p1e_mesh *mesh, const double *vhat, int prec, double *g, double *out3,
+                          int32_t *flag, void *stream);
 
 /* The exact gradient in two calls, for a differentiation hook whose backward pass runs later
  * than its forward pass:

@@ -33,6 +33,8 @@ P1E_FD = 4
 P1E_INPUT_ORDER = 1
 P1E_FULL_GEOMETRY = 4
 
+P1E_STATIC_SCRATCH_BYTES = 64 << 20
+
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EDEGEN", -3: "ENOMEM", -4: "EHIP", -5: "EDOMAIN",
                 -6: "EBUSY", -7: "ESTATE"}
 
@@ -123,6 +125,7 @@ def lib():
         "p1e_mesh_bind": ([vp, vp, u64, ctypes.c_int, vp], ctypes.c_int),
         "p1e_energy": ([vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "p1e_grad_exact": ([vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
+        "p1e_grad_exact_static": ([vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "p1e_grad_patch_fd": ([vp, vp, dbl, vp, vp, vp], ctypes.c_int),
         "p1e_grad_patch_fd4": ([vp, vp, dbl, vp, vp, vp], ctypes.c_int),
         "p1e_energy_forces": ([vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),

@@ -115,6 +115,14 @@ def grad_exact(handle, vhat, prec, g, out3, flag, stream=None):
                                  _dptr(out3), _dptr(flag), _stream_ptr(stream, flag.device)))
 
 
+def grad_exact_static(handle, vhat, prec, g, out3, flag, stream=None):
+    """p1e_grad_exact_static: p1e_grad_exact with the library's static scratch (allocates
+    nothing); out3 may be None."""
+    check(L.lib().p1e_grad_exact_static(ctypes.c_void_p(handle), _dptr(vhat), PREC[prec],
+                                        _dptr(g), _dptr(out3), _dptr(flag),
+                                        _stream_ptr(stream, flag.device)))
+
+
 def energy_forces(handle, vhat, prec, out3, flag, stream=None):
     """p1e_energy_forces: energy, and the exact gradient kept for grad_gather."""
     check(L.lib().p1e_energy_forces(ctypes.c_void_p(handle), _dptr(vhat), PREC[prec],

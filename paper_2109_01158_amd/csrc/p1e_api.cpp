@@ -656,6 +656,15 @@ int p1e_grad_exact(p1e_mesh *m, const double *vhat, int prec, double *g, double 
   return run_grad_exact(m, vhat, prec, g, out3, flag, (hipStream_t)stream);
 }
 
+int p1e_grad_exact_static(p1e_mesh *m, const double *vhat, int prec, double *g, double *out3,
+                          int32_t *flag, void *stream) {
+  if (prec != P1E_FP64 && prec != P1E_MIXED) return fail(P1E_EINVAL, "prec must be FP64 or MIXED");
+  int rc = check_call(m, vhat, prec);
+  if (rc) return rc;
+  if ((!g && m->nfd > 0) || !flag) return fail(P1E_EINVAL, "null output pointer");
+  return run_grad_exact_static(m, vhat, prec, g, out3, flag, (hipStream_t)stream);
+}
+
 int p1e_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
                       void *stream) {
   if (prec != P1E_FP64 && prec != P1E_MIXED) return fail(P1E_EINVAL, "prec must be FP64 or MIXED");

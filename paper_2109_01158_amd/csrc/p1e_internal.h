@@ -129,6 +129,10 @@ int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, i
                       hipStream_t s);
 int run_scale(p1e_mesh *m, const double *scale, double *g, hipStream_t s);
 int run_scale_inplace(p1e_mesh *m, const double *scale, double *g, hipStream_t s);
+// p1e_grad_exact with its scratch in the library's static per-device array
+int run_grad_exact_static(p1e_mesh *m, const double *vhat, int prec, double *g, double *out3,
+                          int32_t *flag, hipStream_t s);
+uint64_t static_scratch_need(const p1e_mesh *m);
 
 }  // namespace p1e
 

@@ -24,9 +24,16 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "p1e_device.h"
 #include "p1e_internal.h"
+
+// Scratch of p1e_grad_exact_static: the tile partials, bad-element counts and halo partial
+// sums of one call, in a fixed per-device array instead of the mesh's bound buffer. In host
+// code the name is only a stand-in for the symbol: kernels get the device address that
+// hipGetSymbolAddress returns for the current device (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[P1E_STATIC_SCRATCH_BYTES];
 
 namespace p1e {
 namespace {
@@ -234,47 +241,51 @@ int persistent_grid(F kernel, int nt, int64_t n) {
   return (int)((nb + X - 1) / X * X);
 }
 
+// Every launcher takes the device view Mv of the mesh: m->dev, or a copy whose scratch
+// pointers lead elsewhere (p1e_grad_exact_static).
 template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
-void launch_tile_kernel(p1e_mesh *m, const T *geo, const double *vhat, double *g, double eps,
-                        hipStream_t s) {
+void launch_tile_kernel(p1e_mesh *m, const TileMesh &Mv, const T *geo, const double *vhat,
+                        double *g, double eps, hipStream_t s) {
   constexpr int NT = tile_threads<T, MODE>();
   auto kern = k_tile<DIM, D, KIND, T, MODE, CLS>;
   const int nb = tile_persistent<T>() ? persistent_grid(kern, NT, m->ntiles) : (int)m->ntiles;
-  hipLaunchKernelGGL(kern, dim3(nb), dim3(NT), 0, s, m->dev, geo, vhat, g, params_of(m, eps));
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(NT), 0, s, Mv, geo, vhat, g, params_of(m, eps));
 }
 
 template <int DIM, int D, int KIND, typename T, int MODE>
-int launch_tile(p1e_mesh *m, const T *geo, const double *vhat, double *g, double eps,
-                hipStream_t s) {
+int launch_tile(p1e_mesh *m, const TileMesh &Mv, const T *geo, const double *vhat, double *g,
+                double eps, hipStream_t s) {
   if (m->ntiles == 0) return P1E_OK;
   const char *name = MODE == MODE_ENERGY ? "k_tile_energy"
                      : MODE == MODE_FORCE ? "k_tile_force"
                      : MODE == MODE_FD    ? "k_tile_fd"
                                           : "k_tile_fd4";
   prof_begin(name, s);
-  if (m->dev.geo_cls != nullptr)
-    launch_tile_kernel<DIM, D, KIND, T, MODE, true>(m, geo, vhat, g, eps, s);
+  if (Mv.geo_cls != nullptr)
+    launch_tile_kernel<DIM, D, KIND, T, MODE, true>(m, Mv, geo, vhat, g, eps, s);
   else
-    launch_tile_kernel<DIM, D, KIND, T, MODE, false>(m, geo, vhat, g, eps, s);
+    launch_tile_kernel<DIM, D, KIND, T, MODE, false>(m, Mv, geo, vhat, g, eps, s);
   prof_end(s);
   return check_launch(name);
 }
 
 // halo rows and finalize (gradient modes)
 template <int D>
-int launch_halo(p1e_mesh *m, double *g, double *out3, int32_t *flag, hipStream_t s) {
+int launch_halo(p1e_mesh *m, const TileMesh &Mv, double *g, double *out3, int32_t *flag,
+                hipStream_t s) {
   prof_begin("k_halo", s);
-  hipLaunchKernelGGL((k_halo<D>), dim3(1 + nblocks(m->nhalo)), dim3(kBlock), 0, s, m->dev, g,
+  hipLaunchKernelGGL((k_halo<D>), dim3(1 + nblocks(m->nhalo)), dim3(kBlock), 0, s, Mv, g,
                      m->dirichlet_bv, out3, flag);
   prof_end(s);
   return check_launch("k_halo");
 }
 
 // finalize alone (energy mode)
-int launch_finalize(p1e_mesh *m, double *out3, int32_t *flag, hipStream_t s) {
+int launch_finalize(p1e_mesh *m, const TileMesh &Mv, double *out3, int32_t *flag,
+                    hipStream_t s) {
   prof_begin("k_finalize", s);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFin), 0, s, (int)m->ntiles, m->dev.part,
-                     m->dev.badp, m->dirichlet_bv, out3, flag);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFin), 0, s, (int)m->ntiles, Mv.part, Mv.badp,
+                     m->dirichlet_bv, out3, flag);
   prof_end(s);
   return check_launch("k_finalize");
 }
@@ -282,27 +293,28 @@ int launch_finalize(p1e_mesh *m, double *out3, int32_t *flag, hipStream_t s) {
 // The pipeline for one (DIM, D, KIND, T): tiles (mode), then the finalize, together with
 // the halo rows when a gradient is asked for.
 template <int DIM, int D, int KIND, typename T, int MODE>
-int pipeline(p1e_mesh *m, const double *vhat, const T *geo, double eps, double *g,
-             double *out3, int32_t *flag, hipStream_t s) {
-  int rc = launch_tile<DIM, D, KIND, T, MODE>(m, geo, vhat, g, eps, s);
+int pipeline(p1e_mesh *m, const TileMesh &Mv, const double *vhat, const T *geo, double eps,
+             double *g, double *out3, int32_t *flag, hipStream_t s) {
+  int rc = launch_tile<DIM, D, KIND, T, MODE>(m, Mv, geo, vhat, g, eps, s);
   if (rc) return rc;
-  if (MODE != MODE_ENERGY) return launch_halo<D>(m, g, out3, flag, s);
-  return launch_finalize(m, out3, flag, s);
+  if (MODE != MODE_ENERGY) return launch_halo<D>(m, Mv, g, out3, flag, s);
+  return launch_finalize(m, Mv, out3, flag, s);
 }
 
 template <typename T, int MODE>
 int dispatch(p1e_mesh *m, const double *vhat, const T *geo, double eps, double *g,
-             double *out3, int32_t *flag, hipStream_t s) {
+             double *out3, int32_t *flag, hipStream_t s, const TileMesh *view = nullptr) {
+  const TileMesh &V = view ? *view : m->dev;
   if (m->kind == P1E_NEOHOOKE) {
-    if (m->dim == 3) return pipeline<3, 3, P1E_NEOHOOKE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
-    return pipeline<2, 2, P1E_NEOHOOKE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
+    if (m->dim == 3) return pipeline<3, 3, P1E_NEOHOOKE, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
+    return pipeline<2, 2, P1E_NEOHOOKE, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
   }
   if (m->kind == P1E_SVK) {
-    if (m->dim == 3) return pipeline<3, 3, P1E_SVK, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
-    return pipeline<2, 2, P1E_SVK, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
+    if (m->dim == 3) return pipeline<3, 3, P1E_SVK, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
+    return pipeline<2, 2, P1E_SVK, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
   }
-  if (m->dim == 3) return pipeline<3, 1, P1E_PLAPLACE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
-  return pipeline<2, 1, P1E_PLAPLACE, T, MODE>(m, vhat, geo, eps, g, out3, flag, s);
+  if (m->dim == 3) return pipeline<3, 1, P1E_PLAPLACE, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
+  return pipeline<2, 1, P1E_PLAPLACE, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
 }
 
 }  // namespace
@@ -331,6 +343,75 @@ int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, int order, double *
 int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
                       hipStream_t s) {
   return run_grad_exact(m, vhat, prec, m->dev.gw, out3, flag, s);
+}
+
+// Device address of `scratch` on the current device, looked up once per device (each GPU
+// holds its own copy of the array at its own address); nullptr with the HIP status in *err
+// if the lookup fails.
+static void *static_scratch(hipError_t *err) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *err = e != hipSuccess ? e : hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (addr[dev] == nullptr) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    addr[dev] = p;
+  }
+  *err = hipSuccess;
+  return addr[dev];
+}
+
+// Byte offsets of the three scratch arrays of a call in the static array: tile partials
+// [2][ntiles] double2, bad counts [ntiles] int32, halo partials [slots][d] double, each
+// 256-byte aligned. Returns the bytes needed.
+static uint64_t static_layout(const p1e_mesh *m, uint64_t &part, uint64_t &badp, uint64_t &hpart) {
+  auto up = [](uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
+  const uint64_t nt1 = (uint64_t)std::max<int64_t>(m->ntiles, 1);
+  part = 0;
+  badp = up(32 * nt1);
+  hpart = badp + up(4 * nt1);
+  return hpart + 8ull * (uint64_t)m->nslots * (uint64_t)m->d;
+}
+
+uint64_t static_scratch_need(const p1e_mesh *m) {
+  uint64_t a, b, c;
+  return static_layout(m, a, b, c);
+}
+
+// p1e_grad_exact with the call's scratch in the static array. Every tile writes its
+// partials and bad count and every halo slot is written by the one tile it belongs to before
+// k_halo reads it, so nothing needs clearing first; calls that overlap on one device race on
+// the array.
+int run_grad_exact_static(p1e_mesh *m, const double *vhat, int prec, double *g, double *out3,
+                          int32_t *flag, hipStream_t s) {
+  uint64_t op, ob, oh;
+  const uint64_t need = static_layout(m, op, ob, oh);
+  if (need > (uint64_t)P1E_STATIC_SCRATCH_BYTES)
+    return fail(P1E_ENOMEM, "mesh needs " + std::to_string(need) +
+                                " bytes of scratch, more than the static array's " +
+                                std::to_string((uint64_t)P1E_STATIC_SCRATCH_BYTES));
+  hipError_t e;
+  char *base = (char *)static_scratch(&e);
+  if (base == nullptr)
+    return fail(P1E_EHIP, std::string("static scratch lookup: ") + hipGetErrorString(e));
+  TileMesh V = m->dev;
+  V.part = (double2 *)(base + op);
+  V.badp = (int32_t *)(base + ob);
+  V.hpart = (double *)(base + oh);
+  if (prec == P1E_MIXED)
+    return dispatch<float, MODE_FORCE>(m, vhat, m->dev.geo32, 0.0, g, out3, flag, s, &V);
+  return dispatch<double, MODE_FORCE>(m, vhat, m->dev.geo64, 0.0, g, out3, flag, s, &V);
 }
 
 int run_scale_inplace(p1e_mesh *m, const double *scale, double *g, hipStream_t s) {
