@@ -4,10 +4,23 @@ One step = one energy-and-gradient evaluation through the autograd hook
 (``p1_energy(vhat).backward()``: element tiles with energy, forces and in-tile patch sums,
 halo rows, compensated finalize; the backward scales the forward's gradient buffer in place,
 which writes nothing for dJ/dJ = 1) on the 460x46x46-cube Kuhn box (5,840,160 tets), mixed
-precision, inputs resident in HBM. Prints ONE JSON line. Extra fields report the FP64 path, the patch central-difference
-gradient on the same mesh, the serving benchmark (256 minimization requests, Poisson arrivals,
-continuous batching vs one-at-a-time FP64 solves: req/s, p50/p99 latency), the dominant kernel against the HBM roofline (HIP events around
-each kernel over a second pass of the same K steps) and the FP64 oracle timed on the host CPU.
+precision, inputs resident in HBM. Prints ONE JSON line with:
+
+* value / ms_per_step: K steps bracketed by device synchronisations (wall clock), and the
+  median step from HIP events around each step of a second pass;
+* roofline: the dominant kernel against the HBM roofline (HIP events around each kernel over
+  a third pass), with the counter-measured traffic and VALU-issue fraction when a profile of
+  the current kernel sources is committed;
+* oracle_rel_err: the FP64 oracle's error of every timed result (mixed and FP64 J + exact
+  gradient on the whole mesh; patch central differences on sampled DOFs);
+* extras: FP64 J + grad J, the patch differences (second and fourth order) on the same mesh,
+  and the mixed J + grad J on the 930x93x93-cube box (48,261,420 tets, a working set far
+  above the 256 MB last-level cache);
+* cpu_baseline: the oracle (plain C element loops) timed on the host before the GPU is
+  touched, on all host cores (one process per contiguous element range) and on one core,
+  median of 5;
+* serve: the serving benchmark (256 minimization requests, Poisson arrivals, continuous
+  batching vs one-at-a-time FP64 solves: req/s, p50/p99 latency, with and without mesh setup).
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline] [--no-serve]
 """
@@ -22,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+MAX_CPU_WORKERS = 16   # host share of one GPU
 
 
 def _args():
@@ -32,10 +46,13 @@ def _args():
     ap.add_argument("--config", default="nh3d_box_6M")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip FP64 and FD extra timings")
+    ap.add_argument("--no-extras", action="store_true", help="skip FP64, FD and 48M timings")
+    ap.add_argument("--no-large", action="store_true", help="skip the 48M-tet timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving benchmark")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-iters", type=int, default=200)
+    ap.add_argument("--fd-sample", type=int, default=3000,
+                    help="DOFs at which the oracle checks the patch differences")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run plain device-to-device copies of this many MiB (a reference "
                          "for hardware byte counters)")
@@ -89,22 +106,184 @@ def profile_record(config, prec):
     return t
 
 
-def cpu_baseline(prob, target_s=12.0):
-    """The FP64 oracle (single-threaded C loops) on the same mesh: energy + exact gradient,
-    repeated until about target_s seconds of CPU time."""
+# ------------------------------------------------------------------ host CPU and the oracle
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "available": avail}
+
+
+def _oracle_range_worker(prob, lo, hi, rounds, barrier, q):
+    """One process of the all-core timing: the oracle on elements [lo, hi) of the mesh (its
+    geometry set up before the first round), energy + exact gradient once per round; each
+    round starts at a barrier shared by all workers."""
+    from dataclasses import replace
     import oracle
-    oracle.build(force=False)
-    O = oracle.Oracle(prob)
-    reps, t = 0, 0.0
-    while t < target_s and reps < 20:
+    O = oracle.Oracle(replace(prob, conn=prob.conn[lo:hi]))
+    O.energy(prob.v)
+    O.grad_exact(prob.v)
+    for r in range(rounds):
+        barrier.wait()
         t0 = time.perf_counter()
         O.energy(prob.v)
         O.grad_exact(prob.v)
-        t += time.perf_counter() - t0
-        reps += 1
-    return {"value": prob.ne * reps / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} x (energy + exact gradient) over the full {prob.ne}-element mesh, "
-                      f"{t:.1f} s, single thread"}
+        q.put((r, time.perf_counter() - t0))
+
+
+def cpu_leg(prob, fd_sample, rounds=5, seed=7):
+    """Oracle references for the timed GPU results, and the oracle's own speed on the host.
+    Runs before the GPU is initialised (the all-core timing forks worker processes)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    O = oracle.Oracle(prob)
+    ref = O.energy(prob.v)
+    gref = O.grad_exact(prob.v)
+    one = []
+    for _ in range(rounds):
+        t0 = time.perf_counter()
+        O.energy(prob.v)
+        O.grad_exact(prob.v)
+        one.append(time.perf_counter() - t0)
+    rng = np.random.default_rng(seed)
+    nfd = prob.n_free_dofs
+    sample = np.sort(rng.choice(nfd, size=min(fd_sample, nfd), replace=False))
+    fd = O.grad_patch_fd(prob.v, prob.eps, sample=sample, with_cond=True)
+    fd4 = O.grad_patch_fd(prob.v, prob.eps, sample=sample, with_cond=True, order=4)
+    del O
+    # all cores: one process per contiguous element range
+    cpu = host_cpu()
+    P = max(1, min(MAX_CPU_WORKERS, cpu["available"] or 1))
+    ctx = mp.get_context("fork")
+    barrier = ctx.Barrier(P)
+    q = ctx.Queue()
+    cuts = np.linspace(0, prob.ne, P + 1).astype(np.int64)
+    procs = [ctx.Process(target=_oracle_range_worker,
+                         args=(prob, int(cuts[i]), int(cuts[i + 1]), rounds, barrier, q))
+             for i in range(P)]
+    for p in procs:
+        p.start()
+    per_round = [[] for _ in range(rounds)]
+    for _ in range(P * rounds):
+        r, dt = q.get(timeout=600)
+        per_round[r].append(dt)
+    for p in procs:
+        p.join()
+    wall = [max(x) for x in per_round]
+    t_all, t_one = float(np.median(wall)), float(np.median(one))
+    base = {
+        "value": prob.ne / t_all, "unit": "elements/s", "cores": P, "kind": "oracle",
+        "sample": f"energy + exact gradient over the full {prob.ne}-element mesh, FP64 C element "
+                  f"loops, {P} processes on contiguous element ranges, median of {rounds} rounds "
+                  f"({t_all:.3f} s per round)",
+        "single_thread": {"value": prob.ne / t_one, "cores": 1,
+                          "sample": f"the same on one core, median of {rounds} ({t_one:.3f} s)"},
+        "host_cpu": cpu,
+    }
+    refs = {"J": ref["J"], "g": gref, "sample": sample, "fd": fd, "fd4": fd4}
+    return base, refs
+
+
+def _rel(a, b):
+    import numpy as np
+    a, b = np.atleast_1d(a), np.atleast_1d(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def fd_errors(g, ref, v_free, eps, order):
+    """Relative 2-norm error over the sample, and the largest per-DOF ratio to the parity
+    bound of the tests: 32u cond/(2 eps) + 4u(|v| + h)/eps gabs + 1e-12|g_ref| with the
+    oracle's rounding scales cond and gabs of the scheme, h its largest step."""
+    import numpy as np
+    u = 2.0 ** -53
+    gref, cond, gabs = ref
+    step = eps if order == 2 else 2 * eps
+    tol = (32 * u * cond / (2 * eps) + 4 * u * (np.abs(v_free) + step) / eps * gabs
+           + 1e-12 * np.abs(gref))
+    return {"rel_err_2norm": _rel(g, gref),
+            "max_err_over_bound": float(np.max(np.abs(g - gref) / tol))}
+
+
+# ------------------------------------------------------------------ GPU timing helpers
+def time_steps(fn, steps):
+    """Wall clock of `steps` calls bracketed by synchronisations, ms per call."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def median_step_ms(fn, steps):
+    """Median of per-call HIP event times on the current stream (no synchronisation between
+    calls)."""
+    import numpy as np
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def large_timing(P, steps, warmup):
+    """Mixed J + grad J through the autograd hook on the 48M-tet box (930x93x93 cubes)."""
+    import torch
+    import p1e_synth as S
+    t0 = time.perf_counter()
+    prob = S.config_problem("nh3d_box_48M")
+    mesh = P.Mesh.from_problem(prob, modes=P.P1E_MIXED)
+    setup = time.perf_counter() - t0
+    info = mesh.info
+    vhat = torch.tensor(prob.vhat(), device="cuda").requires_grad_(True)
+    seed = torch.ones((), dtype=torch.float64, device="cuda")
+
+    def step():
+        vhat.grad = None
+        J = P.p1_energy(vhat, mesh, "mixed")
+        torch.autograd.backward(J, seed)
+
+    for _ in range(warmup):
+        step()
+    ms = time_steps(step, steps)
+    med = median_step_ms(step, steps)
+    P.prof_reset()
+    P.prof_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    P.prof_enable(False)
+    kern = {k: 1e3 * t / c for k, (c, t) in P.prof_collect().items()}
+    ab = algorithmic_bytes(info, "mixed", info["geometry_classes"] > 0)
+    out = {"workload": "nh3d_box_48M: 930x93x93 cubes x 6 Kuhn tets, mixed J + exact grad J "
+                       "through the autograd hook",
+           "ne": info["ne"], "elements_per_s": info["ne"] / (ms * 1e-3), "ms": ms,
+           "ms_median": med, "kernels_avg_us": kern,
+           "k_tile_alg_GBs": ab["k_tile_force"] / (kern["k_tile_force"] * 1e-6) / 1e9,
+           "bound_buffer_bytes": mesh.nbytes, "setup_s": setup}
+    del vhat, mesh
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -116,13 +295,17 @@ def main():
                           "n_gpus": a.gpus}))
         sys.exit(2)
 
-    import torch
     import p1e_synth as S
+    prob = S.config_problem(a.config)
+    # the oracle leg first: it forks worker processes, which must not inherit a GPU context
+    base, refs = (None, None) if a.no_cpu_baseline else cpu_leg(prob, a.fd_sample)
+
+    import numpy as np
+    import torch
     import paper_2109_01158_amd as P
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    prob = S.config_problem(a.config)
     modes = P.P1E_MIXED if a.prec == "mixed" else P.P1E_FP64
     if not a.no_extras:
         modes |= P.P1E_FP64 | P.P1E_FD
@@ -133,35 +316,28 @@ def main():
     vhat0 = torch.tensor(prob.vhat(), device=dev)
     vhat = vhat0.clone().requires_grad_(True)
     seed = torch.ones((), dtype=torch.float64, device=dev)  # dJ/dJ, allocated once
+    res = {}
 
     def step():
         vhat.grad = None
         J = P.p1_energy(vhat, mesh, a.prec)
         torch.autograd.backward(J, seed)
-        return J
+        res["J"] = J
 
     for _ in range(a.warmup):
         step()
-    torch.cuda.synchronize()
     # timed region: K steps bracketed by device synchronisations
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        J = step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    ms = time_steps(step, a.steps)
     value = info["ne"] / (ms * 1e-3)
-    Jv = float(J.item())
-    # the same K steps again with every library kernel bracketed by HIP events on its launch
-    # stream: per-kernel durations for the roofline (the events themselves cost a few us per
-    # kernel, visible as ms_per_step_with_kernel_events)
+    J_timed = float(res["J"].item())
+    g_timed = vhat.grad.detach().cpu().numpy()
+    # the same K steps with HIP events around each step: the median step
+    ms_median = median_step_ms(step, a.steps)
+    # and with every library kernel bracketed by HIP events on its launch stream: per-kernel
+    # durations for the roofline (the events themselves cost a few us per kernel)
     P.prof_reset()
     P.prof_enable(True)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_events = (time.perf_counter() - t2) * 1e3 / a.steps
+    ms_events = time_steps(step, a.steps)
     P.prof_enable(False)
     kern = P.prof_collect()
 
@@ -175,6 +351,15 @@ def main():
             s["alg_GBs"] = abytes[k] / (s["avg_us"] * 1e-6) / 1e9
     step_bytes = sum(abytes.values())
     prof = profile_record(a.config, a.prec)
+    hbm_frac = achieved / HBM_PEAK_GBS if achieved else None
+    issue_frac = (prof or {}).get("valu_issue", {}).get(dom, {}).get("frac")
+    limiter = None
+    if issue_frac is not None and hbm_frac is not None:
+        limiter = "valu_issue" if issue_frac > hbm_frac else "hbm"
+
+    errs = {}
+    if refs is not None:
+        errs[f"{a.prec}_jgrad"] = {"J": _rel(J_timed, refs["J"]), "grad": _rel(g_timed, refs["g"])}
 
     extras = {}
     if not a.no_extras:
@@ -182,36 +367,49 @@ def main():
         g = torch.empty_like(vhat0)
         out3 = torch.empty(3, dtype=torch.float64, device=dev)
         flag = torch.empty(1, dtype=torch.int32, device=dev)
+        last = {}
+
+        def fd2():
+            last["fd"] = mesh.grad_patch_fd(vhat0, prob.eps)
+
+        def fd4():
+            last["fd4"] = mesh.grad_patch_fd4(vhat0, prob.eps)
+
         for name, fn in (("fp64_jgrad", lambda: mesh.grad_exact(vhat0, "fp64", g=g, out3=out3,
                                                                   flag=flag)),
-                         ("patch_fd_fp64", lambda: mesh.grad_patch_fd(vhat0, prob.eps)),
-                         ("patch_fd4_fp64", lambda: mesh.grad_patch_fd4(vhat0, prob.eps))):
+                         ("patch_fd_fp64", fd2), ("patch_fd4_fp64", fd4)):
             for _ in range(2):
                 fn()
-            torch.cuda.synchronize()
             n = max(3, a.steps // 2)
-            t0 = time.perf_counter()
-            for _ in range(n):
-                fn()
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / n
-            extras[name] = {"elements_per_s": info["ne"] / dt, "ms": dt * 1e3}
-
+            dt = time_steps(fn, n)
+            extras[name] = {"elements_per_s": info["ne"] / (dt * 1e-3), "ms": dt,
+                            "ms_median": median_step_ms(fn, n)}
+        if refs is not None:
+            errs["fp64_jgrad"] = {"J": _rel(out3[0].item(), refs["J"]),
+                                  "grad": _rel(g.cpu().numpy(), refs["g"])}
+            v_free = prob.vhat()[refs["sample"]]
+            for key, name, order in (("fd", "patch_fd_fp64", 2), ("fd4", "patch_fd4_fp64", 4)):
+                gs = last[key][0].cpu().numpy()[refs["sample"]]
+                r = refs[key]
+                errs[name] = dict(fd_errors(gs, r, v_free, prob.eps, order),
+                                  sampled_dofs=int(refs["sample"].size))
     if a.copy_calibration > 0:
         src = torch.empty(a.copy_calibration << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
 
     out = {
-        "metric": "elements/s for J+\u2207J (3D Neo-Hookean, 6M tets); serve req/s + p50/p99",
+        "metric": "elements/s for J+∇J (3D Neo-Hookean, 6M tets); serve req/s + p50/p99",
         "value": value,
         "unit": "elements/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": ms,
+        "ms_per_step_median": ms_median,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -225,26 +423,29 @@ def main():
             "patch_incidences": info["nnz"], "parallelism": "single GPU",
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "unit": "GB/s", "frac": hbm_frac,
                      "traffic": (prof or {}).get("traffic_bytes_per_launch", {}).get(dom),
                      "alg_bytes_per_launch": dom_bytes,
                      "alg_bytes_per_element": dom_bytes / info["ne"] if dom_bytes else None,
-                     "valu_issue_frac_profiled":
-                         (prof or {}).get("valu_issue", {}).get(dom, {}).get("frac")},
+                     "valu_issue_frac_profiled": issue_frac,
+                     "limiter": limiter},
         "ms_per_step_with_kernel_events": ms_events,
         "step_alg_bytes_per_element": step_bytes / info["ne"],
         "step_alg_GBs": step_bytes / (ms * 1e-3) / 1e9,
         "kernels": kstats,
-        "J": Jv,
+        "J": J_timed,
+        "oracle_rel_err": errs,
         "setup_s": setup_s,
         "extras": extras,
     }
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob)
+    if base is not None:
+        out["cpu_baseline"] = base
+    del mesh, vhat, vhat0
+    torch.cuda.empty_cache()
+    if not a.no_extras and not a.no_large:
+        extras["nh3d_box_48M_mixed_jgrad"] = large_timing(P, a.steps, a.warmup)
     if not a.no_serve:
         from paper_2109_01158_amd import serving
-        del mesh, vhat, vhat0
-        torch.cuda.empty_cache()
         out["serve"] = serving.benchmark(
             n_requests=a.serve_requests, iters=a.serve_iters,
             log=lambda m: print(m, file=sys.stderr, flush=True))

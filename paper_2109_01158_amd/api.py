@@ -7,6 +7,7 @@ computation runs in libp1e's HIP kernels; torch only provides device memory and 
 """
 
 import ctypes
+import time
 
 import numpy as np
 import torch
@@ -187,8 +188,10 @@ class Mesh:
     def __init__(self, dim, kind, conn, coords, dirichlet=None, dirichlet_values=None,
                  load=None, p=2.0, C1=0.0, D1=0.0, modes=P1E_FP64 | P1E_MIXED,
                  device="cuda", stream=None, flags=0):
+        t0 = time.perf_counter()
         self.handle = mesh_create(dim, kind, conn, coords, dirichlet, dirichlet_values, load,
                                   p, C1, D1, flags)
+        self.create_s = time.perf_counter() - t0  # host setup time (p1e_mesh_create)
         self.info = mesh_get_info(self.handle)
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
@@ -199,8 +202,10 @@ class Mesh:
         self._buf = torch.empty(self.nbytes + align, dtype=torch.uint8, device=self.device)
         off = (-self._buf.data_ptr()) % align
         self.buf = self._buf[off: off + self.nbytes]
+        t0 = time.perf_counter()
         with torch.cuda.device(self.device):
             mesh_bind(self.handle, self.buf, self.nbytes, modes, stream)
+        self.bind_s = time.perf_counter() - t0  # upload (p1e_mesh_bind synchronises)
         self.n_free_dofs = int(self.info["n_free_dofs"])
         # bumped by every call that rewrites the kept gradient (energy_forces, minimize); lets
         # a differentiation hook know whether the gradient of its forward pass is still there
