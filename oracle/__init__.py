@@ -26,8 +26,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "p1e_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-PLAPLACE, NEOHOOKE, SVK = 1, 2, 3
-_KINDS = {"plaplace": PLAPLACE, "neohooke": NEOHOOKE, "svk": SVK}
+PLAPLACE, NEOHOOKE, SVK, GL = 1, 2, 3, 4
+_KINDS = {"plaplace": PLAPLACE, "neohooke": NEOHOOKE, "svk": SVK, "gl": GL}
 
 
 def build(force=True):
@@ -121,6 +121,10 @@ class Oracle:
                 prob.E, prob.nu)
             self.C1 = c1 if C1 is None else C1
             self.D1 = d1 if D1 is None else D1
+            self.p = 0.0
+        elif self.kind == "gl":  # Ginzburg-Landau: the coefficients are the problem's own
+            self.C1 = float(prob.C1) if C1 is None else C1
+            self.D1 = float(prob.D1) if D1 is None else D1
             self.p = 0.0
         else:
             self.C1 = self.D1 = 0.0

@@ -16,7 +16,13 @@
  *                eq. (pLaplacian): W = |grad v|^p / p;
  *                St. Venant-Kirchhoff, the extension Section 2 names after eq. (neoHook)
  *                (the paper gives no formula; the textbook one): W = C1 |E|^2 + D1 (tr E)^2
- *                with the Green-Lagrange strain E = (F^T F - I) / 2, C1 = mu, D1 = lambda / 2.
+ *                with the Green-Lagrange strain E = (F^T F - I) / 2, C1 = mu, D1 = lambda / 2;
+ *                Ginzburg-Landau, the scalar example Section 7 names for adding first-gradient
+ *                problems (the textbook energy eps/2 |grad u|^2 + (u^2 - 1)^2 / 4, with C1 and
+ *                D1 as its two coefficients): |T| C1 |grad u|^2 + D1 int_T (u^2 - 1)^2 dx, the
+ *                integral of the P1 field's quartic taken exactly by expanding the power of
+ *                u = sum_l u_l lambda_l over vertex tuples and integrating each barycentric
+ *                monomial by int_T lambda^a = |T| dim! a! / (|a| + dim)!.
  *   J_grad       eq. (Denergy): sum over elements of |T| W(F_T), element order,
  *                Neumaier-compensated.
  *   b = M f      Section 3.2, eqs. (mass2D), (linearTerm2): consistent P1 mass matrix with
@@ -39,7 +45,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_PLAPLACE = 1, ORC_NEOHOOKE = 2, ORC_SVK = 3 };
+enum { ORC_PLAPLACE = 1, ORC_NEOHOOKE = 2, ORC_SVK = 3, ORC_GL = 4 };
 
 typedef struct {
   int32_t dim;    /* 2 or 3 */
@@ -132,6 +138,78 @@ int64_t orc_geometry(const orc_problem *P, double *vol, double *dphi) {
   return ndegen;
 }
 
+/* ---------------------------------------------------------------- P1 polynomial integrals */
+static double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+/* int_T lambda_0^a[0] ... lambda_dim^a[dim] dx = |T| dim! a[0]! ... a[dim]! / (|a| + dim)! */
+static double bary_moment(int dim, double vol, const int *a) {
+  double num = factorial(dim);
+  int tot = 0;
+  for (int l = 0; l <= dim; ++l) {
+    num *= factorial(a[l]);
+    tot += a[l];
+  }
+  return vol * num / factorial(tot + dim);
+}
+
+/* int_T u^k lambda_m dx (m < 0: without the factor lambda_m) for u = sum_l u_l lambda_l, k <= 4:
+ * the power expanded over all ordered k-tuples of vertices, each product of barycentric
+ * coordinates integrated by bary_moment */
+static double int_power(int dim, double vol, const double *u, int k, int m) {
+  const int nv = dim + 1;
+  int ntup = 1;
+  for (int i = 0; i < k; ++i) ntup *= nv;
+  double sum = 0.0;
+  for (int t = 0; t < ntup; ++t) {
+    int a[4] = {0, 0, 0, 0};
+    double prod = 1.0;
+    int r = t;
+    for (int i = 0; i < k; ++i) {
+      const int l = r % nv;
+      r /= nv;
+      a[l] += 1;
+      prod *= u[l];
+    }
+    if (m >= 0) a[m] += 1;
+    sum += prod * bary_moment(dim, vol, a);
+  }
+  return sum;
+}
+
+/* (Ginzburg-Landau) nodal values of element T */
+static void element_values(const orc_problem *P, const double *v, const int32_t *T, double *u) {
+  for (int l = 0; l <= P->dim; ++l) u[l] = v[T[l]];
+}
+
+/* int_T (u^2 - 1)^2 dx = int u^4 - 2 int u^2 + |T| */
+static double gl_potential(int dim, double vol, const double *u) {
+  return int_power(dim, vol, u, 4, -1) - 2.0 * int_power(dim, vol, u, 2, -1) + vol;
+}
+
+/* d/du_m int_T (u^2 - 1)^2 dx = int_T 4 u (u^2 - 1) lambda_m dx */
+static double gl_potential_du(int dim, double vol, const double *u, int m) {
+  return 4.0 * int_power(dim, vol, u, 3, m) - 4.0 * int_power(dim, vol, u, 1, m);
+}
+
+/* |T| W of element e with nodal field v: |T| W(F_T) for the gradient densities, plus
+ * D1 int_T (u^2 - 1)^2 for Ginzburg-Landau (where W(F_T) = C1 |grad u|^2) */
+static double density(const orc_problem *P, double F[3][3], int *bad);
+static double element_energy(const orc_problem *P, const double *v, int64_t e, double vol,
+                             double F[3][3], int *bad) {
+  double E = vol * density(P, F, bad);
+  if (P->kind == ORC_GL && !*bad) {
+    double u[4];
+    element_values(P, v, P->conn + e * (P->dim + 1), u);
+    E += P->D1 * gl_potential(P->dim, vol, u);
+    if (!isfinite(E)) { *bad = 1; return INFINITY; }
+  }
+  return E;
+}
+
 /* ---------------------------------------------------------------- F_T and densities */
 /* F[j][m] = sum_l v[I(T,l)][j] * dphi_l[m]  (eq. Dv) */
 static void element_F(const orc_problem *P, const double *v, const int32_t *T,
@@ -174,6 +252,10 @@ static double density(const orc_problem *P, double F[3][3], int *bad) {
     double det = det_mat(dim, F);
     if (!(det > 0.0)) { *bad = 1; return INFINITY; }
     W = P->C1 * (I1 - dim - 2.0 * log(det)) + P->D1 * (det - 1.0) * (det - 1.0);
+  } else if (P->kind == ORC_GL) {
+    double s = 0.0;
+    for (int m = 0; m < dim; ++m) s += F[0][m] * F[0][m];
+    W = P->C1 * s; /* the gradient part; the potential is added per element */
   } else {
     double s = 0.0;
     for (int m = 0; m < dim; ++m) s += F[0][m] * F[0][m];
@@ -208,6 +290,8 @@ static void density_dF(const orc_problem *P, double F[3][3], double D[3][3], int
       for (int m = 0; m < dim; ++m)
         D[j][m] = P->C1 * (2.0 * F[j][m] - (2.0 / det) * cof[j][m])
                 + 2.0 * P->D1 * (det - 1.0) * cof[j][m];
+  } else if (P->kind == ORC_GL) {
+    for (int m = 0; m < dim; ++m) D[0][m] = 2.0 * P->C1 * F[0][m];
   } else {
     double s = 0.0;
     for (int m = 0; m < dim; ++m) s += F[0][m] * F[0][m];
@@ -232,15 +316,15 @@ int64_t orc_energy(const orc_problem *P, const double *v, const double *vol, con
     double F[3][3];
     element_F(P, v, P->conn + e * k, dphi + e * k * dim, F);
     int bad = 0;
-    double W = density(P, F, &bad);
+    double E = element_energy(P, v, e, vol[e], F, &bad);
     if (bad) { ++nbad; continue; }
-    acc_add(&acc, vol[e] * W);
+    acc_add(&acc, E);
   }
   *jgrad = nbad ? INFINITY : acc_result(&acc);
   return nbad;
 }
 
-/* Per-element densities W(F_T) (bad elements get +Inf). */
+/* Per-element densities W(F_T) (bad elements get +Inf; Ginzburg-Landau: the gradient part). */
 void orc_densities(const orc_problem *P, const double *v, const double *dphi, double *W_out) {
   const int dim = P->dim, k = dim + 1;
   for (int64_t e = 0; e < P->ne; ++e) {
@@ -296,6 +380,11 @@ int64_t orc_grad_exact(const orc_problem *P, const double *v, const double *vol,
         for (int m = 0; m < dim; ++m) s += D[j][m] * dp[l * dim + m];
         g[(int64_t)T[l] * d + j] += vol[e] * s;
       }
+    if (P->kind == ORC_GL) {
+      double u[4];
+      element_values(P, v, T, u);
+      for (int l = 0; l < k; ++l) g[T[l]] += P->D1 * gl_potential_du(dim, vol[e], u, l);
+    }
   }
   return nbad;
 }
@@ -337,6 +426,7 @@ static double density_abs(const orc_problem *P, double F[3][3], double W) {
       }
     return fabs(W) + sc;
   }
+  if (P->kind == ORC_GL) return fabs(W); /* the potential's scale is added by the caller */
   if (P->kind != ORC_NEOHOOKE) return fabs(W);
   const int dim = P->dim;
   double I1 = 0.0;
@@ -344,6 +434,21 @@ static double density_abs(const orc_problem *P, double F[3][3], double W) {
     for (int m = 0; m < dim; ++m) I1 += F[j][m] * F[j][m];
   double det = det_mat(dim, F);
   return P->C1 * (I1 + dim + 2.0 * fabs(log(det))) + P->D1 * (det - 1.0) * (det - 1.0);
+}
+
+/* |T| |W|_abs of element e, plus (Ginzburg-Landau) the potential's scale
+ * D1 (int u^4 + 2 int u^2 + |T|) */
+static double element_energy_abs(const orc_problem *P, const double *v, int64_t e, double vol,
+                                 double F[3][3]) {
+  int bad = 0;
+  const double W = density(P, F, &bad);
+  double A = vol * density_abs(P, F, W);
+  if (P->kind == ORC_GL) {
+    double u[4];
+    element_values(P, v, P->conn + e * (P->dim + 1), u);
+    A += P->D1 * (int_power(P->dim, vol, u, 4, -1) + 2.0 * int_power(P->dim, vol, u, 2, -1) + vol);
+  }
+  return A;
 }
 
 /* For every DOF listed in dofs[0..ndofs) (global DOF index n = d*i + j), with e_n the n-th unit
@@ -370,19 +475,21 @@ int64_t orc_grad_patch_fd(const orc_problem *P, double *v, const double *vol,
     for (int64_t t = patch_ptr[i]; t < patch_ptr[i + 1]; ++t) {
       const int64_t e = patch_elem[t];
       double Fp[3][3], Fm[3][3];
+      int bad = 0;
       v[n] = v0 + eps;
       element_F(P, v, P->conn + e * k, dphi + e * k * dim, Fp);
+      const double Ep = element_energy(P, v, e, vol[e], Fp, &bad);
+      const double Cp = bad ? 0.0 : element_energy_abs(P, v, e, vol[e], Fp);
       v[n] = v0 - eps;
       element_F(P, v, P->conn + e * k, dphi + e * k * dim, Fm);
+      const double Em = element_energy(P, v, e, vol[e], Fm, &bad);
+      const double Cm = bad ? 0.0 : element_energy_abs(P, v, e, vol[e], Fm);
       v[n] = v0;
-      int bad = 0;
-      double Wp = density(P, Fp, &bad);
-      double Wm = density(P, Fm, &bad);
       if (bad) { ++nbad; continue; }
-      acc_add(&Sp, vol[e] * Wp);
-      acc_add(&Sm, vol[e] * Wm);
-      C += vol[e] * (density_abs(P, Fp, Wp) + density_abs(P, Fm, Wm));
-      A += fabs(vol[e] * (Wp - Wm)) / (2.0 * eps);
+      acc_add(&Sp, Ep);
+      acc_add(&Sm, Em);
+      C += Cp + Cm;
+      A += fabs(Ep - Em) / (2.0 * eps);
     }
     g[q] = (acc_result(&Sp) - acc_result(&Sm)) / (2.0 * eps);
     if (cond) cond[q] = C;
@@ -415,20 +522,20 @@ int64_t orc_grad_patch_fd4(const orc_problem *P, double *v, const double *vol,
     double C = 0.0, A = 0.0;
     for (int64_t t = patch_ptr[i]; t < patch_ptr[i + 1]; ++t) {
       const int64_t e = patch_elem[t];
-      double W[4], Wabs[4];
+      double W[4], Wabs[4]; /* element energies |T| W and their scales at the four steps */
       int bad = 0;
       for (int h = 0; h < 4; ++h) {
         double F[3][3];
         v[n] = v0 + steps[h];
         element_F(P, v, P->conn + e * k, dphi + e * k * dim, F);
-        W[h] = density(P, F, &bad);
-        Wabs[h] = bad ? 0.0 : density_abs(P, F, W[h]);
+        W[h] = element_energy(P, v, e, vol[e], F, &bad);
+        Wabs[h] = bad ? 0.0 : element_energy_abs(P, v, e, vol[e], F);
       }
       v[n] = v0;
       if (bad) { ++nbad; continue; }
-      for (int h = 0; h < 4; ++h) acc_add(&S[h], vol[e] * W[h]);
-      C += vol[e] * (8.0 * (Wabs[0] + Wabs[1]) + Wabs[2] + Wabs[3]) / 6.0;
-      A += vol[e] * (8.0 * fabs(W[0] - W[1]) + 2.0 * fabs(W[2] - W[3])) / (12.0 * eps);
+      for (int h = 0; h < 4; ++h) acc_add(&S[h], W[h]);
+      C += (8.0 * (Wabs[0] + Wabs[1]) + Wabs[2] + Wabs[3]) / 6.0;
+      A += (8.0 * fabs(W[0] - W[1]) + 2.0 * fabs(W[2] - W[3])) / (12.0 * eps);
     }
     const double d1 = acc_result(&S[0]) - acc_result(&S[1]);
     const double d2 = acc_result(&S[2]) - acc_result(&S[3]);

@@ -22,6 +22,7 @@ from .problems import (  # noqa: F401
     neohooke_box_3d,
     svk_beam_2d,
     svk_box_3d,
+    gl_domain,
     twisted_bar,
     plaplace_lshape,
     config_problem,

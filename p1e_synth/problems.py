@@ -38,6 +38,8 @@ class Problem:
     eps: float = 1e-6         # central-difference step
     h: float = 0.0
     amp: float = 0.0
+    C1: float = 0.0           # Ginzburg-Landau coefficients (the other kinds derive theirs
+    D1: float = 0.0           # from p or from E, nu)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -144,6 +146,34 @@ def svk_box_3d(nx=13, ny=7, nz=5, lx=1.0, ly=0.5, lz=0.4, seed=0, eps=1e-6, amp=
     """The box of neohooke_box_3d with the St. Venant-Kirchhoff density."""
     pb = neohooke_box_3d(nx, ny, nz, lx, ly, lz, seed, eps, amp, jitter)
     return replace(pb, kind="svk", name=f"svk_box_{nx}x{ny}x{nz}")
+
+
+def gl_domain(dim=2, n=64, width=0.25, eps_gl=0.01, seed=0, eps=1e-6, amp=0.1, jitter=0.0,
+              f=0.0):
+    """Ginzburg-Landau (scalar, W = C1 |grad u|^2 + D1 (u^2 - 1)^2 with C1 = eps_gl / 2,
+    D1 = 1/4): the strip [-1,1] x [0,width] (2D, right triangles) or the box
+    [-1,1] x [0,width]^2 (3D, Kuhn tets) with n cells along x; u = -1 prescribed at x = -1 and
+    u = +1 at x = +1; trial field the interface profile tanh(x / sqrt(2 eps_gl)) plus
+    amp * U[-1,1] on the free nodes; constant load f."""
+    m = max(1, int(round(n * width / 2.0)))
+    if dim == 2:
+        coords, conn = rect_tri_mesh(n, m, -1.0, 1.0, 0.0, width)
+    else:
+        coords, conn = kuhn_box_mesh(n, m, m, -1.0, 1.0, 0.0, width, 0.0, width)
+    h = 2.0 / n
+    if jitter > 0.0:
+        coords = jitter_interior(coords, min(h, width / m), jitter, seed + 1000)
+    x = coords[:, 0]
+    dmask = _dirichlet_on(coords, 1, lambda X: (X[:, 0] < -1 + 0.5 * h) | (X[:, 0] > 1 - 0.5 * h))
+    dval = np.where(x > 0, 1.0, -1.0)[:, None] * dmask
+    rng = np.random.default_rng(seed)
+    v = np.tanh(x / np.sqrt(2.0 * eps_gl))[:, None] + amp * rng.uniform(-1.0, 1.0, (len(x), 1))
+    v = np.where(dmask == 1, dval, v)
+    return Problem(
+        name=f"gl{dim}d_n{n}", dim=dim, ncomp=1, kind="gl", coords=coords, conn=conn,
+        dirichlet=dmask, dirichlet_values=dval.astype(np.float64),
+        load=np.full((len(x), 1), float(f)), v=v, eps=eps, h=h, amp=amp,
+        C1=0.5 * eps_gl, D1=0.25, meta={"eps_gl": eps_gl, "width": width})
 
 
 def twisted_bar(level, alpha=2.0 * np.pi, lx=0.4, ly=0.01, lz=0.01):

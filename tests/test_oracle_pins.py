@@ -404,10 +404,15 @@ def _tiny_problems():
         S.neohooke_box_3d(3, 2, 2, 1.0, 0.7, 0.6, amp=0.04, seed=9),
         S.svk_beam_2d(4, 3, 1.0, 0.6, amp=0.05, seed=14),
         S.svk_box_3d(3, 2, 2, 1.0, 0.7, 0.6, amp=0.04, seed=15),
+        S.gl_domain(dim=2, n=6, width=0.7, eps_gl=0.05, amp=0.3, seed=16, jitter=0.2),
+        S.gl_domain(dim=3, n=4, width=0.6, eps_gl=0.05, amp=0.3, seed=17, jitter=0.2),
     ]
 
 
-@pytest.mark.parametrize("idx", range(6))
+NTINY = len(_tiny_problems())
+
+
+@pytest.mark.parametrize("idx", range(NTINY))
 def test_exact_gradient_matches_brute_force(oracle_mod, idx):
     """Exact gradient vs central differences of the whole energy J; error ~ eps^2."""
     P = _tiny_problems()[idx]
@@ -437,7 +442,7 @@ def test_gradient_translation_and_rotation_invariance(oracle_mod, kind):
     assert np.abs(M - M.T).max() < 1e-11 * np.abs(M).max()
 
 
-@pytest.mark.parametrize("idx", range(6))
+@pytest.mark.parametrize("idx", range(NTINY))
 def test_patch_fd_equals_brute_force_fd(oracle_mod, idx):
     """Section 6.1: the patch sums reproduce the full-energy central difference. With a
     dyadic field and step the perturbed values are exact, so only rounding separates them."""
@@ -464,7 +469,7 @@ def test_patch_fd_sampled_positions(oracle_mod):
     assert np.array_equal(O.grad_patch_fd(P.v, 1e-6, sample=pos), full[pos])
 
 
-@pytest.mark.parametrize("idx", range(6))
+@pytest.mark.parametrize("idx", range(NTINY))
 def test_fourth_order_patch_fd_equals_brute_force_and_converges(oracle_mod, idx):
     """The fourth-order scheme on patches reproduces the same stencil applied to the whole
     energy (dyadic field and steps: only rounding separates them). Its distance to the
@@ -487,8 +492,93 @@ def test_fourth_order_patch_fd_equals_brute_force_and_converges(oracle_mod, idx)
     e4 = [np.abs(O.grad_patch_fd(v, h, order=4) - ge).max() / scale for h in hs]
     e2 = [np.abs(O.grad_patch_fd(v, h) - ge).max() / scale for h in hs]
     assert 3.5 < e2[0] / e2[1] < 4.5, e2
-    if P.kind == "svk":
+    if P.kind in ("svk", "gl"):  # quartic in every nodal value
         assert max(e4) < 1e-12
     elif idx != 0:
         assert e4[0] < e2[0]
         assert 14 < e4[0] / e4[1] < 18, e4
+
+
+# ----------------------------------------------------------------------------- Ginzburg-Landau
+def _simplex_gauss(dim, n=5):
+    """Points (barycentric, [npts, dim+1]) and weights (summing to 1) of the collapsed
+    (Duffy) tensor Gauss-Legendre rule on the reference simplex, exact for polynomials of
+    degree <= 2n - dim - 1 >= 4 here; independent of the oracle's barycentric moment formula."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    x, w = 0.5 * (x + 1.0), 0.5 * w
+    pts, wts = [], []
+    if dim == 2:
+        for s_, ws in zip(x, w):
+            for t_, wt in zip(x, w):
+                pts.append((s_, t_ * (1 - s_)))
+                wts.append(ws * wt * (1 - s_))
+        fact = 2.0
+    else:
+        for s_, ws in zip(x, w):
+            for t_, wt in zip(x, w):
+                for r_, wr in zip(x, w):
+                    pts.append((s_, t_ * (1 - s_), r_ * (1 - s_) * (1 - t_)))
+                    wts.append(ws * wt * wr * (1 - s_) ** 2 * (1 - t_))
+        fact = 6.0
+    pts = np.array(pts)
+    lam = np.concatenate([1.0 - pts.sum(axis=1, keepdims=True), pts], axis=1)
+    return lam, np.array(wts) * fact
+
+
+def _one_simplex_gl(dim, rng, C1=0.0, D1=1.0):
+    coords = rng.standard_normal((dim + 1, dim))
+    u = rng.uniform(-1.5, 1.5, (dim + 1, 1))
+    return S.Problem(name="gl_one", dim=dim, ncomp=1, kind="gl", coords=coords,
+                     conn=np.arange(dim + 1, dtype=np.int32)[None, :],
+                     dirichlet=np.zeros((dim + 1, 1), np.uint8),
+                     dirichlet_values=np.zeros((dim + 1, 1)), load=np.zeros((dim + 1, 1)),
+                     v=u, C1=C1, D1=D1)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gl_potential_matches_simplex_quadrature(oracle_mod, dim):
+    """int_T (u^2 - 1)^2 of a P1 field and its derivatives int_T 4 u (u^2 - 1) lambda_l on
+    random simplices, against a collapsed Gauss rule (exact for these degrees)."""
+    rng = np.random.default_rng(40 + dim)
+    lam, wq = _simplex_gauss(dim)
+    for _ in range(5):
+        P = _one_simplex_gl(dim, rng)
+        O = oracle_mod.Oracle(P)
+        vol = O.vol[0]
+        uq = lam @ P.v[:, 0]
+        ref = vol * np.sum(wq * (uq ** 2 - 1.0) ** 2)
+        assert O.energy(P.v)["Jgrad"] == pytest.approx(ref, rel=1e-13)
+        gref = vol * (wq * 4.0 * uq * (uq ** 2 - 1.0)) @ lam
+        assert np.allclose(O.grad_exact(P.v), gref, rtol=1e-12, atol=1e-13 * np.abs(gref).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gl_pure_phases_and_constant_fields(oracle_mod, dim):
+    """u = +-1 everywhere stores no energy; a constant u = c stores D1 (c^2 - 1)^2 |Omega|
+    and has no gradient part (|Omega| = 2 width^(dim-1))."""
+    P = S.gl_domain(dim=dim, n=8, width=0.5, eps_gl=0.02, jitter=0.2, seed=3)
+    O = oracle_mod.Oracle(P)
+    area = 2.0 * 0.5 ** (dim - 1)
+    for c in (1.0, -1.0):
+        assert abs(O.energy(np.full((P.nn, 1), c))["Jgrad"]) < 1e-15
+    for c in (0.0, 0.3, -1.7):
+        r = O.energy(np.full((P.nn, 1), c))["Jgrad"]
+        assert r == pytest.approx(P.D1 * (c * c - 1.0) ** 2 * area, rel=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gl_kink_energy_converges_to_closed_form(oracle_mod, dim):
+    """The 1D interface tanh(x / sqrt(2 eps)) is the minimizer of eps/2 u'^2 + (u^2 - 1)^2/4
+    on the line, with energy (2 sqrt 2 / 3) sqrt(eps) per unit cross-section. Its P1
+    interpolant on strips (2D) and slabs (3D) of [-1,1] converges to it at O(h^2): the error
+    falls by 4 per halving of h (the tails beyond |x| = 1 are below 1e-5 of it)."""
+    eps_gl = 0.01
+    Einf = 2.0 * np.sqrt(2.0) / 3.0 * np.sqrt(eps_gl)
+    errs = []
+    for n in ((32, 64, 128, 256) if dim == 2 else (32, 64, 128)):
+        P = S.gl_domain(dim=dim, n=n, width=4.0 / n, eps_gl=eps_gl, amp=0.0)
+        J = oracle_mod.Oracle(P).energy(P.v)["Jgrad"] / (4.0 / n) ** (dim - 1)
+        errs.append(abs(J - Einf) / Einf)
+    ratios = [a / b for a, b in zip(errs, errs[1:])]
+    assert all(3.8 < r < 4.2 for r in ratios), (errs, ratios)
+    assert errs[-1] < (2e-4 if dim == 2 else 6e-4)
