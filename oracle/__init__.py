@@ -26,8 +26,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "p1e_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-PLAPLACE, NEOHOOKE, SVK, GL = 1, 2, 3, 4
-_KINDS = {"plaplace": PLAPLACE, "neohooke": NEOHOOKE, "svk": SVK, "gl": GL}
+PLAPLACE, NEOHOOKE, SVK, GL, PLAPLACE_ORTHO = 1, 2, 3, 4, 5
+_KINDS = {"plaplace": PLAPLACE, "neohooke": NEOHOOKE, "svk": SVK, "gl": GL,
+          "plaplace_ortho": PLAPLACE_ORTHO}
 
 
 def build(force=True):

@@ -13,7 +13,9 @@
  *                l >= 1, grad phi_0 = -sum of the others).
  *   F_T          eq. (Dv): F_T[j][m] = sum_l v[I(T,l)][j] * d phi_{T,l} / d x_m.
  *   densities    eq. (neoHook): W = C1 (|F|^2 - dim - 2 log det F) + D1 (det F - 1)^2;
- *                eq. (pLaplacian): W = |grad v|^p / p;
+ *                eq. (pLaplacian): W = |grad v|^p / p; and the same with the component-wise
+ *                norm, W = sum_m |d v / d x_m|^p / p, whose minima are the energies printed
+ *                for Benchmark 6 (Table 6);
  *                St. Venant-Kirchhoff, the extension Section 2 names after eq. (neoHook)
  *                (the paper gives no formula; the textbook one): W = C1 |E|^2 + D1 (tr E)^2
  *                with the Green-Lagrange strain E = (F^T F - I) / 2, C1 = mu, D1 = lambda / 2;
@@ -45,7 +47,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_PLAPLACE = 1, ORC_NEOHOOKE = 2, ORC_SVK = 3, ORC_GL = 4 };
+enum { ORC_PLAPLACE = 1, ORC_NEOHOOKE = 2, ORC_SVK = 3, ORC_GL = 4, ORC_PLAPLACE_ORTHO = 5 };
 
 typedef struct {
   int32_t dim;    /* 2 or 3 */
@@ -256,6 +258,10 @@ static double density(const orc_problem *P, double F[3][3], int *bad) {
     double s = 0.0;
     for (int m = 0; m < dim; ++m) s += F[0][m] * F[0][m];
     W = P->C1 * s; /* the gradient part; the potential is added per element */
+  } else if (P->kind == ORC_PLAPLACE_ORTHO) {
+    W = 0.0;
+    for (int m = 0; m < dim; ++m) W += pow(fabs(F[0][m]), P->p);
+    W /= P->p;
   } else {
     double s = 0.0;
     for (int m = 0; m < dim; ++m) s += F[0][m] * F[0][m];
@@ -292,6 +298,10 @@ static void density_dF(const orc_problem *P, double F[3][3], double D[3][3], int
                 + 2.0 * P->D1 * (det - 1.0) * cof[j][m];
   } else if (P->kind == ORC_GL) {
     for (int m = 0; m < dim; ++m) D[0][m] = 2.0 * P->C1 * F[0][m];
+  } else if (P->kind == ORC_PLAPLACE_ORTHO) {
+    /* d/dg_m |g_m|^p / p = |g_m|^(p-2) g_m, 0 at g_m = 0 (p > 1) */
+    for (int m = 0; m < dim; ++m)
+      D[0][m] = F[0][m] != 0.0 ? pow(fabs(F[0][m]), P->p - 2.0) * F[0][m] : 0.0;
   } else {
     double s = 0.0;
     for (int m = 0; m < dim; ++m) s += F[0][m] * F[0][m];

@@ -25,7 +25,8 @@ class Problem:
     name: str
     dim: int
     ncomp: int
-    kind: str                 # "plaplace", "neohooke" or "svk" (St. Venant-Kirchhoff)
+    kind: str                 # "plaplace", "plaplace_ortho" (component-wise norm), "neohooke",
+                              # "svk" (St. Venant-Kirchhoff) or "gl" (Ginzburg-Landau)
     coords: np.ndarray        # f64 [nn, dim]
     conn: np.ndarray          # i32 [ne, dim+1]
     dirichlet: np.ndarray     # u8  [nn, ncomp], 1 = prescribed
@@ -72,10 +73,11 @@ def _dirichlet_on(coords, ncomp, pred):
     return mask
 
 
-def plaplace_square(n=32, p=3.0, f=-10.0, seed=0, eps=1e-6, amp=1.0, jitter=0.0):
+def plaplace_square(n=32, p=3.0, f=-10.0, seed=0, eps=1e-6, amp=1.0, jitter=0.0,
+                    kind="plaplace"):
     """Unit square, (n+1)^2 nodes, 2n^2 right triangles, zero Dirichlet boundary,
     interior v ~ amp*U[-1,1]. jitter > 0: interior nodes moved by up to jitter/n per
-    coordinate (jitter_interior, seed + 1000)."""
+    coordinate (jitter_interior, seed + 1000). kind: "plaplace" or "plaplace_ortho"."""
     coords, conn = rect_tri_mesh(n, n)
     if jitter > 0.0:
         coords = jitter_interior(coords, 1.0 / n, jitter, seed + 1000)
@@ -87,7 +89,7 @@ def plaplace_square(n=32, p=3.0, f=-10.0, seed=0, eps=1e-6, amp=1.0, jitter=0.0)
     v = amp * rng.uniform(-1.0, 1.0, size=(coords.shape[0], 1))
     v[dmask == 1] = 0.0
     return Problem(
-        name=f"plaplace_square_n{n}_p{p:g}", dim=2, ncomp=1, kind="plaplace",
+        name=f"{kind}_square_n{n}_p{p:g}", dim=2, ncomp=1, kind=kind,
         coords=coords, conn=conn, dirichlet=dmask,
         dirichlet_values=np.zeros((coords.shape[0], 1)),
         load=np.full((coords.shape[0], 1), float(f)), v=v, p=float(p), eps=eps, h=1.0 / n,
@@ -192,8 +194,9 @@ def twisted_bar(level, alpha=2.0 * np.pi, lx=0.4, ly=0.01, lz=0.01):
         meta={"alpha": alpha, "lx": lx, "ly": ly, "lz": lz})
 
 
-def plaplace_lshape(n, p=3.0, f=-10.0, seed=0, amp=1.0, eps=1e-5):
-    """L-shape of three unit squares, n cells per unit length, zero Dirichlet boundary."""
+def plaplace_lshape(n, p=3.0, f=-10.0, seed=0, amp=1.0, eps=1e-5, kind="plaplace"):
+    """L-shape of three unit squares, n cells per unit length, zero Dirichlet boundary.
+    kind: "plaplace" (|grad v|^p / p) or "plaplace_ortho" (sum_m |d_m v|^p / p)."""
     coords, conn = lshape_tri_mesh(n)
     # boundary nodes: on the outer square boundary or on the two re-entrant edges
     X = coords
@@ -206,7 +209,7 @@ def plaplace_lshape(n, p=3.0, f=-10.0, seed=0, amp=1.0, eps=1e-5):
     v = amp * rng.uniform(-1.0, 1.0, size=(coords.shape[0], 1))
     v[dmask == 1] = 0.0
     return Problem(
-        name=f"plaplace_lshape_n{n}", dim=2, ncomp=1, kind="plaplace", coords=coords,
+        name=f"{kind}_lshape_n{n}", dim=2, ncomp=1, kind=kind, coords=coords,
         conn=conn, dirichlet=dmask, dirichlet_values=np.zeros((coords.shape[0], 1)),
         load=np.full((coords.shape[0], 1), float(f)), v=v, p=float(p), eps=eps, h=1.0 / n,
         amp=amp)
