@@ -64,6 +64,17 @@ extern "C" {
                           C1 = mu and D1 = lambda / 2 (Lame constants); vector field (d = dim),
                           finite for every F (no bad elements but non-finite values). Energy,
                           exact gradient and patch differences; not served by p1e_server. */
+#define P1E_PLAPLACE_ORTHO 5 /* the p-Laplacian with the component-wise norm of the gradient,
+                          W(g) = sum_m |g_m|^p / p, scalar field (d = 1), p > 1: the density whose
+                          minima Benchmark 6 prints (Table 6; eq. pLaplacian writes |g|^p / p,
+                          P1E_PLAPLACE). Everything P1E_PLAPLACE has, minimizer and server
+                          included. */
+#define P1E_GINZBURG_LANDAU 4 /* Ginzburg-Landau, the scalar first-gradient problem Section 7
+                          names: W = C1 |grad u|^2 + D1 (u^2 - 1)^2 (C1 = eps/2, D1 = 1/4 for the
+                          textbook energy eps/2 |grad u|^2 + (u^2 - 1)^2 / 4), scalar field
+                          (d = 1); the potential is integrated exactly over each element
+                          (a quartic of the P1 field). Energy, exact gradient and patch
+                          differences; not served by p1e_server or p1e_minimize. */
 
 /* ------------------------------------------------------------------ precision modes */
 /* Each compute call names one mode; p1e_mesh_bind takes a bit mask of the modes to prepare. */
@@ -81,13 +92,17 @@ extern "C" {
  * already number elements in compact clusters). Either choice changes only the order of
  * floating-point sums. */
 #define P1E_INPUT_ORDER 1
-/* P1E_FULL_GEOMETRY: always store B^-1 and |T| per element. By default, element records
- * (B^-1, |T|) that agree to 2^-40 of each component's largest magnitude share one class, and
- * a mesh with at most 64 classes (uniformly refined structured meshes have a few) whose every
- * record lies within 2^-42 of its class's first record (relative to each component's largest
- * magnitude; the deviation is reported in p1e_mesh_info) stores one record per class and a
- * one-byte class per element; the elements of a class then use its first record, which
- * differs from their own only by the rounding of node coordinates. */
+/* Element geometry (B^-1 and |T|, Section 4.1). By default, element records that agree to
+ * 2^-40 of each component's largest magnitude share one class, and a mesh with at most 64
+ * classes (uniformly refined structured meshes have a few) whose every record lies within
+ * 2^-42 of its class's first record (relative to each component's largest magnitude; the
+ * deviation is reported in p1e_mesh_info) stores one record per class and a one-byte class
+ * per element; the elements of a class then use its first record, which differs from their
+ * own only by the rounding of node coordinates. Any other mesh stores no per-element
+ * geometry: its tiles (then of at most 512 nodes) keep each node's coordinates as an offset
+ * from the tile's centroid (FP32 in mixed mode, FP64 otherwise) and the element pass forms
+ * B^-1 and |T| from its vertices' offsets. P1E_FULL_GEOMETRY: always store B^-1 and |T| per
+ * element instead. */
 #define P1E_FULL_GEOMETRY 4
 
 typedef struct p1e_mesh p1e_mesh;
@@ -103,8 +118,10 @@ int p1e_material_constants(int kind, double E, double nu, double *C1, double *D1
 /* Mesh and problem description (all arrays are host memory, row-major, 0-based). */
 typedef struct p1e_mesh_desc {
   int32_t dim;   /* 2 (triangles) or 3 (tetrahedra) */
-  int32_t ncomp; /* d: 1 for P1E_PLAPLACE, dim for P1E_NEOHOOKE and P1E_SVK */
-  int32_t kind;  /* P1E_PLAPLACE, P1E_NEOHOOKE or P1E_SVK */
+  int32_t ncomp; /* d: 1 for P1E_PLAPLACE(_ORTHO) and P1E_GINZBURG_LANDAU, dim for
+                    P1E_NEOHOOKE and P1E_SVK */
+  int32_t kind;  /* P1E_PLAPLACE, P1E_PLAPLACE_ORTHO, P1E_NEOHOOKE, P1E_SVK or
+                    P1E_GINZBURG_LANDAU */
   int32_t flags; /* 0 or P1E_INPUT_ORDER | P1E_FULL_GEOMETRY */
   int64_t nn; /* number of nodes, 1 <= nn < 2^28 */
   int64_t ne; /* number of elements, 0 <= ne < 2^29 */
@@ -115,7 +132,8 @@ typedef struct p1e_mesh_desc {
   const double *load;        /* [nn][ncomp] nodal values of the P1 load f; NULL = 0 */
   double p;                  /* p-Laplacian exponent, p > 1 */
   double C1, D1;             /* Neo-Hookean constants (C1 = mu/2, D1 = K/2 in Benchmark 2);
-                                St. Venant-Kirchhoff: C1 = mu, D1 = lambda/2 */
+                                St. Venant-Kirchhoff: C1 = mu, D1 = lambda/2; Ginzburg-Landau:
+                                the coefficients of |grad u|^2 and (u^2 - 1)^2 */
 } p1e_mesh_desc;
 
 typedef struct p1e_mesh_info {
@@ -127,8 +145,9 @@ typedef struct p1e_mesh_info {
   double total_volume, min_volume, max_volume;
   double dirichlet_bv; /* sum over prescribed DOFs of b_n v_n (constant part of b.v) */
   uint64_t alignment;  /* required alignment of the bound device buffer (bytes) */
-  int32_t geometry_classes; /* distinct element records kept as a table (0: per element) */
-  int32_t reserved;
+  int32_t geometry_classes; /* distinct element records kept as a table (0: none) */
+  int32_t geometry_mode;    /* 0: B^-1 and |T| stored per element; 1: geometry classes; 2: formed
+                               in the element pass from the vertex coordinates */
   int64_t n_tiles;      /* element tiles */
   int64_t n_tile_nodes; /* sum over tiles of the distinct nodes of the tile */
   int64_t n_halo_rows;  /* free nodes whose patch spans several tiles (or no element) */

@@ -5,8 +5,9 @@ package is its thin Python binding. Importing it fails if the library is not bui
 """
 
 from ._lib import (  # noqa: F401
-    P1E_FD, P1E_FP64, P1E_FULL_GEOMETRY, P1E_INPUT_ORDER, P1E_MIXED,
-    P1E_NEOHOOKE, P1E_PLAPLACE, P1E_STATIC_SCRATCH_BYTES, P1E_SVK, P1EError, lib,
+    P1E_FD, P1E_FP64, P1E_FULL_GEOMETRY, P1E_GINZBURG_LANDAU, P1E_INPUT_ORDER, P1E_MIXED,
+    P1E_NEOHOOKE, P1E_PLAPLACE, P1E_PLAPLACE_ORTHO, P1E_STATIC_SCRATCH_BYTES, P1E_SVK, P1EError,
+    lib,
 )
 from .api import (  # noqa: F401
     Mesh, Server, energy, energy_forces, grad_exact, grad_exact_static, grad_gather,

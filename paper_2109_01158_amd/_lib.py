@@ -25,6 +25,8 @@ P1E_ESTATE = -7
 P1E_PLAPLACE = 1
 P1E_NEOHOOKE = 2
 P1E_SVK = 3
+P1E_GINZBURG_LANDAU = 4
+P1E_PLAPLACE_ORTHO = 5
 
 P1E_FP64 = 1
 P1E_MIXED = 2
@@ -58,7 +60,7 @@ class MeshInfo(ctypes.Structure):
         ("total_volume", ctypes.c_double), ("min_volume", ctypes.c_double),
         ("max_volume", ctypes.c_double), ("dirichlet_bv", ctypes.c_double),
         ("alignment", ctypes.c_uint64), ("geometry_classes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("n_tiles", ctypes.c_int64),
+        ("geometry_mode", ctypes.c_int32), ("n_tiles", ctypes.c_int64),
         ("n_tile_nodes", ctypes.c_int64), ("n_halo_rows", ctypes.c_int64),
         ("n_halo_slots", ctypes.c_int64), ("geometry_class_deviation", ctypes.c_double),
     ]

@@ -13,10 +13,14 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import P1E_FD, P1E_FP64, P1E_MIXED, P1E_NEOHOOKE, P1E_PLAPLACE, P1E_SVK, check
+from ._lib import (P1E_FD, P1E_FP64, P1E_GINZBURG_LANDAU, P1E_MIXED, P1E_NEOHOOKE, P1E_PLAPLACE,
+                   P1E_PLAPLACE_ORTHO, P1E_SVK, check)
 
-_KINDS = {"plaplace": P1E_PLAPLACE, "neohooke": P1E_NEOHOOKE, "svk": P1E_SVK,
-          P1E_PLAPLACE: P1E_PLAPLACE, P1E_NEOHOOKE: P1E_NEOHOOKE, P1E_SVK: P1E_SVK}
+_KINDS = {"plaplace": P1E_PLAPLACE, "plaplace_ortho": P1E_PLAPLACE_ORTHO, "neohooke": P1E_NEOHOOKE,
+          "svk": P1E_SVK, "gl": P1E_GINZBURG_LANDAU, P1E_PLAPLACE: P1E_PLAPLACE,
+          P1E_PLAPLACE_ORTHO: P1E_PLAPLACE_ORTHO, P1E_NEOHOOKE: P1E_NEOHOOKE, P1E_SVK: P1E_SVK,
+          P1E_GINZBURG_LANDAU: P1E_GINZBURG_LANDAU}
+_SCALAR = (P1E_PLAPLACE, P1E_PLAPLACE_ORTHO, P1E_GINZBURG_LANDAU)
 
 PREC = {"fp64": P1E_FP64, "mixed": P1E_MIXED, P1E_FP64: P1E_FP64, P1E_MIXED: P1E_MIXED}
 
@@ -63,10 +67,11 @@ def svk_constants(E, nu):
 # ------------------------------------------------------------------ 1:1 entry points
 def mesh_create(dim, kind, conn, coords, dirichlet=None, dirichlet_values=None, load=None,
                 p=2.0, C1=0.0, D1=0.0, flags=0):
-    """p1e_mesh_create. kind: "plaplace" | "neohooke" | "svk". Arrays are host numpy;
+    """p1e_mesh_create. kind: "plaplace" | "plaplace_ortho" | "neohooke" | "svk" | "gl". Arrays
+    are host numpy;
     returns an opaque handle (int). flags: 0 or P1E_INPUT_ORDER | P1E_FULL_GEOMETRY."""
     k = _KINDS[kind]
-    ncomp = 1 if k == P1E_PLAPLACE else dim
+    ncomp = 1 if k in _SCALAR else dim
     conn = np.ascontiguousarray(conn, dtype=np.int32)
     coords = np.ascontiguousarray(coords, dtype=np.float64)
     dmask = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
@@ -219,6 +224,8 @@ class Mesh:
             C1, D1 = (neohooke_constants if prob.kind == "neohooke" else svk_constants)(
                 prob.E, prob.nu)
             p = 2.0
+        elif prob.kind == "gl":  # Ginzburg-Landau: the problem's own coefficients
+            C1, D1, p = prob.C1, prob.D1, 2.0
         else:
             C1 = D1 = 0.0
             p = prob.p
@@ -351,7 +358,9 @@ def mesh_minimize(mesh, vhat, history=5, max_iters=200, prec="fp64", stream=None
 def _desc_of(prob, flags=0):
     """A MeshDesc for a p1e_synth.Problem-like object; returns (desc, arrays kept alive)."""
     k = _KINDS[prob.kind]
-    if k != P1E_PLAPLACE:
+    if k == P1E_GINZBURG_LANDAU:
+        C1, D1, p = prob.C1, prob.D1, 2.0
+    elif k not in (P1E_PLAPLACE, P1E_PLAPLACE_ORTHO):
         C1, D1 = (neohooke_constants if k == P1E_NEOHOOKE else svk_constants)(prob.E, prob.nu)
         p = 2.0
     else:

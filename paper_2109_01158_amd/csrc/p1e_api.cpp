@@ -71,8 +71,8 @@ void prof_end(hipStream_t s) {
 static uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  uint64_t wref, bhat, conn_loc, geo64, geo32, geo_cls, ttile, trec, tslot, tlent, hrec, hpart,
-      gw, part, badp, total;
+  uint64_t wref, bhat, conn_loc, geo64, geo32, geo_cls, txo64, txo32, ttile, trec, tslot, tlent,
+      hrec, hpart, gw, part, badp, total;
 };
 
 static Layout make_layout(const p1e_mesh *m, int modes) {
@@ -88,10 +88,14 @@ static Layout make_layout(const p1e_mesh *m, int modes) {
   L.wref = take(8ull * m->nn * m->d);
   L.bhat = take(8ull * m->nfd);
   L.conn_loc = take(2ull * m->ne * m->k);
-  const uint64_t grec = m->nclass ? (uint64_t)m->nclass : (uint64_t)m->ne;  // geometry records
+  const bool otf = m->geo_mode == GEO_OTF;
+  const uint64_t grec = otf ? 0 : m->nclass ? (uint64_t)m->nclass : (uint64_t)m->ne;
   L.geo64 = take((modes & (P1E_FP64 | P1E_FD)) ? 8ull * dd * grec : 0);
   L.geo32 = take((modes & P1E_MIXED) ? 4ull * dd * grec : 0);
   L.geo_cls = take(m->nclass ? (uint64_t)m->ne : 0);
+  const uint64_t nxo = otf ? (uint64_t)m->txo.size() : 0;  // tile node offsets
+  L.txo64 = take((modes & (P1E_FP64 | P1E_FD)) ? 8ull * nxo : 0);
+  L.txo32 = take((modes & P1E_MIXED) ? 4ull * nxo : 0);
   L.ttile = take(4ull * m->ttile.size());
   L.trec = take(4ull * m->trec.size());
   L.tslot = take(2ull * m->tslot.size());
@@ -327,13 +331,13 @@ void classify_geometry(p1e_mesh *m) {
   m->nclass = (int)(keys.size() / dd);
   m->geo_tab = std::move(tab);
   m->geo_cls = std::move(cls);
-  std::vector<double>().swap(m->geo64);
 }
 
 int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   m->dim = D->dim;
   m->d = D->ncomp;
-  m->kind = D->kind;
+  m->kind = D->kind == P1E_PLAPLACE_ORTHO ? P1E_PLAPLACE : D->kind;  // a variant of its density
+  m->ortho = D->kind == P1E_PLAPLACE_ORTHO;
   m->k = D->dim + 1;
   m->nn = D->nn;
   m->ne = D->ne;
@@ -430,10 +434,16 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   }
   m->nf = nf;
 
+  // ---- how the element pass gets its geometry: a few classes, else formed on the fly from
+  // the coordinates, or (P1E_FULL_GEOMETRY) stored per element
+  if (!(D->flags & P1E_FULL_GEOMETRY)) classify_geometry(m);
+  m->geo_mode = m->nclass ? GEO_CLASS : (D->flags & P1E_FULL_GEOMETRY) ? GEO_STORED : GEO_OTF;
+
   // ---- element tiles, local patch rows and halo rows (Section 4.2 patches)
-  int rc = build_tiles(m, conn);
+  int rc = build_tiles(m, conn, m->geo_mode == GEO_OTF ? kTileNodes / 2 : kTileNodes);
   if (rc != P1E_OK) return rc;
   std::vector<int32_t>().swap(conn);
+  if (m->geo_mode == GEO_OTF) tile_offsets(m, D->coords);
 
   // ---- b = M f (Section 3.2): element mass matrix |T| (1 + delta_ab) / ((dim+1)(dim+2)),
   // so b_a += |T| (sum_c f_c + f_a) / ((dim+1)(dim+2)); external numbering
@@ -462,7 +472,7 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
     }
   }
   m->dirichlet_bv = dbv.value();
-  if (!(D->flags & P1E_FULL_GEOMETRY)) classify_geometry(m);
+  if (m->geo_mode != GEO_STORED) std::vector<double>().swap(m->geo64);
   return P1E_OK;
 }
 
@@ -481,9 +491,13 @@ int p1e_mesh_create(const p1e_mesh_desc *D, p1e_mesh **out) {
     if (D->ncomp != D->dim) return fail(P1E_EINVAL, "a deformation needs ncomp == dim");
     if (!std::isfinite(D->C1) || !std::isfinite(D->D1))
       return fail(P1E_EINVAL, "C1 and D1 must be finite");
-  } else if (D->kind == P1E_PLAPLACE) {
+  } else if (D->kind == P1E_PLAPLACE || D->kind == P1E_PLAPLACE_ORTHO) {
     if (D->ncomp != 1) return fail(P1E_EINVAL, "p-Laplacian needs ncomp == 1");
     if (!(D->p > 1.0) || !std::isfinite(D->p)) return fail(P1E_EINVAL, "p must be > 1");
+  } else if (D->kind == P1E_GINZBURG_LANDAU) {
+    if (D->ncomp != 1) return fail(P1E_EINVAL, "Ginzburg-Landau needs ncomp == 1");
+    if (!std::isfinite(D->C1) || !std::isfinite(D->D1))
+      return fail(P1E_EINVAL, "C1 and D1 must be finite");
   } else {
     return fail(P1E_EINVAL, "unknown energy kind");
   }
@@ -539,7 +553,7 @@ int p1e_mesh_get_info(const p1e_mesh *m, p1e_mesh_info *o) {
   o->nnz = m->nnz;
   o->dim = m->dim;
   o->ncomp = m->d;
-  o->kind = m->kind;
+  o->kind = m->ortho ? P1E_PLAPLACE_ORTHO : m->kind;
   o->max_valence = m->max_valence;
   o->total_volume = m->total_vol;
   o->min_volume = m->min_vol;
@@ -547,6 +561,7 @@ int p1e_mesh_get_info(const p1e_mesh *m, p1e_mesh_info *o) {
   o->dirichlet_bv = m->dirichlet_bv;
   o->alignment = kAlign;
   o->geometry_classes = m->nclass;
+  o->geometry_mode = m->geo_mode;
   o->geometry_class_deviation = m->class_dev;
   o->n_tiles = m->ntiles;
   o->n_tile_nodes = m->ntnodes;
@@ -576,9 +591,8 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
     if (n == 0) return true;
     return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s) == hipSuccess;
   };
-  const int dd = m->dim * m->dim + 1;
-  const std::vector<double> &g64 = m->nclass ? m->geo_tab : m->geo64;
-  const uint64_t grec = m->nclass ? (uint64_t)m->nclass : (uint64_t)m->ne;
+  const bool otf = m->geo_mode == GEO_OTF;
+  const std::vector<double> &g64 = otf ? m->txo : m->nclass ? m->geo_tab : m->geo64;
   std::vector<float> g32;
   if (mask & P1E_MIXED) {
     g32.resize(g64.size());
@@ -587,8 +601,9 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
   bool ok = up(L.wref, m->wref.data(), 8 * m->wref.size()) &&
             up(L.bhat, m->bhat.data(), 8 * m->bhat.size()) &&
             up(L.conn_loc, m->conn_loc.data(), 2 * m->conn_loc.size()) &&
-            ((mask & (P1E_FP64 | P1E_FD)) ? up(L.geo64, g64.data(), 8ull * dd * grec) : true) &&
-            ((mask & P1E_MIXED) ? up(L.geo32, g32.data(), 4ull * dd * grec) : true) &&
+            ((mask & (P1E_FP64 | P1E_FD)) ? up(otf ? L.txo64 : L.geo64, g64.data(), 8 * g64.size())
+                                           : true) &&
+            ((mask & P1E_MIXED) ? up(otf ? L.txo32 : L.geo32, g32.data(), 4 * g32.size()) : true) &&
             up(L.geo_cls, m->geo_cls.data(), m->geo_cls.size()) &&
             up(L.ttile, m->ttile.data(), 4 * m->ttile.size()) &&
             up(L.trec, m->trec.data(), 4 * m->trec.size()) &&
@@ -612,6 +627,13 @@ int p1e_mesh_bind(p1e_mesh *m, void *buf, uint64_t bytes, int mask, void *stream
   D.geo32 = (mask & P1E_MIXED) ? (const float *)(base + L.geo32) : nullptr;
   D.geo_cls = m->nclass ? (const uint8_t *)(base + L.geo_cls) : nullptr;
   D.nclass = m->nclass;
+  D.geo_mode = m->geo_mode;
+  if (otf) {
+    D.geo64 = nullptr;
+    D.geo32 = nullptr;
+    D.txo64 = (mask & (P1E_FP64 | P1E_FD)) ? (const double *)(base + L.txo64) : nullptr;
+    D.txo32 = (mask & P1E_MIXED) ? (const float *)(base + L.txo32) : nullptr;
+  }
   D.ttile = (const int4 *)(base + L.ttile);
   D.trec = (const int4 *)(base + L.trec);
   D.tslot = (const uint16_t *)(base + L.tslot);

@@ -56,26 +56,29 @@ constexpr int batch_tile_threads() {
 template <int DIM, int D, int KIND, typename T, int C>
 __global__ __launch_bounds__((batch_tile_threads<T>())) void kb_tile(EngineDev E) {
   constexpr int NT = batch_tile_threads<T>();
-  __shared__ TileShared<DIM, D, T, MODE_FORCE, true> sh;
+  __shared__ TileShared<DIM, D, T, MODE_FORCE, (1 << GEO_STORED) | (1 << GEO_CLASS) | (1 << GEO_OTF)> sh;
   int count;
   const int2 *tl = tiles<TK_TILE, C>(E, count);
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const int2 st = tl[t];
     if (!evaluating(E, st.x)) continue;
     const SlotDev &S = E.slots[st.x];
-    const Params prm{S.C1, S.D1, S.p, 0.0};
-    const T *geo = sizeof(T) == 4 ? (const T *)S.M.geo32 : (const T *)S.M.geo64;
+    const Params prm{S.C1, S.D1, S.p, 0.0, S.ortho};
+    const bool otf = S.M.geo_mode == GEO_OTF;
+    const T *geo = sizeof(T) == 4 ? (const T *)(otf ? (const void *)S.M.txo32 : S.M.geo32)
+                                  : (const T *)(otf ? (const void *)S.M.txo64 : S.M.geo64);
     using Split = TileSplit<DIM, NT>;
     typename Split::Head h;
-    if (S.M.geo_cls != nullptr) {
-      tile_head<Split::NPT, NT>(S.M, st.y, h, threadIdx.x);
-      tile_pass<DIM, D, KIND, T, MODE_FORCE, true, NT>(S.M, h, geo, S.vt, S.gt, nullptr, prm,
-                                                       sh, threadIdx.x);
-    } else {
-      tile_head<Split::NPT, NT>(S.M, st.y, h, threadIdx.x);
-      tile_pass<DIM, D, KIND, T, MODE_FORCE, false, NT>(S.M, h, geo, S.vt, S.gt, nullptr, prm,
-                                                        sh, threadIdx.x);
-    }
+    tile_head<Split::NPT, NT>(S.M, st.y, h, threadIdx.x);
+    if (S.M.geo_mode == GEO_CLASS)
+      tile_pass<DIM, D, KIND, T, MODE_FORCE, GEO_CLASS, NT>(S.M, h, geo, S.vt, S.gt, nullptr,
+                                                            prm, sh, threadIdx.x);
+    else if (otf)
+      tile_pass<DIM, D, KIND, T, MODE_FORCE, GEO_OTF, NT>(S.M, h, geo, S.vt, S.gt, nullptr,
+                                                          prm, sh, threadIdx.x);
+    else
+      tile_pass<DIM, D, KIND, T, MODE_FORCE, GEO_STORED, NT>(S.M, h, geo, S.vt, S.gt, nullptr,
+                                                             prm, sh, threadIdx.x);
   }
 }
 

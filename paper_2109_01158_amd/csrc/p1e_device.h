@@ -9,7 +9,8 @@
 //   |F|^2 - dim = 2 tr G + |G|^2,  det F - 1 = tr G + s2(G) + det G  (s2: sum of principal
 //   2x2 minors, absent in 2D),  (det F - 1) - log det F  by log_excess (double),
 //   F - F^-T = [(s2 + det G) I + (det F) G + G^T - cof G] / det F  (2D: cof terms reduce),
-// and accumulates the energies and the patch sums of the element forces in double.
+// and accumulates the energies in double and the patch sums of the element forces in rounds:
+// each lane adds up to four forces of its node in float, and the rounds in double.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,6 +43,7 @@ __device__ __forceinline__ T stream_load(const T *p) {
 
 struct Params {
   double C1, D1, p, eps;
+  int ortho;  // p-Laplacian with the component-wise norm of the gradient (uniform per mesh)
 };
 
 // ----------------------------------------------------------------------- compensated sums
@@ -254,9 +256,10 @@ __device__ __forceinline__ double quotient(double num, double den) {
 // About 40 double instructions, against over 100 for a general-purpose log1p.
 __device__ __forceinline__ double log_excess(double d) {
   const double t = 1.0 + d;
+  constexpr double kRt = 0.70710678118654752440;  // 1/sqrt 2 rounded
   int k;
   double m = frexp(t, &k);  // t = m 2^k, m in [1/2, 1)
-  const bool lo = m < 0.70710678118654752440;
+  const bool lo = m < kRt;
   m = lo ? 2.0 * m : m;
   k = lo ? k - 1 : k;
   const bool k0 = k == 0;
@@ -489,27 +492,103 @@ __device__ __forceinline__ T pl_norm2(const T g[DIM]) {
   return s;
 }
 
-// p-Laplacian density |g|^p / p (eq. pLaplacian), in double
+// p-Laplacian density |g|^p / p (eq. pLaplacian), in double; with ortho the density with the
+// component-wise norm, sum_m |g_m|^p / p (the one whose minima Table 6 prints)
 template <int DIM, typename T>
-__device__ __forceinline__ double pl_energy(const T g[DIM], double p, bool &bad) {
-  const double W = half_pow((double)pl_norm2<DIM, T>(g), p) / p;
+__device__ __forceinline__ double pl_energy(const T g[DIM], double p, bool ortho, bool &bad) {
+  double W;
+  if (ortho) {
+    W = 0.0;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) W += half_pow((double)(g[m] * g[m]), p);
+    W /= p;
+  } else {
+    W = half_pow((double)pl_norm2<DIM, T>(g), p) / p;
+  }
   if (!isfinite(W)) bad = true;
   return W;
 }
 
-// the density and vol times its gradient, vol |g|^(p-2) g (0 at g = 0), from one power |g|^p;
-// the density is bitwise the one of pl_energy
+// the density and vol times its gradient, vol |g|^(p-2) g (0 at g = 0), from one power |g|^p
+// (ortho: vol |g_m|^(p-2) g_m per component); the density is bitwise the one of pl_energy
 template <int DIM, typename T>
-__device__ __forceinline__ double pl_energy_stress(const T g[DIM], double p, T vol, bool &bad,
-                                                   T P[DIM]) {
-  const T s = pl_norm2<DIM, T>(g);
-  const double sp = half_pow((double)s, p);
-  const double W = sp / p;
-  if (!isfinite(W)) bad = true;
-  const T sc = s > T(0) ? (T)(sp / (double)s) * vol : T(0);
+__device__ __forceinline__ double pl_energy_stress(const T g[DIM], double p, bool ortho, T vol,
+                                                   bool &bad, T P[DIM]) {
+  double W;
+  if (ortho) {
+    W = 0.0;
 #pragma unroll
-  for (int m = 0; m < DIM; ++m) P[m] = sc * g[m];
+    for (int m = 0; m < DIM; ++m) {
+      const T s = g[m] * g[m];
+      const double sp = half_pow((double)s, p);
+      W += sp;
+      P[m] = s > T(0) ? (T)(sp / (double)s) * vol * g[m] : T(0);
+    }
+    W /= p;
+  } else {
+    const T s = pl_norm2<DIM, T>(g);
+    const double sp = half_pow((double)s, p);
+    W = sp / p;
+    const T sc = s > T(0) ? (T)(sp / (double)s) * vol : T(0);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) P[m] = sc * g[m];
+  }
+  if (!isfinite(W)) bad = true;
   return W;
+}
+
+// Ginzburg-Landau, the scalar first-gradient problem Section 7 names: W = C1 |grad u|^2 (here)
+// plus the potential D1 int_T (u^2 - 1)^2 dx of the element's P1 field (gl_potential). With
+// u = sum_l u_l lambda_l, int_T u^k dx = |T| k! dim! / (k + dim)! h_k(u_0, ..., u_dim) (h_k the
+// complete homogeneous symmetric polynomial, from the power sums by Newton's identities), so
+//   int_T (u^2 - 1)^2 = |T| (c4 h_4 - 2 c2 h_2 + 1),  c4 = 4! dim!/(4+dim)!, c2 = 2! dim!/(2+dim)!
+// and d h_k / d u_l = h_(k-1)(u_0, ..., u_dim, u_l). Evaluated in double in both precisions.
+template <int DIM>
+struct GlCoef {
+  static constexpr double c4 = DIM == 2 ? 1.0 / 15.0 : 1.0 / 35.0;
+  static constexpr double c2 = DIM == 2 ? 1.0 / 6.0 : 1.0 / 10.0;
+};
+struct PowerSums {
+  double p1, p2, p3, p4;
+};
+template <int DIM, typename T>
+__device__ __forceinline__ PowerSums gl_power_sums(const T (&uu)[DIM + 1][1]) {
+  PowerSums q{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int l = 0; l <= DIM; ++l) {
+    const double x = (double)uu[l][0], x2 = x * x;
+    q.p1 += x;
+    q.p2 += x2;
+    q.p3 += x2 * x;
+    q.p4 += x2 * x2;
+  }
+  return q;
+}
+// h_2 and h_4 from power sums
+__device__ __forceinline__ double gl_h2(const PowerSums &q) { return 0.5 * (q.p1 * q.p1 + q.p2); }
+__device__ __forceinline__ double gl_h4(const PowerSums &q) {
+  const double h1 = q.p1, h2 = gl_h2(q);
+  const double h3 = (q.p1 * h2 + q.p2 * h1 + q.p3) / 3.0;
+  return 0.25 * (q.p1 * h3 + q.p2 * h2 + q.p3 * h1 + q.p4);
+}
+// D1 int_T (u^2 - 1)^2 dx
+template <int DIM>
+__device__ __forceinline__ double gl_potential(const PowerSums &q, double vol, double D1) {
+  return D1 * vol * (GlCoef<DIM>::c4 * gl_h4(q) - 2.0 * GlCoef<DIM>::c2 * gl_h2(q) + 1.0);
+}
+// its first and third derivatives in u_l (the potential is a quartic in u_l)
+template <int DIM>
+__device__ __forceinline__ double gl_potential_d1(const PowerSums &q, double x, double vol,
+                                                  double D1) {
+  const double x2 = x * x;
+  const double r1 = q.p1 + x, r2 = q.p2 + x2, r3 = q.p3 + x2 * x;  // power sums with u_l twice
+  const double h3 = (r1 * r1 * r1 + 3.0 * r1 * r2 + 2.0 * r3) / 6.0;
+  return D1 * vol * (GlCoef<DIM>::c4 * h3 - 2.0 * GlCoef<DIM>::c2 * r1);
+}
+template <int DIM>
+__device__ __forceinline__ double gl_potential_d3(const PowerSums &q, double x, double vol,
+                                                  double D1) {
+  return D1 * vol * GlCoef<DIM>::c4 * (18.0 * x + 6.0 * q.p1);
 }
 
 // density dispatch on a D x DIM gradient
@@ -519,8 +598,12 @@ __device__ __forceinline__ double density(const T G[D][DIM], const Params &prm, 
     return nh_energy<DIM, T>(G, prm.C1, prm.D1, bad);
   } else if constexpr (KIND == P1E_SVK) {
     return svk_energy<DIM, T>(G, prm.C1, prm.D1, bad);
+  } else if constexpr (KIND == P1E_GINZBURG_LANDAU) {  // the gradient part only
+    const double W = prm.C1 * (double)pl_norm2<DIM, T>(G[0]);
+    if (!isfinite(W)) bad = true;
+    return W;
   } else {
-    return pl_energy<DIM, T>(G[0], prm.p, bad);
+    return pl_energy<DIM, T>(G[0], prm.p, prm.ortho != 0, bad);
   }
 }
 
@@ -547,24 +630,75 @@ __device__ __forceinline__ void store_entries(T *__restrict__ r, int nep, int e,
   }
 }
 
+// Element geometry from its vertices (Section 4.1): the edge matrix
+// B = [x_1 - x_0, ..., x_dim - x_0] (columns) from the vertex offsets xx[l][m] (offsets from a
+// common origin), B^-1 by its adjugate (row l of B^-1 is grad phi_(l+1)) and |T| = |det B| / dim!.
+template <int DIM, typename T>
+__device__ __forceinline__ void simplex_geometry(const T (&xx)[DIM + 1][DIM], T Bi[DIM][DIM],
+                                                 T &vol) {
+  T B[DIM][DIM];
+#pragma unroll
+  for (int m = 0; m < DIM; ++m)
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) B[m][l] = xx[l + 1][m] - xx[0][m];
+  T det;
+  if constexpr (DIM == 3) {
+    T cof[3][3];  // cof[m][l]: the cofactor of B[m][l]
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const int m1 = (m + 1) % 3, m2 = (m + 2) % 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+        cof[m][l] = mad(B[m1][l1], B[m2][l2], -(B[m1][l2] * B[m2][l1]));
+      }
+    det = mad(B[0][0], cof[0][0], mad(B[0][1], cof[0][1], B[0][2] * cof[0][2]));
+    T r;
+    if constexpr (std::is_same<T, float>::value)
+      r = __builtin_amdgcn_rcpf(det);
+    else
+      r = T(1) / det;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) Bi[l][m] = cof[m][l] * r;
+    vol = fabs(det) * T(1.0 / 6.0);
+  } else {
+    det = mad(B[0][0], B[1][1], -(B[0][1] * B[1][0]));
+    T r;
+    if constexpr (std::is_same<T, float>::value)
+      r = __builtin_amdgcn_rcpf(det);
+    else
+      r = T(1) / det;
+    Bi[0][0] = B[1][1] * r;
+    Bi[0][1] = -B[0][1] * r;
+    Bi[1][0] = -B[1][0] * r;
+    Bi[1][1] = B[0][0] * r;
+    vol = fabs(det) * T(0.5);
+  }
+}
+
 // The element pass for element e < ne, given u at its vertices (uu): G = grad u (eq. Dv),
 // the density (energy of the element added to (s, c), bad elements counted in cnt) and, by
 // MODE, the element forces |T| dW/dF grad phi_l (Section 6.2) or the per-element central
 // differences of |T| W under a perturbation of one row of F (Section 6.1), written as
 // vertex-major entries r[(l nep + er) D + j].
-// geo: [DIM*DIM][ne] entries of B^-1 followed by [ne] sizes |T|; or, with CLS, a table of
-// records [DIM*DIM entries of B^-1, |T|] and cls = the element's class.
+// Geometry by GEO: (GEO_STORED) geo holds [DIM*DIM][ne] entries of B^-1 followed by [ne]
+// sizes |T|; (GEO_CLASS) geo is a table of records [DIM*DIM entries of B^-1, |T|] and cls the
+// element's class; (GEO_OTF) xx holds the vertices' coordinate offsets (simplex_geometry).
 // FIRST: (s, c) holds nothing yet, so the element's energy is assigned instead of added
-template <int DIM, int D, int KIND, typename T, int MODE, bool CLS, bool FIRST = false>
+template <int DIM, int D, int KIND, typename T, int MODE, int GEO, bool FIRST = false>
 __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 1][D],
                                              const T *__restrict__ geo, int cls,
+                                             const T (&xx)[DIM + 1][DIM],
                                              T *__restrict__ r, int nep, int er,
                                              const Params &prm, double &s, double &c,
                                              int &cnt) {
   constexpr int K = DIM + 1;
   T Bi[DIM][DIM];
   T vol;
-  if constexpr (CLS) {
+  if constexpr (GEO == GEO_OTF) {
+    simplex_geometry<DIM, T>(xx, Bi, vol);
+  } else if constexpr (GEO == GEO_CLASS) {
     const T *rec = geo + cls * (DIM * DIM + 1);
 #pragma unroll
     for (int l = 0; l < DIM; ++l)
@@ -597,8 +731,13 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
     W = nh_energy_stress<DIM, T>(G, prm.C1, prm.D1, vol, bad, P);  // P = |T| dW/dF
   } else if constexpr (MODE == MODE_FORCE && KIND == P1E_SVK) {
     W = svk_energy_stress<DIM, T>(G, prm.C1, prm.D1, vol, bad, P);
+  } else if constexpr (MODE == MODE_FORCE && KIND == P1E_GINZBURG_LANDAU) {
+    W = density<DIM, D, KIND, T>(G, prm, bad);
+    const T a = T(2) * (T)prm.C1 * vol;  // vol dW/dgrad u = 2 C1 vol grad u
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) P[0][m] = a * G[0][m];
   } else if constexpr (MODE == MODE_FORCE) {
-    W = pl_energy_stress<DIM, T>(G[0], prm.p, vol, bad, P[0]);
+    W = pl_energy_stress<DIM, T>(G[0], prm.p, prm.ortho != 0, vol, bad, P[0]);
   } else if constexpr (is_fd(MODE) && KIND == P1E_NEOHOOKE) {
     nv = nh_invariants<DIM, T>(G);
     W = nh_density<DIM, T>(nv, prm.C1, prm.D1, bad);
@@ -619,6 +758,12 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
         out[l * D + j] = acc;
         out[j] -= acc;
       }
+    if constexpr (KIND == P1E_GINZBURG_LANDAU) {  // + d/du_l of the potential
+      const PowerSums q = gl_power_sums<DIM, T>(uu);
+#pragma unroll
+      for (int l = 0; l < K; ++l)
+        out[l] += (T)gl_potential_d1<DIM>(q, (double)uu[l][0], (double)vol, prm.D1);
+    }
     store_entries<T, D, K>(r, nep, er, out);
   }
   if constexpr (is_fd(MODE)) {
@@ -693,6 +838,25 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
         }
         continue;
       }
+      if constexpr (KIND == P1E_GINZBURG_LANDAU) {
+        // |T| W(+h) - |T| W(-h) from the structure of the step: the gradient part changes by
+        // C1 |T| (|g + h a|^2 - |g - h a|^2) = 4 h C1 |T| g.a, and the potential, a quartic in
+        // u_l, by 2 h P' + h^3 P''' / 3 (its odd Taylor terms), both exact
+        const PowerSums q = gl_power_sums<DIM, T>(uu);
+        const double x = (double)uu[l][0], vd = (double)vol;
+        double ga = 0.0;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) ga = fma((double)G[0][m], (double)a[m], ga);
+        const double p1 = gl_potential_d1<DIM>(q, x, vd, prm.D1);
+        const double p3 = gl_potential_d3<DIM>(q, x, vd, prm.D1);
+        auto dE = [&](double h) {
+          return 4.0 * h * prm.C1 * vd * ga + 2.0 * h * p1 + h * h * h * p3 / 3.0;
+        };
+        const double d = scheme(dE(eps), MODE == MODE_FD4 ? dE(2.0 * eps) : 0.0);
+        if (!isfinite(d)) bad = true;
+        out[l] = (T)d;
+        continue;
+      }
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         auto dW = [&](double h) {  // W(+h) - W(-h): two density evaluations
@@ -717,13 +881,18 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
     }
     store_entries<T, D, K>(r, nep, er, out);
   }
+  double Ee = (double)vol * W;  // the element's energy |T| W
+  if constexpr (KIND == P1E_GINZBURG_LANDAU) {
+    Ee += gl_potential<DIM>(gl_power_sums<DIM, T>(uu), (double)vol, prm.D1);
+    if (!isfinite(Ee)) bad = true;
+  }
   if (bad) {
     cnt += 1;
   } else if (FIRST) {
-    s = (double)vol * W;
+    s = Ee;
   } else {
     double t, err;
-    two_sum(s, (double)vol * W, t, err);
+    two_sum(s, Ee, t, err);
     s = t;
     c += err;
   }
@@ -732,16 +901,23 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
 // LDS of one element tile: the staged nodal values, the element results (vertex-major,
 // [dim+1][kTileElems][D]), the tile's local patch entries and the geometry class table.
 // 16-byte aligned: nodal values and patch entries move as 16-byte vectors.
-template <int DIM, int D, typename T, int MODE, bool CLS>
+// GSET: the geometry modes (bits 1 << GEO) the workgroup may meet. With GEO_OTF tiles (at
+// most kTileNodes / 2 nodes) the first half of us holds the nodal values and the second half
+// (xs) the nodes' coordinate offsets, so us has slots of max(NS, NSX) scalars.
+template <int DIM, int D, typename T, int MODE, int GSET>
 struct alignas(16) TileShared {
   static constexpr int K = DIM + 1, NS = NodeVec<T, D>::NS, REC = DIM * DIM + 1;
+  static constexpr int NSX = NodeVec<T, DIM>::NS;
+  static constexpr bool CLS = (GSET >> GEO_CLASS) & 1, OTF = (GSET >> GEO_OTF) & 1;
+  static constexpr int NSU = OTF && NSX > NS ? NSX : NS;
   static constexpr int NENT = (K * kTileElems + kEntAlign - 1) / kEntAlign * kEntAlign;
-  T us[kTileNodes * NS];
+  T us[kTileNodes * NSU];
   T fs[MODE == MODE_ENERGY ? 4 : K * kTileElems * D + 4];  // + a zero record at the end
   uint16_t lent[MODE == MODE_ENERGY ? kEntAlign : NENT + kEntAlign];  // + slack read past rows
   T tab[CLS ? kMaxGeoClasses * REC : 4];
   double red[2 * 16];  // per-wavefront shares: energy, then b.v
   int nbad[16];
+  __device__ T *xs() { return us + (kTileNodes / 2) * NSU; }
 };
 
 // Patch sums of a tile's free nodes (Section 4.2 patch restricted to the tile), GL lanes per
@@ -791,10 +967,16 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int j = 0; j < D; ++j) q[u][j] = sh.fs[x[u] + j];
+      if constexpr (std::is_same<T, float>::value) {
+        // (mixed) the round's four forces summed in float, the rounds in double
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+        for (int j = 0; j < D; ++j) acc[j] += (double)((q[0][j] + q[1][j]) + (q[2][j] + q[3][j]));
+      } else {
 #pragma unroll
-        for (int j = 0; j < D; ++j) acc[j] += (double)q[u][j];
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int j = 0; j < D; ++j) acc[j] += (double)q[u][j];
+      }
     }
     static_assert(GL == 1 || GL == 2, "one or two lanes per node");
     if constexpr (GL == 2) {  // the node's two lanes are neighbours: a DPP swap within quads
@@ -824,7 +1006,8 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
 //  0. issue the loads that depend on nothing else: the local connectivity (and classes) of
 //     the thread's elements, its node records, and the tile's local patch entries (into LDS);
 //  1. stage the nodal field u (u = v - x for Neo-Hookean, u = v for the p-Laplacian) of the
-//     tile's nodes in LDS; the tile that meets a node first adds b.v of its free DOFs;
+//     tile's nodes in LDS (GEO_OTF: and their coordinate offsets); the tile that meets a node
+//     first adds b.v of its free DOFs;
 //  2. element pass of the tile's elements, vertex values read from LDS, element results
 //     written to LDS; energies into (s, c);
 //  3. patch sums of the tile's free nodes from LDS (tile_patch_sums);
@@ -832,7 +1015,8 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
 //     values), then compensated sums of the wavefront shares: energy -> part[t],
 //     b.v -> part[ntiles + t], bad count.
 // Every order is fixed: the results do not depend on timing. No atomics.
-// geo: the global geometry arrays (or class table, staged in sh.tab when CLS).
+// geo: by GEO, the per-element geometry arrays, the class table (staged in sh.tab) or the
+// tile nodes' coordinate offsets (staged in sh.xs()).
 // What a tile's pass reads first: its bounds and its node records (the nodal loads depend
 // on them). A persistent caller loads the next tile's head while the current tile sums its
 // patches, so that a tile starts with one memory round trip instead of two.
@@ -866,7 +1050,7 @@ struct TileSplit {
   using Head = TileHead<NPT>;
 };
 
-template <int DIM, int D, int KIND, typename T, int MODE, bool CLS, int NT, class SH>
+template <int DIM, int D, int KIND, typename T, int MODE, int GEO, int NT, class SH>
 __device__ __forceinline__ void tile_pass(const TileMesh &M,
                                           const typename TileSplit<DIM, NT>::Head &h,
                                           const T *__restrict__ geo,
@@ -890,11 +1074,11 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
     const int e = e0 + min(k * NT + tid, net - 1);
 #pragma unroll
     for (int l = 0; l < K; ++l) nd[k][l] = stream_load(M.conn_loc + (int64_t)l * M.ne + e);
-    cl[k] = CLS ? (int)stream_load(M.geo_cls + e) : 0;
+    cl[k] = GEO == GEO_CLASS ? (int)stream_load(M.geo_cls + e) : 0;
   }
   constexpr int LQ = (K * kTileElems / kEntAlign + NT - 1) / NT;  // 16-byte entry groups
   constexpr int TQ = (kMaxGeoClasses * REC + NT - 1) / NT;
-  const int nlq = (tb.z - ta.z) / kEntAlign, ntq = CLS ? M.nclass * REC : 0;
+  const int nlq = (tb.z - ta.z) / kEntAlign, ntq = GEO == GEO_CLASS ? M.nclass * REC : 0;
   uint4 lq[LQ];
   T tq[TQ];
   if constexpr (MODE != MODE_ENERGY) {
@@ -903,7 +1087,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
     for (int i = 0; i < LQ; ++i)
       if (i * NT + tid < nlq) lq[i] = src[i * NT + tid];
   }
-  if constexpr (CLS) {
+  if constexpr (GEO == GEO_CLASS) {
 #pragma unroll
     for (int i = 0; i < TQ; ++i)
       if (i * NT + tid < ntq) tq[i] = geo[i * NT + tid];
@@ -918,10 +1102,15 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
     const int mask = rec[k].y & 7;
     const bool own = (rec[k].z >> 1) & 1;
     double w[D], vj[D], bj[D];
+    T xo[DIM];  // (GEO_OTF) the node's coordinate offset, read once
 #pragma unroll
     for (int j = 0; j < D; ++j) w[j] = 0.0, vj[j] = 0.0, bj[j] = 0.0;
     if (a < nloc) {
       const int gi = rec[k].x, fb = rec[k].y >> 3;
+      if constexpr (GEO == GEO_OTF) {
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) xo[j] = stream_load(geo + (int64_t)(r0 + a) * DIM + j);
+      }
 #pragma unroll
       for (int j = 0; j < D; ++j) w[j] = M.wref[(int64_t)gi * D + j];
 #pragma unroll
@@ -940,7 +1129,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
           if (i * NT + tid < nlq) dst[i * NT + tid] = lq[i];
         if (tid < D) sh.fs[K * kTileElems * D + tid] = T(0);
       }
-      if constexpr (CLS) {
+      if constexpr (GEO == GEO_CLASS) {
 #pragma unroll
         for (int i = 0; i < TQ; ++i)
           if (i * NT + tid < ntq) sh.tab[i * NT + tid] = tq[i];
@@ -956,6 +1145,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
         if (fr) bvn = fma(bj[j], vj[j], bvn);
       }
       NodeVec<T, D>::store(sh.us, h.slot[k], o);
+      if constexpr (GEO == GEO_OTF) NodeVec<T, DIM>::store(sh.xs(), h.slot[k], xo);
       if (own) {
         if (NPT == 1) {
           sb = bvn;
@@ -990,16 +1180,18 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
   for (int k = 0; k < EPT; ++k) {
     const int le = k * NT + tid;
     if (le < net) {
-      T uu[K][D];
+      T uu[K][D], xx[K][DIM];
 #pragma unroll
       for (int l = 0; l < K; ++l) NodeVec<T, D>::load(sh.us, nd[k][l], uu[l]);
+      if constexpr (GEO == GEO_OTF) {
+#pragma unroll
+        for (int l = 0; l < K; ++l) NodeVec<T, DIM>::load(sh.xs(), nd[k][l], xx[l]);
+      }
       constexpr bool FIRST = EPT == 1;
-      if constexpr (CLS)
-        element_pass<DIM, D, KIND, T, MODE, true, FIRST>(e0 + le, M.ne, uu, sh.tab, cl[k],
-                                                         sh.fs, kTileElems, le, prm, s, c, cnt);
-      else
-        element_pass<DIM, D, KIND, T, MODE, false, FIRST>(e0 + le, M.ne, uu, geo, 0, sh.fs,
-                                                          kTileElems, le, prm, s, c, cnt);
+      element_pass<DIM, D, KIND, T, MODE, GEO, FIRST>(e0 + le, M.ne, uu,
+                                                      GEO == GEO_CLASS ? sh.tab : geo, cl[k],
+                                                      xx, sh.fs, kTileElems, le, prm, s, c,
+                                                      cnt);
     }
   }
   // the next tile's head: in flight while this tile sums its patches

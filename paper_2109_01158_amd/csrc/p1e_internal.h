@@ -29,6 +29,15 @@ constexpr uint64_t kAlign = 256;   // alignment of every sub-array in the bound 
 constexpr int kMaxGeoClasses = 64; // geometry classes kept as one-byte indices
 constexpr double kClassDeviation = 0x1p-42;  // largest relative record change of a class
 
+// How the element pass gets B^-1 and |T| (Section 4.1):
+//   GEO_STORED  per-element records [dim*dim+1][ne] (P1E_FULL_GEOMETRY);
+//   GEO_CLASS   a table of at most kMaxGeoClasses records and a one-byte class per element;
+//   GEO_OTF     formed in the tile from its nodes' coordinates, staged in LDS as offsets from
+//               the tile's centroid (meshes without few enough classes); such tiles touch at
+//               most kTileNodes / 2 nodes, and the offsets take the other half of the nodal
+//               value slots.
+enum GeoMode { GEO_STORED = 0, GEO_CLASS = 1, GEO_OTF = 2 };
+
 // Device view of a bound mesh (all arrays in the caller's buffer). Internal numbering: the
 // elements in tile order, the nodes in order of first use by the elements.
 //
@@ -54,6 +63,10 @@ struct TileMesh {
   const float *geo32 = nullptr;     // FP32 (mixed mode)
   const uint8_t *geo_cls = nullptr; // [ne] class of each element, or nullptr
   int32_t nclass = 0;
+  int32_t geo_mode = GEO_STORED;
+  // GEO_OTF: per tile node (record order) its coordinates minus the tile's centroid, [dim]
+  const double *txo64 = nullptr;    // FP64
+  const float *txo32 = nullptr;     // FP32 (mixed mode)
   // tiles
   const int4 *ttile = nullptr;  // [ntiles+1] {first element, first node record, first patch
                                 //  entry, 0}; the last one closes the ranges
@@ -73,6 +86,7 @@ struct TileMesh {
 
 struct p1e_mesh {
   int dim = 0, d = 0, kind = 0, k = 0;
+  int ortho = 0;  // P1E_PLAPLACE_ORTHO: kind P1E_PLAPLACE with the component-wise norm
   int64_t nn = 0, ne = 0, nf = 0, nfd = 0, nnz = 0;
   double p = 2.0, C1 = 0.0, D1 = 0.0;
   int max_valence = 0;
@@ -84,6 +98,8 @@ struct p1e_mesh {
   double class_dev = 0.0;          // largest relative change of a record by its class
   std::vector<uint8_t> geo_cls;    // [ne] class of each element
   std::vector<double> geo_tab;     // [nclass][dim*dim+1]
+  int geo_mode = p1e::GEO_STORED;  // GeoMode
+  std::vector<double> txo;         // GEO_OTF: [sum nloc][dim] node offsets from tile centroids
   std::vector<int32_t> ninfo;      // [nn] internal order
   std::vector<double> wref;        // [nn][d] internal order
   std::vector<double> bhat;        // [nfd]
@@ -115,7 +131,8 @@ void prof_end(hipStream_t s);
 inline int64_t nblocks(int64_t n, int per = kBlock) { return (n + per - 1) / per; }
 
 // host setup of the element tiles, node order and halo rows (p1e_tiles.cpp)
-int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn);
+int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn, int node_cap);
+void tile_offsets(p1e_mesh *m, const double *coords);
 void colour_slots(p1e_mesh *m);
 
 // launchers (p1e_kernels.hip). All enqueue on stream and return P1E_OK or a status.
@@ -169,6 +186,7 @@ struct SlotDev {
   double2 *vpart;  // [ntile_v][4] vector-reduction partials
   int32_t ntile_h, ntile_v;
   double C1, D1, p, dirichlet_bv;
+  int32_t ortho;  // p-Laplacian with the component-wise norm
   // L-BFGS vectors, nfd doubles each; S and Y hold kMaxHistory vectors each
   double *v, *g, *d, *vt, *gt, *S, *Y;
 };

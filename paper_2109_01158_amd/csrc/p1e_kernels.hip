@@ -63,7 +63,7 @@ constexpr int tile_waves_per_eu() { return sizeof(T) == 4 ? 2 * tile_threads<T, 
 template <typename T>
 constexpr bool tile_persistent() { return sizeof(T) == 8; }
 
-template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
+template <int DIM, int D, int KIND, typename T, int MODE, int GEO>
 __global__ __launch_bounds__((tile_threads<T, MODE>())) __attribute__((amdgpu_waves_per_eu(tile_waves_per_eu<T, MODE>()))) void k_tile(TileMesh M,
                                                                   const T *__restrict__ geo,
                                                                   const double *__restrict__ vhat,
@@ -71,11 +71,11 @@ __global__ __launch_bounds__((tile_threads<T, MODE>())) __attribute__((amdgpu_wa
                                                                   Params prm) {
   constexpr int NT = tile_threads<T, MODE>();
   using Head = typename TileSplit<DIM, NT>::Head;
-  __shared__ TileShared<DIM, D, T, MODE, CLS> sh;
+  __shared__ TileShared<DIM, D, T, MODE, 1 << GEO> sh;
   if constexpr (!tile_persistent<T>()) {  // one tile per workgroup
     Head h;
     tile_head<TileSplit<DIM, NT>::NPT, NT>(M, xcd_tile(blockIdx.x, gridDim.x), h, threadIdx.x);
-    tile_pass<DIM, D, KIND, T, MODE, CLS, NT>(M, h, geo, vhat, g, nullptr, prm, sh,
+    tile_pass<DIM, D, KIND, T, MODE, GEO, NT>(M, h, geo, vhat, g, nullptr, prm, sh,
                                               threadIdx.x);
     return;
   }
@@ -87,7 +87,7 @@ __global__ __launch_bounds__((tile_threads<T, MODE>())) __attribute__((amdgpu_wa
   tile_head<TileSplit<DIM, NT>::NPT, NT>(M, t, h, threadIdx.x);
   for (;;) {
     const int tn = t + step < end ? t + step : -1;
-    tile_pass<DIM, D, KIND, T, MODE, CLS, NT>(M, h, geo, vhat, g, nullptr, prm, sh,
+    tile_pass<DIM, D, KIND, T, MODE, GEO, NT>(M, h, geo, vhat, g, nullptr, prm, sh,
                                               threadIdx.x, tn, &hn);
     if (tn < 0) break;
     h = hn;
@@ -220,7 +220,9 @@ int check_launch(const char *what) {
   return P1E_OK;
 }
 
-Params params_of(const p1e_mesh *m, double eps) { return Params{m->C1, m->D1, m->p, eps}; }
+Params params_of(const p1e_mesh *m, double eps) {
+  return Params{m->C1, m->D1, m->p, eps, m->ortho};
+}
 
 // Blocks of a persistent grid over n tiles: as many as the device holds at once (occupancy
 // query, once per kernel and device), at most n, rounded up to a multiple of the XCD count.
@@ -243,11 +245,11 @@ int persistent_grid(F kernel, int nt, int64_t n) {
 
 // Every launcher takes the device view Mv of the mesh: m->dev, or a copy whose scratch
 // pointers lead elsewhere (p1e_grad_exact_static).
-template <int DIM, int D, int KIND, typename T, int MODE, bool CLS>
+template <int DIM, int D, int KIND, typename T, int MODE, int GEO>
 void launch_tile_kernel(p1e_mesh *m, const TileMesh &Mv, const T *geo, const double *vhat,
                         double *g, double eps, hipStream_t s) {
   constexpr int NT = tile_threads<T, MODE>();
-  auto kern = k_tile<DIM, D, KIND, T, MODE, CLS>;
+  auto kern = k_tile<DIM, D, KIND, T, MODE, GEO>;
   const int nb = tile_persistent<T>() ? persistent_grid(kern, NT, m->ntiles) : (int)m->ntiles;
   hipLaunchKernelGGL(kern, dim3(nb), dim3(NT), 0, s, Mv, geo, vhat, g, params_of(m, eps));
 }
@@ -261,10 +263,12 @@ int launch_tile(p1e_mesh *m, const TileMesh &Mv, const T *geo, const double *vha
                      : MODE == MODE_FD    ? "k_tile_fd"
                                           : "k_tile_fd4";
   prof_begin(name, s);
-  if (Mv.geo_cls != nullptr)
-    launch_tile_kernel<DIM, D, KIND, T, MODE, true>(m, Mv, geo, vhat, g, eps, s);
+  if (Mv.geo_mode == GEO_CLASS)
+    launch_tile_kernel<DIM, D, KIND, T, MODE, GEO_CLASS>(m, Mv, geo, vhat, g, eps, s);
+  else if (Mv.geo_mode == GEO_OTF)
+    launch_tile_kernel<DIM, D, KIND, T, MODE, GEO_OTF>(m, Mv, geo, vhat, g, eps, s);
   else
-    launch_tile_kernel<DIM, D, KIND, T, MODE, false>(m, Mv, geo, vhat, g, eps, s);
+    launch_tile_kernel<DIM, D, KIND, T, MODE, GEO_STORED>(m, Mv, geo, vhat, g, eps, s);
   prof_end(s);
   return check_launch(name);
 }
@@ -313,31 +317,40 @@ int dispatch(p1e_mesh *m, const double *vhat, const T *geo, double eps, double *
     if (m->dim == 3) return pipeline<3, 3, P1E_SVK, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
     return pipeline<2, 2, P1E_SVK, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
   }
+  if (m->kind == P1E_GINZBURG_LANDAU) {
+    if (m->dim == 3) return pipeline<3, 1, P1E_GINZBURG_LANDAU, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
+    return pipeline<2, 1, P1E_GINZBURG_LANDAU, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
+  }
   if (m->dim == 3) return pipeline<3, 1, P1E_PLAPLACE, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
   return pipeline<2, 1, P1E_PLAPLACE, T, MODE>(m, V, vhat, geo, eps, g, out3, flag, s);
 }
 
 }  // namespace
 
+// the geometry array of a precision: per-element records or class table, or (GEO_OTF) the
+// tile nodes' coordinate offsets
+const float *geo32_of(const TileMesh &M) { return M.geo_mode == GEO_OTF ? M.txo32 : M.geo32; }
+const double *geo64_of(const TileMesh &M) { return M.geo_mode == GEO_OTF ? M.txo64 : M.geo64; }
+
 int run_energy(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
                hipStream_t s) {
   if (prec == P1E_MIXED)
-    return dispatch<float, MODE_ENERGY>(m, vhat, m->dev.geo32, 0.0, nullptr, out3, flag, s);
-  return dispatch<double, MODE_ENERGY>(m, vhat, m->dev.geo64, 0.0, nullptr, out3, flag, s);
+    return dispatch<float, MODE_ENERGY>(m, vhat, geo32_of(m->dev), 0.0, nullptr, out3, flag, s);
+  return dispatch<double, MODE_ENERGY>(m, vhat, geo64_of(m->dev), 0.0, nullptr, out3, flag, s);
 }
 
 int run_grad_exact(p1e_mesh *m, const double *vhat, int prec, double *g, double *out3,
                    int32_t *flag, hipStream_t s) {
   if (prec == P1E_MIXED)
-    return dispatch<float, MODE_FORCE>(m, vhat, m->dev.geo32, 0.0, g, out3, flag, s);
-  return dispatch<double, MODE_FORCE>(m, vhat, m->dev.geo64, 0.0, g, out3, flag, s);
+    return dispatch<float, MODE_FORCE>(m, vhat, geo32_of(m->dev), 0.0, g, out3, flag, s);
+  return dispatch<double, MODE_FORCE>(m, vhat, geo64_of(m->dev), 0.0, g, out3, flag, s);
 }
 
 int run_grad_fd(p1e_mesh *m, const double *vhat, double eps, int order, double *g,
                 int32_t *flag, hipStream_t s) {
   if (order == 4)
-    return dispatch<double, MODE_FD4>(m, vhat, m->dev.geo64, eps, g, nullptr, flag, s);
-  return dispatch<double, MODE_FD>(m, vhat, m->dev.geo64, eps, g, nullptr, flag, s);
+    return dispatch<double, MODE_FD4>(m, vhat, geo64_of(m->dev), eps, g, nullptr, flag, s);
+  return dispatch<double, MODE_FD>(m, vhat, geo64_of(m->dev), eps, g, nullptr, flag, s);
 }
 
 int run_energy_forces(p1e_mesh *m, const double *vhat, int prec, double *out3, int32_t *flag,
@@ -410,14 +423,14 @@ int run_grad_exact_static(p1e_mesh *m, const double *vhat, int prec, double *g, 
   V.badp = (int32_t *)(base + ob);
   V.hpart = (double *)(base + oh);
   if (prec == P1E_MIXED)
-    return dispatch<float, MODE_FORCE>(m, vhat, m->dev.geo32, 0.0, g, out3, flag, s, &V);
-  return dispatch<double, MODE_FORCE>(m, vhat, m->dev.geo64, 0.0, g, out3, flag, s, &V);
+    return dispatch<float, MODE_FORCE>(m, vhat, geo32_of(m->dev), 0.0, g, out3, flag, s, &V);
+  return dispatch<double, MODE_FORCE>(m, vhat, geo64_of(m->dev), 0.0, g, out3, flag, s, &V);
 }
 
 int run_scale_inplace(p1e_mesh *m, const double *scale, double *g, hipStream_t s) {
   if (m->nfd == 0) return P1E_OK;
   prof_begin("k_scale_inplace", s);
-  const int nb = (int)std::min<int64_t>(nblocks((m->nfd + 1) / 2), 512);
+  const int nb = (int)std::min<int64_t>(nblocks((m->nfd + 1) / 2), 1024);
   hipLaunchKernelGGL(k_scale_inplace, dim3(nb), dim3(kBlock), 0, s, (int)m->nfd, scale, g);
   prof_end(s);
   return check_launch("k_scale_inplace");

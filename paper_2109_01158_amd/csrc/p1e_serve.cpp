@@ -166,6 +166,7 @@ struct Engine {
     S.C1 = m->C1;
     S.D1 = m->D1;
     S.p = m->p;
+    S.ortho = m->ortho;
     S.dirichlet_bv = m->dirichlet_bv;
     uint64_t off = 0;
     auto take = [&](uint64_t b) {
@@ -482,7 +483,7 @@ int p1e_server_submit_at(p1e_server *s, const p1e_mesh_desc *d, const double *vh
                          int64_t n0, double t_arrival, int64_t *id) {
   if (!s || !d || !id) return fail(P1E_EINVAL, "null argument");
   if (d->dim != 2 && d->dim != 3) return fail(P1E_EINVAL, "dim must be 2 or 3");
-  if (d->kind != P1E_PLAPLACE && d->kind != P1E_NEOHOOKE)
+  if (d->kind != P1E_PLAPLACE && d->kind != P1E_PLAPLACE_ORTHO && d->kind != P1E_NEOHOOKE)
     return fail(P1E_EINVAL, "the server covers the p-Laplacian and Neo-Hookean kinds");
   if (d->nn < 1 || d->ne < 0 || !d->coords || (d->ne > 0 && !d->conn))
     return fail(P1E_EINVAL, "bad mesh description");

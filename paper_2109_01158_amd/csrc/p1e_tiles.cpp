@@ -96,8 +96,9 @@ static void assign_slots(int nloc, int net, int k, int R, const std::vector<int3
 }
 
 // conn: [k][ne] internal node of each element vertex (internal element order). Uses
-// m->ninfo (internal nodes: first free DOF << 3 | free mask).
-int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
+// m->ninfo (internal nodes: first free DOF << 3 | free mask). A tile touches at most
+// node_cap (<= kTileNodes) nodes.
+int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn, int node_cap) {
   const int k = m->k;
   const int64_t ne = m->ne, nn = m->nn;
   auto is_free = [&](int64_t v) { return (m->ninfo[v] & 7) != 0; };
@@ -112,7 +113,7 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
     while (e < ne && e - e0 < kTileElems) {
       int add = 0;
       for (int l = 0; l < k; ++l) add += mark[conn[(size_t)l * ne + e]] != t;
-      if (nodes + add > kTileNodes) break;
+      if (nodes + add > node_cap) break;
       for (int l = 0; l < k; ++l) {
         const int32_t v = conn[(size_t)l * ne + e];
         if (mark[v] != t) {
@@ -229,6 +230,24 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn) {
   m->slots_coloured = false;
   if (m->tlent.size() >= (size_t(1) << 31)) return fail(P1E_EINVAL, "mesh too large for tiles");
   return P1E_OK;
+}
+
+// GEO_OTF: per tile node (record order) its coordinates minus the centroid of the tile's
+// nodes, FP64 [sum nloc][dim]. Near the centroid the offsets are of the tile's size, so the
+// edge vectors the element pass forms from them lose little even in FP32.
+void tile_offsets(p1e_mesh *m, const double *coords) {
+  const int dim = m->dim;
+  m->txo.assign((size_t)m->ntnodes * dim, 0.0);
+  for (int64_t t = 0; t < m->ntiles; ++t) {
+    const int64_t r0 = m->ttile[4 * t + 1], r1 = m->ttile[4 * (t + 1) + 1];
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int64_t r = r0; r < r1; ++r)
+      for (int j = 0; j < dim; ++j) c[j] += coords[(int64_t)m->trec[4 * r] * dim + j];
+    for (int j = 0; j < dim; ++j) c[j] /= (double)std::max<int64_t>(r1 - r0, 1);
+    for (int64_t r = r0; r < r1; ++r)
+      for (int j = 0; j < dim; ++j)
+        m->txo[(size_t)r * dim + j] = coords[(int64_t)m->trec[4 * r] * dim + j] - c[j];
+  }
 }
 
 // Replace the identity slots of build_tiles by coloured ones (assign_slots) in every tile:

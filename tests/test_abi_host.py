@@ -175,8 +175,39 @@ def test_geometry_classes(p1e):
     P3 = S.plaplace_square(n=17)  # 578 elements, more than 256 possible classes
     X = P3.coords + 1e-3 * np.random.default_rng(0).standard_normal(P3.coords.shape)
     h = p1e.mesh_create(2, "plaplace", P3.conn, X, P3.dirichlet, p=3.0)
-    assert p1e.mesh_get_info(h)["geometry_classes"] == 0
+    info = p1e.mesh_get_info(h)
+    assert info["geometry_classes"] == 0 and info["geometry_mode"] == 2  # formed on the fly
     p1e.mesh_destroy(h)
+    h = p1e.mesh_create(2, "plaplace", P3.conn, X, P3.dirichlet, p=3.0,
+                        flags=p1e.P1E_FULL_GEOMETRY)
+    assert p1e.mesh_get_info(h)["geometry_mode"] == 0  # stored per element
+    p1e.mesh_destroy(h)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_geometry_on_the_fly_tiles(p1e, dim):
+    """A mesh without geometry classes keeps no per-element geometry: its tiles touch at most
+    512 nodes (the coordinate offsets take the other half of the nodal-value slots), and the
+    bound buffer holds one coordinate offset per tile node instead of dim^2 + 1 values per
+    element."""
+    P = (S.neohooke_beam_2d(80, 20, 2.0, 0.5, seed=3, jitter=0.2) if dim == 2 else
+         S.neohooke_box_3d(30, 8, 8, 1.0, 0.27, 0.27, seed=3, jitter=0.2))
+    args = (dim, "neohooke", P.conn, P.coords, P.dirichlet, P.dirichlet_values, P.load)
+    h = p1e.mesh_create(*args, C1=1.0, D1=1.0)
+    hs = p1e.mesh_create(*args, C1=1.0, D1=1.0, flags=p1e.P1E_FULL_GEOMETRY)
+    try:
+        i, js = p1e.mesh_get_info(h), p1e.mesh_get_info(hs)
+        assert i["geometry_mode"] == 2 and js["geometry_mode"] == 0
+        assert i["n_tile_nodes"] <= 512 * i["n_tiles"]
+        assert i["nnz"] == js["nnz"] and i["n_free_dofs"] == js["n_free_dofs"]
+        for mode, w in ((p1e.P1E_MIXED, 4), (p1e.P1E_FP64, 8)):
+            saved = p1e.workspace_bytes(hs, mode) - p1e.workspace_bytes(h, mode)
+            # per-element records out, per-tile-node offsets in (64 KiB for alignment and the
+            # tile tables of the smaller tiles)
+            assert saved >= w * ((dim * dim + 1) * P.ne - dim * i["n_tile_nodes"]) - (64 << 10)
+    finally:
+        p1e.mesh_destroy(h)
+        p1e.mesh_destroy(hs)
 
 
 @pytest.mark.parametrize("rel", [0.0, 1e-15, 3e-14, 1e-13, 3e-13, 1e-12])

@@ -68,6 +68,17 @@ def _cases():
             S.svk_box_3d(13, 7, 5, 1.0, 7 / 13, 5 / 13, seed=17, jitter=0.2), "linear"),
         # p = 1.5 with v = 0 on a sub-region: elements with grad v = 0 (gradient 0 there)
         "plap_p1.5_flat": lambda: _flat(S.plaplace_square(n=31, p=1.5, seed=19)),
+        # Ginzburg-Landau (the scalar example of Section 7): a diffuse interface across a
+        # strip and a slab, u = -1 / +1 prescribed at the two ends; the slab jittered with a
+        # random load
+        # the p-Laplacian with the component-wise norm (the density of Table 6)
+        "plapo_lshape_16": lambda: S.plaplace_lshape(16, p=3.0, seed=22, kind="plaplace_ortho"),
+        "plapo_square_jit_p1.5": lambda: S.plaplace_square(n=27, p=1.5, seed=23, jitter=0.2,
+                                                           kind="plaplace_ortho"),
+        "gl2d_strip_64": lambda: S.gl_domain(dim=2, n=64, width=0.5, eps_gl=0.01, seed=20),
+        "gl3d_slab_jit_randload": lambda: S.with_load(
+            S.gl_domain(dim=3, n=24, width=0.5, eps_gl=0.02, seed=21, jitter=0.2), "random",
+            seed=3, scale=0.5),
     }
 
 
@@ -187,7 +198,7 @@ def test_patch_fd_gradient(P, oracle_mod, name):
 
 
 FD4_CASES = ["plap_p1.5_45", "plap_p5_37", "nh2d_beam_60x13", "nh3d_box_13x7x5",
-             "svk2d_beam_60x13", "svk3d_box_13x7x5"]
+             "svk2d_beam_60x13", "svk3d_box_13x7x5", "gl2d_strip_64", "gl3d_slab_jit_randload"]
 
 
 @pytest.mark.parametrize("name", FD4_CASES)
@@ -211,8 +222,10 @@ def test_fourth_order_patch_fd_gradient(P, oracle_mod, name):
     _note(f"[parity fd4] {name}: worst |g - g_ref| / tol = {np.max(np.abs(g - gref) / tol):.3g}")
     bad = np.flatnonzero(np.abs(g - gref) > tol)
     assert bad.size == 0, (bad[:5], g[bad[:5]], gref[bad[:5]], tol[bad[:5]])
-    if prob.kind != "plaplace":  # (the p-Laplacian differences are rounding-limited here)
-        gex = O.grad_exact(prob.v)
+    gex = O.grad_exact(prob.v)
+    if prob.kind == "gl":  # a quartic in every nodal value: the scheme is exact up to rounding
+        assert _rel2(g, gex) <= 1e-8
+    elif prob.kind != "plaplace":  # (the p-Laplacian differences are rounding-limited here)
         assert _rel2(g, gex) <= _rel2(g2, gex)
 
 
@@ -383,6 +396,37 @@ def test_geometry_classes_match_per_element_geometry(P, name):
     tols = [1e-13, 1e-14, 1e-14, 1e-6, 1e-6, 1e-6, 1e-9]
     for a, b, t in zip(*outs, tols):
         assert np.linalg.norm(a - b) <= t * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name", ["nh3d_box_jit_randload", "nh2d_beam_jit_linload",
+                                  "plap_square_jit_randload", "svk3d_box_jit_linload",
+                                  "gl3d_slab_jit_randload"])
+def test_geometry_on_the_fly_matches_stored_geometry(P, oracle_mod, name):
+    """Jittered meshes have no geometry classes: by default the element pass forms B^-1 and
+    |T| from the vertices' coordinate offsets (FP32 in mixed mode, FP64 otherwise);
+    P1E_FULL_GEOMETRY stores them per element instead. Both against the oracle at the parity
+    bars (FP64 1e-12; mixed 1e-5 energy, 1e-4 gradient), and FP64 against each other."""
+    prob = _get(name)
+    O = oracle_mod.Oracle(prob)
+    ref = O.energy(prob.v)
+    gref = O.grad_exact(prob.v)
+    v = torch.tensor(prob.vhat(), device="cuda")
+    g64 = {}
+    for flags, mode in ((0, 2), (P.P1E_FULL_GEOMETRY, 0)):
+        m = P.Mesh.from_problem(prob, modes=P.P1E_FP64 | P.P1E_MIXED, flags=flags)
+        assert m.info["geometry_mode"] == mode
+        for prec, tj, tg in (("fp64", 1e-12, 1e-12), ("mixed", 1e-5, 1e-4)):
+            g, o, f = m.grad_exact(v, prec)
+            torch.cuda.synchronize()
+            assert int(f.item()) == 0
+            ej = _rel(o[0].item(), ref["J"])
+            eg = _rel2(g.cpu().numpy(), gref)
+            _note(f"[geometry mode {mode}] {name} {prec}: J rel err {ej:.2e}, grad {eg:.2e}")
+            assert ej <= tj and eg <= tg
+            if prec == "fp64":
+                g64[mode] = g.cpu().numpy()
+        m.close()
+    assert _rel2(g64[2], g64[0]) <= 1e-13
 
 
 DELTAS = [-0.999, -0.9, -0.5, -0.3, -0.2929, -0.2928, -0.1, -1e-3, -1e-7, -1e-12, 0.0, 1e-12,
