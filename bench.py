@@ -14,8 +14,9 @@ precision, inputs resident in HBM. Prints ONE JSON line with:
 * oracle_rel_err: the FP64 oracle's error of every timed result (mixed and FP64 J + exact
   gradient on the whole mesh; patch central differences on sampled DOFs);
 * extras: FP64 J + grad J, the patch differences (second and fourth order) on the same mesh,
-  and the mixed J + grad J on the 930x93x93-cube box (48,261,420 tets, a working set far
-  above the 256 MB last-level cache);
+  the mixed J + grad J on the 930x93x93-cube box (48,261,420 tets, a working set far above
+  the 256 MB last-level cache), and on a jittered 6M-tet box with no geometry classes
+  (element geometry formed from the vertex coordinates, and stored per element);
 * cpu_baseline: the oracle (plain C element loops) timed on the host before the GPU is
   touched, on all host cores (one process per contiguous element range) and on one core,
   median of 5;
@@ -59,11 +60,13 @@ def _args():
     return ap.parse_args()
 
 
-def algorithmic_bytes(info, prec, classed):
+def algorithmic_bytes(info, prec):
     """Compulsory HBM bytes of one J + exact grad J call, per kernel (each array touched once).
 
-    k_tile_force: local connectivity 2(dim+1) B and the geometry class 1 B (or B^-1 and |T|,
-    dim^2 + 1 words) per element; local patch entries 2 B per free-node incidence; the tile
+    k_tile_force: local connectivity 2(dim+1) B per element and its geometry (by the mesh's
+    geometry mode: a one-byte class per element; or B^-1 and |T|, dim^2 + 1 words per element;
+    or, formed on the fly, a coordinate offset of dim words per tile node); local patch
+    entries 2 B per free-node incidence; the tile
     node records (node, record, slot: 12 B; row pointer: 2 B) per tile node; per node the
     DOF map 4 B and the subtrahend/prescribed values 8d B; per free DOF vhat and b read and
     g written (rows complete in one tile); per free row its row info 4 B; the halo partial
@@ -76,7 +79,8 @@ def algorithmic_bytes(info, prec, classed):
     dim, d = info["dim"], info["ncomp"]
     w = 4 if prec == "mixed" else 8
     tn, nh, ns = info["n_tile_nodes"], info["n_halo_rows"], info["n_halo_slots"]
-    geo = ne if classed else ne * w * (dim * dim + 1)
+    mode = info["geometry_mode"]
+    geo = ne if mode == 1 else ne * w * (dim * dim + 1) if mode == 0 else tn * w * dim
     complete_dofs = d * (nf - nh)
     tile = (ne * 2 * (dim + 1) + geo + 2 * nnz + 14 * tn + nn * (4 + 8 * d) + 16 * nfd
             + 4 * nf + 8 * complete_dofs + 8 * d * ns)
@@ -274,7 +278,7 @@ def large_timing(P, steps, warmup):
     torch.cuda.synchronize()
     P.prof_enable(False)
     kern = {k: 1e3 * t / c for k, (c, t) in P.prof_collect().items()}
-    ab = algorithmic_bytes(info, "mixed", info["geometry_classes"] > 0)
+    ab = algorithmic_bytes(info, "mixed")
     out = {"workload": "nh3d_box_48M: 930x93x93 cubes x 6 Kuhn tets, mixed J + exact grad J "
                        "through the autograd hook",
            "ne": info["ne"], "elements_per_s": info["ne"] / (ms * 1e-3), "ms": ms,
@@ -283,6 +287,47 @@ def large_timing(P, steps, warmup):
            "bound_buffer_bytes": mesh.nbytes, "setup_s": setup}
     del vhat, mesh
     torch.cuda.empty_cache()
+    return out
+
+
+def geometry_timing(P, steps, warmup):
+    """Mixed J + grad J on the 6M-tet box with interior nodes jittered by up to 0.2 h (every
+    element its own shape: no geometry classes), with B^-1 and |T| formed in the element pass
+    from the vertex coordinates (the default) and stored per element (P1E_FULL_GEOMETRY)."""
+    import torch
+    import p1e_synth as S
+    prob = S.neohooke_box_3d(460, 46, 46, seed=0, jitter=0.2)
+    out = {"workload": "nh3d_box_6M with interior nodes jittered by up to 0.2 h (no geometry "
+                       "classes): mixed J + exact grad J through the autograd hook"}
+    for flags, name in ((0, "on_the_fly"), (P.P1E_FULL_GEOMETRY, "stored_per_element")):
+        mesh = P.Mesh.from_problem(prob, modes=P.P1E_MIXED, flags=flags)
+        info = mesh.info
+        vhat = torch.tensor(prob.vhat(), device="cuda").requires_grad_(True)
+        seed = torch.ones((), dtype=torch.float64, device="cuda")
+
+        def step():
+            vhat.grad = None
+            J = P.p1_energy(vhat, mesh, "mixed")
+            torch.autograd.backward(J, seed)
+
+        for _ in range(warmup):
+            step()
+        ms = time_steps(step, steps)
+        P.prof_reset()
+        P.prof_enable(True)
+        time_steps(step, steps)
+        P.prof_enable(False)
+        kern = {k: 1e3 * t / c for k, (c, t) in P.prof_collect().items()}
+        ab = algorithmic_bytes(info, "mixed")
+        ach = ab["k_tile_force"] / (kern["k_tile_force"] * 1e-6) / 1e9
+        out[name] = {"geometry_mode": info["geometry_mode"], "n_tiles": info["n_tiles"],
+                     "elements_per_s": info["ne"] / (ms * 1e-3), "ms": ms,
+                     "kernels_avg_us": kern, "bound_buffer_bytes": mesh.nbytes,
+                     "k_tile_alg_bytes_per_element": ab["k_tile_force"] / info["ne"],
+                     "k_tile_roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}}
+        del vhat, mesh
+        torch.cuda.empty_cache()
     return out
 
 
@@ -341,7 +386,7 @@ def main():
     P.prof_enable(False)
     kern = P.prof_collect()
 
-    abytes = algorithmic_bytes(info, a.prec, info["geometry_classes"] > 0)
+    abytes = algorithmic_bytes(info, a.prec)
     kstats = {k: {"launches": c, "avg_us": 1e3 * t / c} for k, (c, t) in kern.items()}
     dom = max(kstats, key=lambda k: kstats[k]["avg_us"])
     dom_bytes = abytes.get(dom)
@@ -444,6 +489,8 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_extras and not a.no_large:
         extras["nh3d_box_48M_mixed_jgrad"] = large_timing(P, a.steps, a.warmup)
+    if not a.no_extras:
+        extras["jittered_6M_geometry"] = geometry_timing(P, a.steps, a.warmup)
     if not a.no_serve:
         from paper_2109_01158_amd import serving
         out["serve"] = serving.benchmark(
