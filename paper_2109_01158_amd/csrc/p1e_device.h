@@ -1001,6 +1001,9 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
   }
 }
 
+#ifndef P1E_LDS_ENERGY_SUM
+#define P1E_LDS_ENERGY_SUM 1
+#endif
 // One element tile t of mesh M, by one workgroup of NT threads (kTileElems / NT elements and
 // kTileNodes / NT node records per thread):
 //  0. issue the loads that depend on nothing else: the local connectivity (and classes) of
@@ -1011,9 +1014,10 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
 //  2. element pass of the tile's elements, vertex values read from LDS, element results
 //     written to LDS; energies into (s, c);
 //  3. patch sums of the tile's free nodes from LDS (tile_patch_sums);
-//  4. block sums: per-wavefront plain sums (taken right after the phase that produces the
-//     values), then compensated sums of the wavefront shares: energy -> part[t],
-//     b.v -> part[ntiles + t], bad count.
+//  4. block sums: b.v by per-wavefront plain sums taken right after staging, the energy by
+//     wavefront 0 over the threads' values left in LDS (or per wavefront where they do not
+//     fit), then compensated sums of the shares: energy -> part[t], b.v -> part[ntiles + t],
+//     bad count.
 // Every order is fixed: the results do not depend on timing. No atomics.
 // geo: by GEO, the per-element geometry arrays, the class table (staged in sh.tab) or the
 // tile nodes' coordinate offsets (staged in sh.xs()).
@@ -1196,26 +1200,44 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
   }
   // the next tile's head: in flight while this tile sums its patches
   if (next != nullptr && tnext >= 0) tile_head<NPT, NT>(M, tnext, *next, tid);
+  // The tile's energy: where the nodal-value slots (dead once the elements are done) hold a
+  // double per thread, every thread leaves its element energy there and wavefront 0 adds
+  // them (one column of NW values per lane, then one wavefront sum); otherwise each
+  // wavefront sums its own share. All densities are nonnegative, so the plain FP64 sums are
+  // within (NW + 5) u of the tile's energy; tiles are combined compensated.
+  constexpr bool kLdsEnergy = P1E_LDS_ENERGY_SUM && sizeof(sh.us) >= NT * sizeof(double);
   {
-    const double wj = wave_sum(s + c);  // this wavefront's share of the energy
     const int wn = wave_count(cnt);
-    if (lane == 0) {
-      sh.red[wave] = wj;
-      sh.nbad[wave] = wn;
+    if constexpr (!kLdsEnergy) {
+      const double wj = wave_sum(s + c);  // this wavefront's share of the energy
+      if (lane == 0) sh.red[wave] = wj;
     }
+    if (lane == 0) sh.nbad[wave] = wn;
   }
   // 3. patch sums of the tile's free nodes
-  if constexpr (MODE != MODE_ENERGY) {
+  if constexpr (MODE != MODE_ENERGY || kLdsEnergy) {
     __syncthreads();
-    if (nloc <= NT / 2)
-      tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh, prec, tid);
-    else
-      tile_patch_sums<D, T, NT, 1>(M, r0, nloc, scale, g, sh, prec, tid);
+    if constexpr (kLdsEnergy) reinterpret_cast<double *>(sh.us)[tid] = s + c;
+    if constexpr (MODE != MODE_ENERGY) {
+      if (nloc <= NT / 2)
+        tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh, prec, tid);
+      else
+        tile_patch_sums<D, T, NT, 1>(M, r0, nloc, scale, g, sh, prec, tid);
+    }
   }
   // 4. partials: compensated sums of the per-wavefront shares
   __syncthreads();
   if (wave == 0) {
-    const double2 rj = waves_combine<NW>(sh.red);
+    double2 rj;
+    if constexpr (kLdsEnergy) {
+      const double *E = reinterpret_cast<const double *>(sh.us);
+      double a = E[lane];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) a += E[w * 64 + lane];
+      rj = make_double2(wave_sum(a), 0.0);
+    } else {
+      rj = waves_combine<NW>(sh.red);
+    }
     const double2 rb = waves_combine<NW>(sh.red + NW);
     if (lane == 0) {
       int n = 0;
