@@ -29,6 +29,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "p1e_admission.h"
 #include "p1e_internal.h"
 
 using namespace p1e;
@@ -311,7 +312,7 @@ struct p1e_server {
   Engine eng;
   char *data = nullptr;  // request area of the pool
   uint64_t data_bytes = 0;
-  std::map<uint64_t, uint64_t> free_blocks;  // offset -> length (first fit, coalesced)
+  Admission adm;  // slots and first-fit blocks of the request area
   double t0 = 0.0;
 
   struct Req {
@@ -411,34 +412,6 @@ struct p1e_server {
     }
   }
 
-  bool alloc(uint64_t bytes, uint64_t &off) {
-    for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
-      if (it->second >= bytes) {
-        off = it->first;
-        uint64_t rest = it->second - bytes;
-        uint64_t at = it->first + bytes;
-        free_blocks.erase(it);
-        if (rest) free_blocks[at] = rest;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(uint64_t off, uint64_t bytes) {
-    auto it = free_blocks.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_blocks.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_blocks.erase(nx);
-    }
-    if (it != free_blocks.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_blocks.erase(it);
-      }
-    }
-  }
 };
 
 extern "C" {
@@ -466,7 +439,7 @@ int p1e_server_create(const p1e_server_opts *o, p1e_server **out) {
   if (rc) return rc;
   S->data = (char *)o->pool + tb;
   S->data_bytes = o->pool_bytes - tb;
-  S->free_blocks[0] = S->data_bytes;
+  S->adm.reset(o->max_slots, S->data_bytes);
   S->in_slot.assign(o->max_slots, nullptr);
   S->t0 = now_s();
   const int nt = std::max(1, (int)o->setup_threads);
@@ -554,7 +527,7 @@ int p1e_server_step(p1e_server *s, int32_t *n_active, int32_t *n_waiting) {
       r->info.t_done = now_s() - s->t0;
       rc = E.detach(k);
       if (rc) return rc;
-      s->release(r->off, r->bytes);
+      s->adm.retire(k, r->off, r->bytes);
       p1e_mesh_destroy(r->mesh);
       r->mesh = nullptr;
       s->in_slot[k] = nullptr;
@@ -581,27 +554,20 @@ int p1e_server_step(p1e_server *s, int32_t *n_active, int32_t *n_waiting) {
       continue;
     }
     int k = -1;
-    for (int i = 0; i < E.E.max_slots; ++i)
-      if (!s->in_slot[i]) {
-        k = i;
-        break;
-      }
-    if (k < 0) break;
-    uint64_t off;
-    if (!s->alloc(r->bytes, off)) {
-      if (r->bytes > s->data_bytes) {  // can never fit
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->ready.erase(r->id);
-        r->info.status = P1E_ENOMEM;
-        r->info.t_admit = r->info.t_done = now_s() - s->t0;
-        p1e_mesh_destroy(r->mesh);
-        r->mesh = nullptr;
-        s->finished[r->id] = r;
-        s->unpolled.push_back(r->id);
-        continue;
-      }
-      break;  // wait for memory
+    uint64_t off = 0;
+    const Admit a = s->adm.try_admit(r->id, r->bytes, k, off);
+    if (a == Admit::kNever) {  // larger than the whole request area
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->ready.erase(r->id);
+      r->info.status = P1E_ENOMEM;
+      r->info.t_admit = r->info.t_done = now_s() - s->t0;
+      p1e_mesh_destroy(r->mesh);
+      r->mesh = nullptr;
+      s->finished[r->id] = r;
+      s->unpolled.push_back(r->id);
+      continue;
     }
+    if (a == Admit::kWait) break;  // no slot or no block yet: wait for a retirement
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->ready.erase(r->id);

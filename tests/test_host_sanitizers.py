@@ -1,4 +1,4 @@
-"""The library's host setup under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
+"""The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
 
 tests/host_fuzz/fuzz_mesh.cpp drives p1e_mesh_create / p1e_mesh_get_info /
 p1e_workspace_bytes / p1e_material_constants with random valid and corrupted meshes of every
@@ -39,4 +39,23 @@ def test_mesh_setup_fuzz_under_sanitizers(tmp_path):
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]
     assert "AddressSanitizer" not in out and "runtime error" not in out, out[-4000:]
+    assert "0 failed checks" in out
+
+
+@pytest.mark.timeout(300)
+def test_admission_with_a_fake_executor(tmp_path):
+    """The serving loop's admission bookkeeping (p1e_admission.h, as p1e_server_step uses it)
+    under a fake executor: Poisson arrivals, log-uniform sizes, first-fit pool bytes and slots;
+    invariants at every step, FIFO admission, and (one slot) the latency percentiles of the
+    single-server queue recursion (tests/host_fuzz/sim_admission.cpp)."""
+    if shutil.which("g++") is None:
+        pytest.skip("needs g++")
+    exe = str(tmp_path / "sim_admission")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined", "-I" + CSRC,
+                    os.path.join(HERE, "host_fuzz", "sim_admission.cpp"), "-o", exe],
+                   check=True, capture_output=True, text=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0, out[-4000:]
     assert "0 failed checks" in out
