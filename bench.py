@@ -70,9 +70,9 @@ def algorithmic_bytes(info, prec):
     node records (node, record, slot: 12 B; row pointer: 2 B) per tile node; per node the
     DOF map 4 B and the subtrahend/prescribed values 8d B; per free DOF vhat and b read and
     g written (rows complete in one tile); per free row its row info 4 B; the halo partial
-    sums 8d B per slot written. k_halo: per halo row 8 B of row index and pointer, its row
-    info 4 B, b read and g written (8d B each); per slot its index 4 B and partial 8d B
-    read. k_scale_inplace: the incoming gradient is 1 here, so the kernel reads its 8-byte
+    sums d words per slot written (FP32 in mixed precision). k_halo: per halo row 8 B of row
+    index and pointer, its row info 4 B, b read and g written (8d B each); per slot its index
+    4 B and partial d words read. k_scale_inplace: the incoming gradient is 1 here, so the kernel reads its 8-byte
     scale and writes nothing (with another scale: 16 B per free DOF)."""
     ne, nn, nf, nfd, nnz = (info["ne"], info["nn"], info["n_free_nodes"], info["n_free_dofs"],
                             info["nnz"])
@@ -83,8 +83,8 @@ def algorithmic_bytes(info, prec):
     geo = ne if mode == 1 else ne * w * (dim * dim + 1) if mode == 0 else tn * w * dim
     complete_dofs = d * (nf - nh)
     tile = (ne * 2 * (dim + 1) + geo + 2 * nnz + 14 * tn + nn * (4 + 8 * d) + 16 * nfd
-            + 4 * nf + 8 * complete_dofs + 8 * d * ns)
-    halo = nh * (12 + 16 * d) + ns * (4 + 8 * d)
+            + 4 * nf + 8 * complete_dofs + w * d * ns)
+    halo = nh * (12 + 16 * d) + ns * (4 + w * d)
     return {"k_tile_force": tile, "k_halo": halo, "k_scale_inplace": 0}
 
 

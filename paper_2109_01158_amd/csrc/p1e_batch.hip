@@ -82,8 +82,8 @@ __global__ __launch_bounds__((batch_tile_threads<T>())) void kb_tile(EngineDev E
   }
 }
 
-// halo rows (kBlock per tile) of every evaluating slot of class C
-template <int D, int C>
+// halo rows (kBlock per tile) of every evaluating slot of class C; partials of type T
+template <int D, int C, typename T>
 __global__ __launch_bounds__(kBlock) void kb_halo(EngineDev E) {
   int count;
   const int2 *tl = tiles<TK_HALO, C>(E, count);
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void kb_halo(EngineDev E) {
     if (!evaluating(E, st.x)) continue;
     const SlotDev &S = E.slots[st.x];
     const int h = st.y * kBlock + threadIdx.x;
-    if (h < S.M.nhalo) halo_row<D>(S.M, h, S.gt, nullptr);
+    if (h < S.M.nhalo) halo_row<D, T>(S.M, h, S.gt, nullptr);
   }
 }
 
@@ -480,10 +480,10 @@ int eval_launches(const EngineDev &E, hipStream_t s) {
   hipLaunchKernelGGL((kb_tile<2, 2, P1E_NEOHOOKE, T, CLS_NH2>), dim3(kGridTile), dim3(NT), 0, s, E);
   hipLaunchKernelGGL((kb_tile<3, 3, P1E_NEOHOOKE, T, CLS_NH3>), dim3(kGridTile), dim3(NT), 0, s, E);
   hipLaunchKernelGGL(kb_finalize, dim3(E.max_slots), dim3(kVB), 0, s, E);
-  hipLaunchKernelGGL((kb_halo<1, CLS_PLAP2>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
-  hipLaunchKernelGGL((kb_halo<1, CLS_PLAP3>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
-  hipLaunchKernelGGL((kb_halo<2, CLS_NH2>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
-  hipLaunchKernelGGL((kb_halo<3, CLS_NH3>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_halo<1, CLS_PLAP2, T>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_halo<1, CLS_PLAP3, T>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_halo<2, CLS_NH2, T>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
+  hipLaunchKernelGGL((kb_halo<3, CLS_NH3, T>), dim3(kGridHalo), dim3(kBlock), 0, s, E);
   return P1E_OK;
 }
 

@@ -993,10 +993,10 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
           g[f] = sc * (acc[j] - bj[j]);
           ++f;
         }
-    } else {
-      double *hp = M.hpart + (int64_t)(rec.z >> 2) * D;
+    } else {  // halo partials in the tile's element type (FP32 in mixed precision)
+      T *hp = reinterpret_cast<T *>(M.hpart) + (int64_t)(rec.z >> 2) * D;
 #pragma unroll
-      for (int j = 0; j < D; ++j) hp[j] = acc[j];
+      for (int j = 0; j < D; ++j) hp[j] = (T)acc[j];
     }
   }
 }
@@ -1251,8 +1251,9 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
 }
 
 // Halo row h: a free node whose patch spans several tiles (or none) sums its slots (one per
-// tile, ascending tile order) and writes g = scale * (sum - b).
-template <int D>
+// tile, ascending tile order; partials of type T, summed in FP64) and writes
+// g = scale * (sum - b).
+template <int D, typename T>
 __device__ __forceinline__ void halo_row(const TileMesh &M, int h, double *__restrict__ g,
                                          const double *__restrict__ scale) {
   const int4 hr = M.hrec[h];
@@ -1266,17 +1267,17 @@ __device__ __forceinline__ void halo_row(const TileMesh &M, int h, double *__res
   double acc[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) acc[j] = 0.0;
-  const double *hp = M.hpart + (int64_t)hr.x * D;
+  const T *hp = reinterpret_cast<const T *>(M.hpart) + (int64_t)hr.x * D;
   // slots in rounds of 4 whose loads are issued together; the sum stays sequential in tile
   // order (absent slots load nothing and add zero)
   for (int q = 0; q < hr.y; q += 4) {
-    double x[4][D];
+    T x[4][D];
     bool ok[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       ok[u] = q + u < hr.y;
 #pragma unroll
-      for (int j = 0; j < D; ++j) x[u][j] = 0.0;
+      for (int j = 0; j < D; ++j) x[u][j] = T(0);
       if (ok[u])
 #pragma unroll
         for (int j = 0; j < D; ++j) x[u][j] = hp[(q + u) * D + j];
@@ -1284,7 +1285,7 @@ __device__ __forceinline__ void halo_row(const TileMesh &M, int h, double *__res
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int j = 0; j < D; ++j) acc[j] += ok[u] ? x[u][j] : 0.0;
+      for (int j = 0; j < D; ++j) acc[j] += ok[u] ? (double)x[u][j] : 0.0;
   }
   const double sc = scale ? *scale : 1.0;
   int f = fb;

@@ -76,7 +76,8 @@ struct TileMesh {
                                     // element result in the tile's LDS, per node ascending e
   const int4 *hrec = nullptr;   // [nhalo] halo row records
   // scratch
-  double *hpart = nullptr;   // [slots][d] partial patch sums of halo rows, by row
+  double *hpart = nullptr;   // [slots][d] partial patch sums of halo rows, by row, in the
+                             // tiles' element type (float in mixed precision; sized for double)
   double *gw = nullptr;      // [nfd] gradient kept by p1e_energy_forces
   double2 *part = nullptr;   // [2][max(ntiles,1)] compensated partials: energy, then b.v
   int32_t *badp = nullptr;   // [max(ntiles,1)] bad-element counts

@@ -165,7 +165,8 @@ __global__ __launch_bounds__(kFin) void k_finalize(int nt, const double2 *__rest
 }
 
 // halo rows (blocks 1..) and, in block 0, the finalize: both only read what k_tile wrote
-template <int D>
+// (halo partials of the tiles' element type T)
+template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_halo(TileMesh M, double *__restrict__ g,
                                                  double dirichlet_bv, double *out3,
                                                  int32_t *flag) {
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_halo(TileMesh M, double *__restrict_
     return;
   }
   const int h = (blockIdx.x - 1) * kBlock + threadIdx.x;
-  if (h < M.nhalo) halo_row<D>(M, h, g, nullptr);
+  if (h < M.nhalo) halo_row<D, T>(M, h, g, nullptr);
 }
 
 // two DOFs per thread as one 16-byte access when g is 16-byte aligned (gw always is)
@@ -274,11 +275,11 @@ int launch_tile(p1e_mesh *m, const TileMesh &Mv, const T *geo, const double *vha
 }
 
 // halo rows and finalize (gradient modes)
-template <int D>
+template <int D, typename T>
 int launch_halo(p1e_mesh *m, const TileMesh &Mv, double *g, double *out3, int32_t *flag,
                 hipStream_t s) {
   prof_begin("k_halo", s);
-  hipLaunchKernelGGL((k_halo<D>), dim3(1 + nblocks(m->nhalo)), dim3(kBlock), 0, s, Mv, g,
+  hipLaunchKernelGGL((k_halo<D, T>), dim3(1 + nblocks(m->nhalo)), dim3(kBlock), 0, s, Mv, g,
                      m->dirichlet_bv, out3, flag);
   prof_end(s);
   return check_launch("k_halo");
@@ -301,7 +302,7 @@ int pipeline(p1e_mesh *m, const TileMesh &Mv, const double *vhat, const T *geo, 
              double *g, double *out3, int32_t *flag, hipStream_t s) {
   int rc = launch_tile<DIM, D, KIND, T, MODE>(m, Mv, geo, vhat, g, eps, s);
   if (rc) return rc;
-  if (MODE != MODE_ENERGY) return launch_halo<D>(m, Mv, g, out3, flag, s);
+  if (MODE != MODE_ENERGY) return launch_halo<D, T>(m, Mv, g, out3, flag, s);
   return launch_finalize(m, Mv, out3, flag, s);
 }
 
