@@ -138,9 +138,6 @@ __device__ __forceinline__ double2 waves_combine(const double *v) {
 // The dispatcher hands consecutive workgroups to the 8 XCDs in turn, and each XCD has its
 // own L2. Renumber blocks so that every XCD works on one contiguous range of tiles: tiles
 // that share nodes or elements then share an L2. Bijective on [0, nb).
-#ifndef P1E_XCD_COUNT
-#define P1E_XCD_COUNT 8
-#endif
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   constexpr int X = P1E_XCD_COUNT;
   const int q = nb / X, r = nb % X;
@@ -898,8 +895,9 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
   }
 }
 
-// LDS of one element tile: the staged nodal values, the element results (vertex-major,
-// [dim+1][kTileElems][D]), the tile's local patch entries and the geometry class table.
+// LDS of one element tile: the element results (vertex-major, [dim+1][kTileElems][D]; first,
+// so that a patch entry's byte offset is its LDS address), the staged nodal values, the
+// tile's local patch entries and the geometry class table.
 // 16-byte aligned: nodal values and patch entries move as 16-byte vectors.
 // GSET: the geometry modes (bits 1 << GEO) the workgroup may meet. With GEO_OTF tiles (at
 // most kTileNodes / 2 nodes) the first half of us holds the nodal values and the second half
@@ -911,14 +909,20 @@ struct alignas(16) TileShared {
   static constexpr bool CLS = (GSET >> GEO_CLASS) & 1, OTF = (GSET >> GEO_OTF) & 1;
   static constexpr int NSU = OTF && NSX > NS ? NSX : NS;
   static constexpr int NENT = (K * kTileElems + kEntAlign - 1) / kEntAlign * kEntAlign;
-  T us[kTileNodes * NSU];
   T fs[MODE == MODE_ENERGY ? 4 : K * kTileElems * D + 4];  // + a zero record at the end
+  T us[kTileNodes * NSU];
   uint16_t lent[MODE == MODE_ENERGY ? kEntAlign : NENT + kEntAlign];  // + slack read past rows
   T tab[CLS ? kMaxGeoClasses * REC : 4];
   double red[2 * 16];  // per-wavefront shares: energy, then b.v
   int nbad[16];
   __device__ T *xs() { return us + (kTileNodes / 2) * NSU; }
 };
+
+// byte offset of a patch entry's element result: entries hold the offset for FP32 results
+template <typename T>
+__device__ __forceinline__ int ent_bytes(int raw) {
+  return sizeof(T) == 4 ? raw : 2 * raw;
+}
 
 // Patch sums of a tile's free nodes (Section 4.2 patch restricted to the tile), GL lanes per
 // node: the lanes of a node take every GL-th entry of its local patch row (ascending element,
@@ -954,19 +958,24 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
 #pragma unroll
     for (int j = 0; j < D; ++j) acc[j] = 0.0;
     const int p0 = rec.w & 0xffff, n = rec.w >> 16;
-    constexpr int kZero = (DIM_OF_SH<SH>::K) * kTileElems * D;  // the zero record
+    // entries are byte offsets into an FP32 fs (offset 0 of the LDS); FP64 results are twice
+    // as far
+    const char *fsb = reinterpret_cast<const char *>(sh.fs);
+    const uint16_t *le = sh.lent + p0;
+    constexpr int kZeroB = (DIM_OF_SH<SH>::K) * kTileElems * D * (int)sizeof(T);  // zero record
     for (int p = sub; p < n; p += 4 * GL) {
-      int x[4];
+      int xb[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {  // read unconditionally (at most 3 GL past the row's end)
-        const int raw = sh.lent[p0 + p + u * GL];
-        x[u] = p + u * GL < n ? raw : kZero;
+        const int raw = le[p + u * GL];
+        xb[u] = p + u * GL < n ? ent_bytes<T>(raw) : kZeroB;
       }
       T q[4][D];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int j = 0; j < D; ++j) q[u][j] = sh.fs[x[u] + j];
+        for (int j = 0; j < D; ++j)
+          q[u][j] = *reinterpret_cast<const T *>(fsb + xb[u] + j * (int)sizeof(T));
       if constexpr (std::is_same<T, float>::value) {
         // (mixed) the round's four forces summed in float, the rounds in double
 #pragma unroll

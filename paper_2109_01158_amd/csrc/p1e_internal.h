@@ -20,10 +20,15 @@ namespace p1e {
 #ifndef P1E_TILE_ELEMS
 #define P1E_TILE_ELEMS 1024
 #endif
+// XCDs of the device: each has its own L2, and the dispatcher hands consecutive workgroups
+// to them in turn
+#ifndef P1E_XCD_COUNT
+#define P1E_XCD_COUNT 8
+#endif
 constexpr int kTileElems = P1E_TILE_ELEMS;  // elements per tile (at most)
 constexpr int kTileNodes = P1E_TILE_ELEMS;  // distinct nodes per tile (at most)
 constexpr int kEntAlign = 8;       // each tile's patch entries start on a 16-byte boundary
-static_assert((4 * kTileElems) * 3 < 65536, "patch entry offsets fit 16 bits");
+static_assert((4 * kTileElems) * 3 * 4 <= 65536, "patch entry byte offsets fit 16 bits");
 constexpr int kBlock = 256;        // threads per block of the halo-row and vector kernels
 constexpr uint64_t kAlign = 256;   // alignment of every sub-array in the bound buffer
 constexpr int kMaxGeoClasses = 64; // geometry classes kept as one-byte indices
@@ -72,8 +77,9 @@ struct TileMesh {
                                 //  entry, 0}; the last one closes the ranges
   const int4 *trec = nullptr;   // [sum nloc] tile node records
   const uint16_t *tslot = nullptr;  // [sum nloc] LDS slot of each tile node's nodal value
-  const uint16_t *tlent = nullptr;  // local patch entries: offset (l kTileElems + e) d of the
-                                    // element result in the tile's LDS, per node ascending e
+  const uint16_t *tlent = nullptr;  // local patch entries: byte offset (l kTileElems + e) d 4
+                                    // of the element's FP32 result in the tile's LDS (twice
+                                    // that for FP64 results), per node ascending e
   const int4 *hrec = nullptr;   // [nhalo] halo row records
   // scratch
   double *hpart = nullptr;   // [slots][d] partial patch sums of halo rows, by row, in the

@@ -181,14 +181,27 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn, int node_cap) {
       }
     std::sort(nodes.begin(), nodes.end());
     const int nloc = (int)nodes.size();
+    // Record order: free nodes by descending number of patch-sum rounds (rounds of 8 entries,
+    // two lanes per node), then the nodes without a free DOF; ascending node within each
+    // group. A wavefront's patch sums take as many rounds as its longest row, so grouping
+    // rows of equal length saves rounds, and the ascending runs keep the nodal loads and the
+    // gradient stores contiguous.
     for (int a = 0; a < nloc; ++a) loc[nodes[a]] = a;
     cnt.assign(nloc, 0);
     for (int64_t e = e0; e < e1; ++e)
-      for (int l = 0; l < k; ++l) {
-        const int a = loc[conn[(size_t)l * ne + e]];
-        m->conn_loc[(size_t)l * ne + e] = (uint16_t)a;  // slot = local index until coloured
-        cnt[a] += 1;
-      }
+      for (int l = 0; l < k; ++l) cnt[loc[conn[(size_t)l * ne + e]]] += 1;
+    {
+      auto key = [&](int32_t v) { return is_free(v) ? -((cnt[loc[v]] + 7) / 8) : 1; };
+      std::stable_sort(nodes.begin(), nodes.end(),
+                       [&](int32_t x, int32_t y) { return key(x) < key(y); });
+      std::vector<int32_t> c2(nloc);
+      for (int a = 0; a < nloc; ++a) c2[a] = cnt[loc[nodes[a]]];
+      cnt.swap(c2);
+    }
+    for (int a = 0; a < nloc; ++a) loc[nodes[a]] = a;
+    for (int64_t e = e0; e < e1; ++e)
+      for (int l = 0; l < k; ++l)  // slot = local index until coloured
+        m->conn_loc[(size_t)l * ne + e] = (uint16_t)loc[conn[(size_t)l * ne + e]];
     // local patch rows of the tile's free nodes, entries in ascending element
     const int64_t ent0 = (int64_t)m->tlent.size();
     m->ttile.insert(m->ttile.end(),
@@ -204,8 +217,8 @@ int build_tiles(p1e_mesh *m, const std::vector<int32_t> &conn, int node_cap) {
     for (int64_t e = e0; e < e1; ++e)
       for (int l = 0; l < k; ++l) {
         const int a = loc[conn[(size_t)l * ne + e]];
-        if (is_free(nodes[a]))  // LDS offset of the entry's result: (l kTileElems + e) d
-          m->tlent[ent0 + fill[a]++] = (uint16_t)((l * kTileElems + (e - e0)) * m->d);
+        if (is_free(nodes[a]))  // byte offset of the entry's FP32 result, (l kTileElems + e) d 4
+          m->tlent[ent0 + fill[a]++] = (uint16_t)((l * kTileElems + (e - e0)) * m->d * 4);
       }
     for (int a = 0; a < nloc; ++a) {
       const int32_t v = nodes[a];
