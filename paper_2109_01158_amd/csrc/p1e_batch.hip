@@ -69,7 +69,7 @@ __global__ __launch_bounds__((batch_tile_threads<T>())) void kb_tile(EngineDev E
                                   : (const T *)(otf ? (const void *)S.M.txo64 : S.M.geo64);
     using Split = TileSplit<DIM, NT>;
     typename Split::Head h;
-    tile_head<Split::NPT, NT>(S.M, st.y, h, threadIdx.x);
+    tile_head<Split::NPT, NT, true>(S.M, st.y, h, threadIdx.x);
     if (S.M.geo_mode == GEO_CLASS)
       tile_pass<DIM, D, KIND, T, MODE_FORCE, GEO_CLASS, NT>(S.M, h, geo, S.vt, S.gt, nullptr,
                                                             prm, sh, threadIdx.x);

@@ -939,20 +939,26 @@ template <int D, typename T, int NT, int GL, class SH>
 __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int nloc,
                                                 const double *__restrict__ scale,
                                                 double *__restrict__ g, SH &sh, int4 rec0,
-                                                int tid) {
+                                                const double (&b0)[D], int tid) {
   static_assert(3 * GL <= kEntAlign, "reads past a row stay within the entry slack");
   const int sub = tid % GL;
   for (int a = tid / GL; a < nloc; a += NT / GL) {
-    const int4 rec = a < NT / GL ? rec0 : M.trec[r0 + a];  // rec0: loaded by the caller
+    const bool first = a < NT / GL;
+    const int4 rec = first ? rec0 : M.trec[r0 + a];  // rec0 and b0: loaded by the caller
     if (rec.w == 0) continue;  // no free DOF (uniform over the node's lanes)
     const int mask = rec.y & 7, fb = rec.y >> 3;
     const bool complete = rec.z & 1;
     double bj[D];  // b of a complete node's free DOFs, loaded ahead of the sums
+    if (first) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      bj[j] = 0.0;
-      if (complete && sub == 0 && ((mask >> j) & 1))
-        bj[j] = M.bhat[fb + __popc(mask & ((1 << j) - 1))];
+      for (int j = 0; j < D; ++j) bj[j] = b0[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        bj[j] = 0.0;
+        if (complete && sub == 0 && ((mask >> j) & 1))
+          bj[j] = M.bhat[fb + __popc(mask & ((1 << j) - 1))];
+      }
     }
     double acc[D];
 #pragma unroll
@@ -1039,10 +1045,18 @@ struct TileHead {
   int4 ta, tb;  // ttile[t], ttile[t + 1]
   int4 rec[NPT];
   int slot[NPT];  // LDS slot of the node's nodal value (tslot)
+  int4 prec;      // (gradient modes) the record of the lane's first patch-sum node
 };
 
+// The lane's first node of the patch-sum phase: node tid / 2 (two lanes per node) when the
+// tile has at most NT / 2 nodes, else node tid.
+template <int NT>
+__device__ __forceinline__ int patch_node(int tid, int nloc) {
+  return nloc <= NT / 2 ? tid / 2 : tid;
+}
+
 // records past the tile's nodes are zero
-template <int NPT, int NT>
+template <int NPT, int NT, bool PATCH>
 __device__ __forceinline__ void tile_head(const TileMesh &M, int t, TileHead<NPT> &h, int tid) {
   h.t = t;
   h.ta = M.ttile[t];
@@ -1053,6 +1067,11 @@ __device__ __forceinline__ void tile_head(const TileMesh &M, int t, TileHead<NPT
     const int a = k * NT + tid;
     h.rec[k] = a < nloc ? M.trec[r0 + a] : make_int4(0, 0, 0, 0);
     h.slot[k] = a < nloc ? (int)stream_load(M.tslot + r0 + a) : 0;  // read once
+  }
+  h.prec = make_int4(0, 0, 0, 0);
+  if constexpr (PATCH) {
+    const int a = patch_node<NT>(tid, nloc);
+    if (a < nloc) h.prec = M.trec[r0 + a];
   }
 }
 
@@ -1107,8 +1126,20 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
   }
   // 1. nodal field of the tile; b.v of the nodes this tile owns (only the owner reads b).
   // Per node all loads first (one memory round trip), then the arithmetic; component j's DOF
-  // is the node's first free DOF plus the free components before j.
+  // is the node's first free DOF plus the free components before j. In the same round trip,
+  // b of the lane's first patch-sum node when the lane writes that node's complete row.
   double sb = 0.0, cb = 0.0;
+  double pb[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) pb[j] = 0.0;
+  if constexpr (MODE != MODE_ENERGY) {
+    const int4 pr = h.prec;
+    const int mask = pr.y & 7, fb = pr.y >> 3;
+    if ((pr.z & 1) && (nloc > NT / 2 || (tid & 1) == 0))
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if ((mask >> j) & 1) pb[j] = M.bhat[fb + __popc(mask & ((1 << j) - 1))];
+  }
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int a = k * NT + tid;
@@ -1180,12 +1211,6 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
     if (lane == 0) sh.red[NW + wave] = wb;
   }
   __syncthreads();
-  // the first node record of the patch-sum phase, loaded ahead of the element pass
-  int4 prec = make_int4(0, 0, 0, 0);
-  if constexpr (MODE != MODE_ENERGY) {
-    const int a = nloc <= NT / 2 ? tid / 2 : tid;
-    if (a < nloc) prec = M.trec[r0 + a];
-  }
   // 2. elements
   double s = 0.0, c = 0.0;
   int cnt = 0;
@@ -1208,7 +1233,8 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
     }
   }
   // the next tile's head: in flight while this tile sums its patches
-  if (next != nullptr && tnext >= 0) tile_head<NPT, NT>(M, tnext, *next, tid);
+  if (next != nullptr && tnext >= 0)
+    tile_head<NPT, NT, MODE != MODE_ENERGY>(M, tnext, *next, tid);
   // The tile's energy: where the nodal-value slots (dead once the elements are done) hold a
   // double per thread, every thread leaves its element energy there and wavefront 0 adds
   // them (one column of NW values per lane, then one wavefront sum); otherwise each
@@ -1229,9 +1255,9 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
     if constexpr (kLdsEnergy) reinterpret_cast<double *>(sh.us)[tid] = s + c;
     if constexpr (MODE != MODE_ENERGY) {
       if (nloc <= NT / 2)
-        tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh, prec, tid);
+        tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh, h.prec, pb, tid);
       else
-        tile_patch_sums<D, T, NT, 1>(M, r0, nloc, scale, g, sh, prec, tid);
+        tile_patch_sums<D, T, NT, 1>(M, r0, nloc, scale, g, sh, h.prec, pb, tid);
     }
   }
   // 4. partials: compensated sums of the per-wavefront shares

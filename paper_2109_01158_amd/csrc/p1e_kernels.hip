@@ -74,7 +74,8 @@ __global__ __launch_bounds__((tile_threads<T, MODE>())) __attribute__((amdgpu_wa
   __shared__ TileShared<DIM, D, T, MODE, 1 << GEO> sh;
   if constexpr (!tile_persistent<T>()) {  // one tile per workgroup
     Head h;
-    tile_head<TileSplit<DIM, NT>::NPT, NT>(M, xcd_tile(blockIdx.x, gridDim.x), h, threadIdx.x);
+    tile_head<TileSplit<DIM, NT>::NPT, NT, MODE != MODE_ENERGY>(
+        M, xcd_tile(blockIdx.x, gridDim.x), h, threadIdx.x);
     tile_pass<DIM, D, KIND, T, MODE, GEO, NT>(M, h, geo, vhat, g, nullptr, prm, sh,
                                               threadIdx.x);
     return;
@@ -84,7 +85,7 @@ __global__ __launch_bounds__((tile_threads<T, MODE>())) __attribute__((amdgpu_wa
   if (t >= end) return;
   // persistent: each tile loads the next one's head while it sums its patches
   Head h, hn;
-  tile_head<TileSplit<DIM, NT>::NPT, NT>(M, t, h, threadIdx.x);
+  tile_head<TileSplit<DIM, NT>::NPT, NT, MODE != MODE_ENERGY>(M, t, h, threadIdx.x);
   for (;;) {
     const int tn = t + step < end ? t + step : -1;
     tile_pass<DIM, D, KIND, T, MODE, GEO, NT>(M, h, geo, vhat, g, nullptr, prm, sh,
