@@ -276,19 +276,19 @@ __device__ __forceinline__ double log_excess(double d) {
 }
 
 // log((1 + y) / (1 - y)) = 2 atanh y for |y| < 1: the log of the det F ratio of a difference
-// step. When every lane of the wavefront has |y| < 1/64, by the odd series
-// 2 (y + y^3/3 + ... + y^9/9) (the omitted terms are below 1e-19 of the sum), without
-// division; otherwise as x - log_excess(x) = log1p(x) with x = 2y / (1 - y). The branch is
-// uniform over the wavefront.
-__device__ __forceinline__ double log_ratio_step(double y) {
-  if (__all(fabs(y) < 0.015625)) {
-    const double w = y * y;
-    double t = scalar_const(1.0 / 9.0);
+// step. For |y| < 1/64 by the odd series 2 (y + y^3/3 + ... + y^9/9) (the omitted terms are
+// below 1e-19 of the sum), without division; otherwise as x - log_excess(x) = log1p(x) with
+// x = 2y / (1 - y). The caller picks one form for a whole wavefront (a uniform branch).
+constexpr double kSeriesBound = 0.015625;
+__device__ __forceinline__ double log_ratio_series(double y) {
+  const double w = y * y;
+  double t = scalar_const(1.0 / 9.0);
 #pragma unroll
-    for (int i = 7; i >= 3; i -= 2) t = fma(t, w, scalar_const(1.0 / i));
-    t = fma(t, w, 1.0);
-    return 2.0 * y * t;
-  }
+  for (int i = 7; i >= 3; i -= 2) t = fma(t, w, scalar_const(1.0 / i));
+  t = fma(t, w, 1.0);
+  return 2.0 * y * t;
+}
+__device__ __forceinline__ double log_ratio_general(double y) {
   const double x = quotient(2.0 * y, 1.0 - y);
   return x - log_excess(x);
 }
@@ -790,6 +790,7 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
           cf[j][m] = DIM == 3 ? t + nv.cg[j][m] : t;
         }
     }
+    double yv[KIND == P1E_NEOHOOKE ? K * D : 1], av[KIND == P1E_NEOHOOKE ? K * D : 1];
 #pragma unroll
     for (int l = 0; l < K; ++l) {
       T a[DIM];
@@ -808,9 +809,10 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
         // F -> F +- h e_j a^T changes det F by +- h c with c = (cof F)_j . a (det F is
         // linear in each row) and |F|^2 by +- 2 h F_j . a + h^2 |a|^2, so
         //   W+ - W- = C1 (4 h F_j . a - 2 log(det F+ / det F-)) + 4 D1 h c (det F - 1),
-        // with det F+ / det F- = (1 + y) / (1 - y), y = h c / det F (log_ratio_step): the
-        // same difference as two density evaluations, without their cancellation, with one
-        // logarithm instead of two and one division per element.
+        // with det F+ / det F- = (1 + y) / (1 - y), y = h c / det F: the same difference
+        // as two density evaluations, without their cancellation, with one logarithm instead
+        // of two and one division per element. Here the log-free part A and y at h = eps;
+        // the logarithms follow for all the element's DOFs at once.
 #pragma unroll
         for (int j = 0; j < D; ++j) {
           double c = 0.0, fa = (double)a[j];
@@ -819,19 +821,8 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
             c = fma((double)cf[j][m], (double)a[m], c);
             fa = fma((double)G[j][m], (double)a[m], fa);
           }
-          double dW[2];  // W(+h) - W(-h) for h = eps and (fourth order) 2 eps
-#pragma unroll
-          for (int u = 0; u < (MODE == MODE_FD4 ? 2 : 1); ++u) {
-            const double h = u == 0 ? eps : 2.0 * eps;
-            const double y = h * c * rdet;
-            const bool ok = rdet > 0.0 && fabs(y) < 1.0;  // det F+ > 0 and det F- > 0
-            if (!ok) bad = true;
-            const double lg = log_ratio_step(ok ? y : 0.0);
-            dW[u] = prm.C1 * (4.0 * h * fa - 2.0 * lg) + 4.0 * prm.D1 * h * c * delta;
-          }
-          const double q = (double)vol * scheme(dW[0], MODE == MODE_FD4 ? dW[1] : 0.0);
-          if (!isfinite(q)) bad = true;
-          out[l * D + j] = (T)q;
+          yv[l * D + j] = eps * c * rdet;
+          av[l * D + j] = prm.C1 * (4.0 * eps * fa) + 4.0 * prm.D1 * eps * c * delta;
         }
         continue;
       }
@@ -875,6 +866,37 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
         const double d1 = dW(eps), d2 = MODE == MODE_FD4 ? dW(2.0 * eps) : 0.0;
         out[l * D + j] = (T)((double)vol * scheme(d1, d2));
       }
+    }
+    if constexpr (KIND == P1E_NEOHOOKE) {
+      // W+ - W- = A - 2 C1 log((1 + y) / (1 - y)) at h = eps, and (fourth order) 2A and 2y
+      // at h = 2 eps; both det F+ and det F- must be positive (|y| < 1 at the largest step).
+      // One uniform choice of the logarithm's form for every DOF of the wavefront's elements.
+      constexpr double ymul = MODE == MODE_FD4 ? 2.0 : 1.0;
+      bool small = true;
+#pragma unroll
+      for (int n = 0; n < K * D; ++n) {
+        const bool ok = rdet > 0.0 && fabs(ymul * yv[n]) < 1.0;
+        if (!ok) {
+          bad = true;
+          yv[n] = 0.0;
+        }
+        small = small && fabs(ymul * yv[n]) < kSeriesBound;
+      }
+      auto finish = [&](auto lratio) {
+#pragma unroll
+        for (int n = 0; n < K * D; ++n) {
+          const double d1 = av[n] - 2.0 * prm.C1 * lratio(yv[n]);
+          const double d2 =
+              MODE == MODE_FD4 ? 2.0 * av[n] - 2.0 * prm.C1 * lratio(2.0 * yv[n]) : 0.0;
+          const double q = (double)vol * scheme(d1, d2);
+          if (!isfinite(q)) bad = true;
+          out[n] = (T)q;
+        }
+      };
+      if (__all(small))
+        finish([](double y) { return log_ratio_series(y); });
+      else
+        finish([](double y) { return log_ratio_general(y); });
     }
     store_entries<T, D, K>(r, nep, er, out);
   }
