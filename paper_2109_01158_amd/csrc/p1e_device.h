@@ -790,6 +790,10 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
           cf[j][m] = DIM == 3 ? t + nv.cg[j][m] : t;
         }
     }
+    // (Neo-Hookean) y = c eps / det F, and the log-free part of the result, 2 |T| C1 F_j . a
+    // + 2 |T| D1 (det F - 1) c, for every DOF of the element
+    const double ky = eps * rdet, ka = 2.0 * (double)vol * prm.C1,
+                 kc = 2.0 * (double)vol * prm.D1 * delta;
     double yv[KIND == P1E_NEOHOOKE ? K * D : 1], av[KIND == P1E_NEOHOOKE ? K * D : 1];
 #pragma unroll
     for (int l = 0; l < K; ++l) {
@@ -811,8 +815,9 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
         //   W+ - W- = C1 (4 h F_j . a - 2 log(det F+ / det F-)) + 4 D1 h c (det F - 1),
         // with det F+ / det F- = (1 + y) / (1 - y), y = h c / det F: the same difference
         // as two density evaluations, without their cancellation, with one logarithm instead
-        // of two and one division per element. Here the log-free part A and y at h = eps;
-        // the logarithms follow for all the element's DOFs at once.
+        // of two and one division per element. Here y at h = eps and the log-free part of
+        // the scheme's result, |T| (4 eps C1 F_j . a + 4 eps D1 c (det F - 1)) / (2 eps); the
+        // logarithms follow for all the element's DOFs at once.
 #pragma unroll
         for (int j = 0; j < D; ++j) {
           double c = 0.0, fa = (double)a[j];
@@ -821,8 +826,8 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
             c = fma((double)cf[j][m], (double)a[m], c);
             fa = fma((double)G[j][m], (double)a[m], fa);
           }
-          yv[l * D + j] = eps * c * rdet;
-          av[l * D + j] = prm.C1 * (4.0 * eps * fa) + 4.0 * prm.D1 * eps * c * delta;
+          yv[l * D + j] = c * ky;
+          av[l * D + j] = fma(ka, fa, kc * c);
         }
         continue;
       }
@@ -868,27 +873,30 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
       }
     }
     if constexpr (KIND == P1E_NEOHOOKE) {
-      // W+ - W- = A - 2 C1 log((1 + y) / (1 - y)) at h = eps, and (fourth order) 2A and 2y
-      // at h = 2 eps; both det F+ and det F- must be positive (|y| < 1 at the largest step).
-      // One uniform choice of the logarithm's form for every DOF of the wavefront's elements.
-      constexpr double ymul = MODE == MODE_FD4 ? 2.0 : 1.0;
+      // |T| (W+ - W-) = |T| (A - 2 C1 L(y)) at h = eps (A the log-free part, L(y) =
+      // log((1 + y) / (1 - y))) and |T| (2A - 2 C1 L(2y)) at h = 2 eps, so the second-order
+      // result is av - (|T| C1 / eps) L(y) and the fourth-order one
+      // av - (|T| C1 / (6 eps)) (8 L(y) - L(2y)). Both det F+ and det F- must be positive
+      // (|y| < 1 at the largest step). One uniform choice of the logarithm's form for every
+      // DOF of the wavefront's elements.
+      constexpr double ymax = MODE == MODE_FD4 ? 0.5 : 1.0;
       bool small = true;
 #pragma unroll
       for (int n = 0; n < K * D; ++n) {
-        const bool ok = rdet > 0.0 && fabs(ymul * yv[n]) < 1.0;
+        const bool ok = rdet > 0.0 && fabs(yv[n]) < ymax;
         if (!ok) {
           bad = true;
           yv[n] = 0.0;
         }
-        small = small && fabs(ymul * yv[n]) < kSeriesBound;
+        small = small && fabs(yv[n]) < ymax * kSeriesBound;
       }
+      const double kl = (double)vol * prm.C1 / (MODE == MODE_FD4 ? 6.0 * eps : eps);
       auto finish = [&](auto lratio) {
 #pragma unroll
         for (int n = 0; n < K * D; ++n) {
-          const double d1 = av[n] - 2.0 * prm.C1 * lratio(yv[n]);
-          const double d2 =
-              MODE == MODE_FD4 ? 2.0 * av[n] - 2.0 * prm.C1 * lratio(2.0 * yv[n]) : 0.0;
-          const double q = (double)vol * scheme(d1, d2);
+          const double lg = MODE == MODE_FD4 ? fma(8.0, lratio(yv[n]), -lratio(2.0 * yv[n]))
+                                             : lratio(yv[n]);
+          const double q = fma(-kl, lg, av[n]);
           if (!isfinite(q)) bad = true;
           out[n] = (T)q;
         }
