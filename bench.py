@@ -6,8 +6,10 @@ halo rows, compensated finalize; the backward scales the forward's gradient buff
 which writes nothing for dJ/dJ = 1) on the 460x46x46-cube Kuhn box (5,840,160 tets), mixed
 precision, inputs resident in HBM. Prints ONE JSON line with:
 
-* value / ms_per_step: K steps bracketed by device synchronisations (wall clock), and the
-  median step from HIP events around each step of a second pass;
+* value / ms_per_step: K steps bracketed by device synchronisations (wall clock), after W
+  untimed steps (the default W = 500, about 60 ms of work, brings the GPU out of the idle
+  clock state the host-side oracle timing leaves it in), and the median step from HIP events
+  around each step of a second pass;
 * roofline: the dominant kernel against the HBM roofline (HIP events around each kernel over
   a third pass), with the counter-measured traffic and VALU-issue fraction when a profile of
   the current kernel sources is committed;
@@ -23,7 +25,7 @@ precision, inputs resident in HBM. Prints ONE JSON line with:
 * serve: the serving benchmark (256 minimization requests, Poisson arrivals, continuous
   batching vs one-at-a-time FP64 solves: req/s, p50/p99 latency, with and without mesh setup).
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline] [--no-serve]
+Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 500] [--no-cpu-baseline] [--no-serve]
 """
 
 import argparse
@@ -42,8 +44,8 @@ MAX_CPU_WORKERS = 16   # host share of one GPU
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--config", default="nh3d_box_6M")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
