@@ -159,7 +159,9 @@ typedef struct p1e_mesh_info {
 /* Build a mesh handle: validates the description, computes element geometry (|T| and basis
  * gradients, Section 4.1), the free-node patch lists (Section 4.2, split by element tiles
  * into rows of (element, local vertex) pairs), the DOF maps and b = M f (Section 3.2).
- * Host-only; needs no GPU. Returns P1E_EINVAL or P1E_EDEGEN on bad input. */
+ * Host-only; needs no GPU. Returns P1E_EINVAL or P1E_EDEGEN on bad input, and P1E_EINVAL for
+ * a mesh beyond the library's limits: fewer than 2^28 free DOFs, and every per-node, per-DOF
+ * and per-halo-slot array of the bound buffer below 4 GiB. */
 int p1e_mesh_create(const p1e_mesh_desc *desc, p1e_mesh **out);
 
 /* Release the handle (host memory only; the bound device buffer belongs to the caller). */

@@ -442,6 +442,15 @@ int build_mesh(const p1e_mesh_desc *D, p1e_mesh *m) {
   // ---- element tiles, local patch rows and halo rows (Section 4.2 patches)
   int rc = build_tiles(m, conn, m->geo_mode == GEO_OTF ? kTileNodes / 2 : kTileNodes);
   if (rc != P1E_OK) return rc;
+  // the tile kernels index their arrays through 32-bit byte offsets: each below 4 GiB
+  {
+    const uint64_t big = std::max<uint64_t>(
+        {8ull * (uint64_t)nn * d, 8ull * (uint64_t)nfd, 16ull * (uint64_t)m->ntnodes,
+         8ull * (uint64_t)m->ntnodes * dim, 2ull * (uint64_t)ne, 8ull * (uint64_t)m->nslots * d});
+    if (big >= (1ull << 32))
+      return fail(P1E_EINVAL, "mesh too large: a per-node, per-DOF or per-slot array would "
+                              "exceed 4 GiB");
+  }
   std::vector<int32_t>().swap(conn);
   if (m->geo_mode == GEO_OTF) tile_offsets(m, D->coords);
 

@@ -41,6 +41,20 @@ __device__ __forceinline__ T stream_load(const T *p) {
 #endif
 }
 
+// Element i of an array through a 32-bit byte offset: the access then takes the array's base
+// as a scalar register pair and the offset as one vector register, instead of forming a
+// 64-bit address per lane. Every array the tile kernels index this way is below 4 GiB
+// (p1e_mesh_create refuses larger meshes).
+template <typename T>
+__device__ __forceinline__ const T *at32(const T *p, int i) {
+  return reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) +
+                                     (uint32_t)i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T *at32(T *p, int i) {
+  return reinterpret_cast<T *>(reinterpret_cast<char *>(p) + (uint32_t)i * (uint32_t)sizeof(T));
+}
+
 struct Params {
   double C1, D1, p, eps;
   int ortho;  // p-Laplacian with the component-wise norm of the gradient (uniform per mesh)
@@ -974,7 +988,7 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
   const int sub = tid % GL;
   for (int a = tid / GL; a < nloc; a += NT / GL) {
     const bool first = a < NT / GL;
-    const int4 rec = first ? rec0 : M.trec[r0 + a];  // rec0 and b0: loaded by the caller
+    const int4 rec = first ? rec0 : *at32(M.trec, r0 + a);  // rec0, b0: loaded by the caller
     if (rec.w == 0) continue;  // no free DOF (uniform over the node's lanes)
     const int mask = rec.y & 7, fb = rec.y >> 3;
     const bool complete = rec.z & 1;
@@ -987,7 +1001,7 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
       for (int j = 0; j < D; ++j) {
         bj[j] = 0.0;
         if (complete && sub == 0 && ((mask >> j) & 1))
-          bj[j] = M.bhat[fb + __popc(mask & ((1 << j) - 1))];
+          bj[j] = *at32(M.bhat, fb + __popc(mask & ((1 << j) - 1)));
       }
     }
     double acc[D];
@@ -1035,11 +1049,11 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
 #pragma unroll
       for (int j = 0; j < D; ++j)
         if ((mask >> j) & 1) {
-          g[f] = sc * (acc[j] - bj[j]);
+          *at32(g, f) = sc * (acc[j] - bj[j]);
           ++f;
         }
     } else {  // halo partials in the tile's element type (FP32 in mixed precision)
-      T *hp = reinterpret_cast<T *>(M.hpart) + (int64_t)(rec.z >> 2) * D;
+      T *hp = at32(reinterpret_cast<T *>(M.hpart), (rec.z >> 2) * D);
 #pragma unroll
       for (int j = 0; j < D; ++j) hp[j] = (T)acc[j];
     }
@@ -1095,13 +1109,13 @@ __device__ __forceinline__ void tile_head(const TileMesh &M, int t, TileHead<NPT
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int a = k * NT + tid;
-    h.rec[k] = a < nloc ? M.trec[r0 + a] : make_int4(0, 0, 0, 0);
-    h.slot[k] = a < nloc ? (int)stream_load(M.tslot + r0 + a) : 0;  // read once
+    h.rec[k] = a < nloc ? *at32(M.trec, r0 + a) : make_int4(0, 0, 0, 0);
+    h.slot[k] = a < nloc ? (int)stream_load(at32(M.tslot, r0 + a)) : 0;  // read once
   }
   h.prec = make_int4(0, 0, 0, 0);
   if constexpr (PATCH) {
     const int a = patch_node<NT>(tid, nloc);
-    if (a < nloc) h.prec = M.trec[r0 + a];
+    if (a < nloc) h.prec = *at32(M.trec, r0 + a);
   }
 }
 
@@ -1135,8 +1149,8 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
   for (int k = 0; k < EPT; ++k) {
     const int e = e0 + min(k * NT + tid, net - 1);
 #pragma unroll
-    for (int l = 0; l < K; ++l) nd[k][l] = stream_load(M.conn_loc + (int64_t)l * M.ne + e);
-    cl[k] = GEO == GEO_CLASS ? (int)stream_load(M.geo_cls + e) : 0;
+    for (int l = 0; l < K; ++l) nd[k][l] = stream_load(at32(M.conn_loc + (int64_t)l * M.ne, e));
+    cl[k] = GEO == GEO_CLASS ? (int)stream_load(at32(M.geo_cls, e)) : 0;
   }
   constexpr int LQ = (K * kTileElems / kEntAlign + NT - 1) / NT;  // 16-byte entry groups
   constexpr int TQ = (kMaxGeoClasses * REC + NT - 1) / NT;
@@ -1168,7 +1182,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
     if ((pr.z & 1) && (nloc > NT / 2 || (tid & 1) == 0))
 #pragma unroll
       for (int j = 0; j < D; ++j)
-        if ((mask >> j) & 1) pb[j] = M.bhat[fb + __popc(mask & ((1 << j) - 1))];
+        if ((mask >> j) & 1) pb[j] = *at32(M.bhat, fb + __popc(mask & ((1 << j) - 1)));
   }
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
@@ -1183,16 +1197,16 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
       const int gi = rec[k].x, fb = rec[k].y >> 3;
       if constexpr (GEO == GEO_OTF) {
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) xo[j] = stream_load(geo + (int64_t)(r0 + a) * DIM + j);
+        for (int j = 0; j < DIM; ++j) xo[j] = stream_load(at32(geo, (r0 + a) * DIM + j));
       }
 #pragma unroll
-      for (int j = 0; j < D; ++j) w[j] = M.wref[(int64_t)gi * D + j];
+      for (int j = 0; j < D; ++j) w[j] = *at32(M.wref, gi * D + j);
 #pragma unroll
       for (int j = 0; j < D; ++j)
         if ((mask >> j) & 1) {
           const int f = fb + __popc(mask & ((1 << j) - 1));
-          vj[j] = vhat[f];
-          if (own) bj[j] = M.bhat[f];
+          vj[j] = *at32(vhat, f);
+          if (own) bj[j] = *at32(M.bhat, f);
         }
     }
     if (k == 0) {  // registers -> LDS while the nodal loads are in flight
