@@ -5,7 +5,8 @@
 // with random Dirichlet masks, values and loads, flags and geometry modes; a share of them is
 // corrupted (index out of range, repeated vertex, coincident vertices, non-finite coordinate,
 // bad sizes, kinds, exponents or pointers) and must be refused with the documented status.
-// For the valid ones the reported counts are checked against counts made here.
+// For the valid ones the reported counts are checked against counts made here, and the element
+// tiles against their definition (white box: the library's host structures).
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -16,6 +17,7 @@
 #include <vector>
 
 #include "p1e.h"
+#include "p1e_internal.h"
 
 static int g_fail = 0;
 #define CHECK(c, ...)                                              \
@@ -28,6 +30,66 @@ static int g_fail = 0;
       ++g_fail;                                                    \
     }                                                              \
   } while (0)
+
+// The tiles of a built mesh against their definition: per tile at most kTileElems elements and
+// the node cap, each node once; identity LDS slots before colouring; every local patch entry
+// is the byte offset (l kTileElems + e) d 4 of an element result whose vertex l is the row's
+// node, in ascending element, one per incidence; free nodes' records first, by descending
+// number of patch-sum rounds of 8 entries, then the nodes without a free DOF, ascending node
+// within each group.
+static void check_tiles(const p1e_mesh *m, int cap, int it) {
+  const int k = m->k, d = m->d;
+  const int64_t ne = m->ne;
+  std::vector<int> cnt, seen(m->nn, -1);
+  for (int64_t t = 0; t < m->ntiles; ++t) {
+    const int64_t e0 = m->ttile[4 * t], e1 = m->ttile[4 * t + 4];
+    const int64_t r0 = m->ttile[4 * t + 1], r1 = m->ttile[4 * t + 5];
+    const int64_t ent0 = m->ttile[4 * t + 2];
+    const int nloc = (int)(r1 - r0);
+    CHECK(e1 > e0 && e1 - e0 <= p1e::kTileElems && nloc <= cap, "iter %d tile %lld size", it,
+          (long long)t);
+    cnt.assign(nloc, 0);
+    for (int a = 0; a < nloc; ++a) {
+      const int32_t v = m->trec[4 * (r0 + a)];
+      CHECK(seen[v] != (int)t, "iter %d tile %lld: node %d twice", it, (long long)t, v);
+      seen[v] = (int)t;
+      CHECK(m->slots_coloured || m->tslot[r0 + a] == a, "iter %d: slot", it);
+    }
+    auto node_at = [&](int l, int64_t e) { return m->trec[4 * (r0 + m->conn_loc[l * ne + e])]; };
+    for (int64_t e = e0; e < e1; ++e)
+      for (int l = 0; l < k; ++l) {
+        const int a = m->conn_loc[l * ne + e];
+        CHECK(a < nloc, "iter %d: local index", it);
+        if (a < nloc) cnt[a] += 1;
+      }
+    int prev_key = 1 << 30, prev_v = -1;
+    for (int a = 0; a < nloc; ++a) {
+      const int32_t *rec = &m->trec[4 * (r0 + a)];
+      const int32_t v = rec[0];
+      const bool fr = (m->ninfo[v] & 7) != 0;
+      const int key = fr ? (cnt[a] + 7) / 8 : -1;
+      CHECK(key < prev_key || (key == prev_key && v > prev_v), "iter %d tile %lld: record order",
+            it, (long long)t);
+      prev_key = key;
+      prev_v = v;
+      if (!fr) {
+        CHECK(rec[3] == 0, "iter %d: row of a prescribed node", it);
+        continue;
+      }
+      const int p0 = rec[3] & 0xffff, n = rec[3] >> 16;
+      CHECK(n == cnt[a], "iter %d: row length %d vs %d", it, n, cnt[a]);
+      int prev_le = -1;
+      for (int q = 0; q < n; ++q) {
+        const int off = m->tlent[ent0 + p0 + q];
+        const int idx = off / (4 * d), l = idx / p1e::kTileElems, le = idx % p1e::kTileElems;
+        const bool ok = off % (4 * d) == 0 && l < k && le < e1 - e0 && le > prev_le &&
+                        node_at(l, e0 + le) == v;
+        CHECK(ok, "iter %d tile %lld node %d: entry %d", it, (long long)t, v, off);
+        prev_le = le;
+      }
+    }
+  }
+}
 
 struct Mesh {
   int dim = 2;
@@ -200,6 +262,7 @@ int main(int argc, char **argv) {
       CHECK(valid ? b > 0 && b % info.alignment == 0 : b == 0, "workspace mask %d: %llu", mask,
             (unsigned long long)b);
     }
+    check_tiles(h, cap, it);
     p1e_mesh_destroy(h);
   }
   // material constants: valid and invalid arguments
