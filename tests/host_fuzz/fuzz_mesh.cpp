@@ -89,6 +89,33 @@ static void check_tiles(const p1e_mesh *m, int cap, int it) {
       }
     }
   }
+  // halo rows: the free nodes in several tiles (or none), ascending node, each with one slot
+  // per tile in ascending tile order; a record's flags say complete (one tile) and owner
+  // (the first tile)
+  std::vector<int> ntile(m->nn, 0), rank_in(m->nn, 0);
+  for (int64_t r = 0; r < m->ntnodes; ++r) ntile[m->trec[4 * r]] += 1;
+  std::vector<int64_t> first_slot(m->nn, -1);
+  int64_t h = 0, slots = 0;
+  for (int64_t v = 0; v < m->nn; ++v)
+    if ((m->ninfo[v] & 7) && ntile[v] != 1) {
+      CHECK(h < m->nhalo && m->hrec[4 * h] == slots && m->hrec[4 * h + 1] == ntile[v] &&
+                m->hrec[4 * h + 2] == m->ninfo[v],
+            "iter %d: halo row %lld", it, (long long)h);
+      first_slot[v] = slots;
+      slots += ntile[v];
+      ++h;
+    }
+  CHECK(h == m->nhalo && slots == m->nslots, "iter %d: halo rows %lld slots %lld", it,
+        (long long)h, (long long)slots);
+  for (int64_t r = 0; r < m->ntnodes; ++r) {  // records in tile order
+    const int32_t v = m->trec[4 * r], z = m->trec[4 * r + 2];
+    const int rank = rank_in[v]++;
+    if (!(m->ninfo[v] & 7)) continue;
+    const bool complete = ntile[v] == 1;
+    CHECK((z & 1) == (int)complete && ((z >> 1) & 1) == (int)(rank == 0) &&
+              (complete || (z >> 2) == first_slot[v] + rank),
+          "iter %d: record flags of node %d", it, v);
+  }
 }
 
 struct Mesh {
