@@ -91,11 +91,17 @@ def algorithmic_bytes(info, prec):
 
 
 def kernel_source_hash():
+    """Hash of the code (comments and blank lines dropped) of the sources the profiled kernels
+    are built from: a profile stays valid across edits of comments only."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("p1e_device.h", "p1e_kernels.hip", "p1e_internal.h", "p1e_tiles.cpp"):
-        with open(os.path.join(ROOT, "paper_2109_01158_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2109_01158_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -1069,7 +1069,8 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
 //     the thread's elements, its node records, and the tile's local patch entries (into LDS);
 //  1. stage the nodal field u (u = v - x for Neo-Hookean, u = v for the p-Laplacian) of the
 //     tile's nodes in LDS (GEO_OTF: and their coordinate offsets); the tile that meets a node
-//     first adds b.v of its free DOFs;
+//     first adds b.v of its free DOFs; in the same round trip, b of the lane's first
+//     patch-sum node when that node's row is complete in the tile;
 //  2. element pass of the tile's elements, vertex values read from LDS, element results
 //     written to LDS; energies into (s, c);
 //  3. patch sums of the tile's free nodes from LDS (tile_patch_sums);
@@ -1080,9 +1081,10 @@ __device__ __forceinline__ void tile_patch_sums(const TileMesh &M, int r0, int n
 // Every order is fixed: the results do not depend on timing. No atomics.
 // geo: by GEO, the per-element geometry arrays, the class table (staged in sh.tab) or the
 // tile nodes' coordinate offsets (staged in sh.xs()).
-// What a tile's pass reads first: its bounds and its node records (the nodal loads depend
-// on them). A persistent caller loads the next tile's head while the current tile sums its
-// patches, so that a tile starts with one memory round trip instead of two.
+// What a tile's pass reads first: its bounds, its node records and each lane's first
+// patch-sum record (the nodal loads depend on them). A persistent caller loads the next
+// tile's head while the current tile sums its patches, so that a tile starts with one memory
+// round trip instead of two.
 template <int NPT>
 struct TileHead {
   int t;
