@@ -250,7 +250,7 @@ int p1e_grad_patch_fd4(p1e_mesh *mesh, const double *vhat, double eps, double *g
  * s.y > 1e-12 |s||y|, Armijo backtracking (c1 = 1e-4, halving, at most 40 trials), the first
  * step (and any step after a restart) scaled so that the largest nodal update is 0.1 h with h
  * the edge of the smallest element's reference cell, and a restart from steepest descent when
- * the two-loop direction is not a descent direction. Exactly max_iters accepted iterations
+ * the L-BFGS direction is not a descent direction. Exactly max_iters accepted iterations
  * unless the gradient vanishes or the line search stalls. */
 typedef struct p1e_lbfgs_opts {
   int32_t history;   /* m, 1..8 */

@@ -5,13 +5,13 @@
 // it runs alone or among others, so its results are bitwise identical either way.
 //
 // One engine step advances every active slot by one L-BFGS line-search trial (memory m,
-// two-loop recursion with H0 = (s.y / y.y) I, Armijo backtracking by halving, first step
-// scaled so that the largest nodal update is 0.1 h):
+// H0 = (s.y / y.y) I, the product H g in compact form, Armijo backtracking by halving, first
+// step scaled so that the largest nodal update is 0.1 h):
 //   evaluate   J and grad J at the trial point vt (element tiles, halo rows, finalize; the
 //              same bodies as the single-mesh path, Sections 5 and 6.2)
 //   decide     accept (Armijo) or halve the step
 //   update     v, g and the newest (s, y) pair of accepted slots; trial point of rejected ones
-//   direction  two-loop recursion for slots that accepted, then the next trial point
+//   direction  d = -H g for slots that accepted, then the next trial point
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -189,6 +189,7 @@ __global__ __launch_bounds__(kVB) void kb_decide(EngineDev E) {
   }
   st[ST_ACC] = acc;
   st[ST_NEEDDIR] = needdir;
+  st[ST_NEWPAIR] = 0;  // set by kb_hist when a new pair is kept
 }
 
 // per-tile view of a slot's vectors for the vector kernels
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kVB) void kb_vupdate(EngineDev E) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         block_reduce<kVB>(q[j][0], q[j][1], cnt);
-        if (threadIdx.x == 0) S.vpart[4 * (V.i0 / kVecTile) + j] = make_double2(q[j][0], q[j][1]);
+        if (threadIdx.x == 0) S.vpart[kNPart * (V.i0 / kVecTile) + j] = make_double2(q[j][0], q[j][1]);
         __syncthreads();
       }
     }
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(kVB) void kb_hist(EngineDev E) {
   for (int j = 0; j < 3; ++j) {
     double s, c;
     int cnt;
-    slot_sum(S.vpart, S.ntile_v, 4, j, nullptr, s, c, cnt);
+    slot_sum(S.vpart, S.ntile_v, kNPart, j, nullptr, s, c, cnt);
     r[j] = s + c;
     __syncthreads();
   }
@@ -276,6 +277,7 @@ __global__ __launch_bounds__(kVB) void kb_hist(EngineDev E) {
       const int next = st[ST_NEXT];
       st[ST_HEAD] = next;
       st[ST_NH] = min(st[ST_NH] + 1, m);
+      st[ST_NEWPAIR] = 1;
       sc[SC_RHO0 + next] = 1.0 / ys;
       sc[SC_GAMMA] = ys / yy;
     } else if (st[ST_NH] == m) {
@@ -296,96 +298,215 @@ __device__ __forceinline__ int hist_index(const EngineDev &E, int slot, int i) {
   return (st[ST_HEAD] - i + E.history) % E.history;
 }
 
-// d = g for slots that need a new direction
-__global__ __launch_bounds__(kVB) void kb_vcopy(EngineDev E) {
+// The direction d = -H g in the compact form of the L-BFGS matrix (Byrd, Nocedal and
+// Schnabel): with the stored pairs in chronological order, R the upper triangle (diagonal
+// included) of S^T Y, D its diagonal and H0 = gamma I (gamma = s.y / y.y of the newest pair),
+//   H g = gamma g + S w - gamma Y t,  t = R^-1 S^T g,  w = R^-T ((D + gamma Y^T Y) t - gamma Y^T g),
+// the product the two-loop recursion forms, in three launches: one pass for the dot products
+// S^T g and Y^T g (and, after a new pair, S^T y_new and Y^T y_new, which extend the S^T Y and
+// Y^T Y kept per slot), an O(m^2) solve per slot, and one pass forming d.
+constexpr int kNDot = 4 * kMaxHistory;  // dot products of the first pass, by loop position i:
+// [i] s_i.g, [M + i] y_i.g, [2M + i] s_i.y_new, [3M + i] y_i.y_new (M = kMaxHistory)
+
+// a double summed over the block (plain FP64 in a fixed order); thread 0 gets it
+__device__ __forceinline__ double block_sum(double x, double *sh) {
+  x = wave_sum(x);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kVB / 64; ++w) r += sh[w];
+  return r;
+}
+
+// first pass: per vector tile, the partial dot products of the stored pairs with g (and with
+// the new pair's y) into vpart[tile][0 .. kNDot)
+__global__ __launch_bounds__(kVB) void kb_dots(EngineDev E) {
+  __shared__ double sh[kVB / 64];
   const int count = E.counts[kCountVec];
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const VTile V = vtile(E, t);
     if (!needs_dir(E, V.slot)) continue;
+    const int *st = E.st + V.slot * kNSt;
+    const int nh = st[ST_NH];
+    if (nh == 0) continue;  // d = -g: no dot products
+    const bool newp = st[ST_NEWPAIR] != 0;
     const SlotDev &S = E.slots[V.slot];
-    for (int k = 0; k < kVecTile; k += kVB) {
-      const int i = V.i0 + k + threadIdx.x;
-      if (i < V.n) S.d[i] = S.g[i];
+    const double *ynew = S.Y + (int64_t)st[ST_HEAD] * V.n;
+    const double *si_[kMaxHistory], *yi_[kMaxHistory];
+#pragma unroll
+    for (int i = 0; i < kMaxHistory; ++i) {
+      const int64_t h = i < nh ? hist_index(E, V.slot, i) : 0;
+      si_[i] = S.S + h * V.n;
+      yi_[i] = S.Y + h * V.n;
     }
+    double acc[kNDot];
+#pragma unroll
+    for (int q = 0; q < kNDot; ++q) acc[q] = 0.0;
+    for (int k = 0; k < kVecTile; k += kVB) {
+      const int j = V.i0 + k + threadIdx.x;
+      if (j >= V.n) continue;
+      const double gj = S.g[j], yn = newp ? ynew[j] : 0.0;
+#pragma unroll
+      for (int i = 0; i < kMaxHistory; ++i) {
+        if (i >= nh) break;
+        const double si = si_[i][j], yi = yi_[i][j];
+        acc[i] = fma(si, gj, acc[i]);
+        acc[kMaxHistory + i] = fma(yi, gj, acc[kMaxHistory + i]);
+        acc[2 * kMaxHistory + i] = fma(si, yn, acc[2 * kMaxHistory + i]);
+        acc[3 * kMaxHistory + i] = fma(yi, yn, acc[3 * kMaxHistory + i]);
+      }
+    }
+    double2 *p = S.vpart + (int64_t)kNPart * (V.i0 / kVecTile);
+#pragma unroll
+    for (int q = 0; q < kNDot; ++q) {
+      const int i = q % kMaxHistory, kind = q / kMaxHistory;
+      if (i >= nh || (kind >= 2 && !newp)) continue;  // uniform over the block
+      const double r = block_sum(acc[q], sh);
+      if (threadIdx.x == 0) p[q] = make_double2(r, 0.0);
+    }
+    __syncthreads();
   }
 }
 
-// one block per slot: first loop (phase 0) a_i = rho s_i.q, coef = -a_i;
-// second loop (phase 1) b = rho y_i.r, coef = a_i - b
-__global__ __launch_bounds__(kVB) void kb_coef(EngineDev E, int i, int phase) {
+// one block per slot: the dot products summed over the slot's tiles (fixed order), S^T Y and
+// Y^T Y extended by the new pair, the compact solve, and the coefficients of the second pass
+// in syy: [kCoefG] for g, [kCoefS + h] for S_h, [kCoefY + h] for Y_h (d = -g without pairs)
+__global__ __launch_bounds__(kVB) void kb_compact(EngineDev E) {
+  constexpr int M = kMaxHistory, CH = kVB / kNDot;  // chunks of tiles per dot product
+  __shared__ double red[CH][kNDot], val[kNDot], sy[M * M], yy[M * M];
   const int slot = blockIdx.x;
   if (!needs_dir(E, slot)) return;
-  const int h = hist_index(E, slot, i);
-  if (h < 0) return;
   const SlotDev &S = E.slots[slot];
-  double s, c;
-  int cnt;
-  slot_sum(S.vpart, S.ntile_v, 4, 0, nullptr, s, c, cnt);
-  if (threadIdx.x == 0) {
-    double *sc = E.sc + slot * kNSc;
-    const double dot = (s + c) * sc[SC_RHO0 + h];
-    if (phase == 0) {
-      sc[SC_A0 + i] = dot;
-      sc[SC_COEF] = -dot;
-    } else {
-      sc[SC_COEF] = sc[SC_A0 + i] - dot;
+  const int *st = E.st + slot * kNSt;
+  const int nh = st[ST_NH], head = st[ST_HEAD], m = E.history;
+  const bool newp = st[ST_NEWPAIR] != 0;
+  double *syy = S.syy;
+  if (nh > 0) {
+    for (int i = threadIdx.x; i < M * M; i += kVB) {
+      sy[i] = syy[kSY + i];
+      yy[i] = syy[kYY + i];
+    }
+    const int q = threadIdx.x % kNDot, ch = threadIdx.x / kNDot;
+    double s = 0.0, c = 0.0;
+    const int i = q % M, kind = q / M;
+    if (i < nh && (kind < 2 || newp))
+      for (int tt = ch; tt < S.ntile_v; tt += CH)
+        pair_add(s, c, S.vpart[(int64_t)kNPart * tt + q].x, 0.0);
+    red[ch][q] = s + c;
+    __syncthreads();
+    if (threadIdx.x < kNDot) {
+      double r = 0.0;
+      for (int w = 0; w < CH; ++w) r += red[w][threadIdx.x];
+      val[threadIdx.x] = r;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (nh == 0) {
+    syy[kCoefG] = -1.0;
+    return;
+  }
+  auto hist = [&](int i) { return (head - i + m) % m; };  // loop position i, 0 = newest
+  if (newp) {  // the newest pair against every stored pair (i = 0: itself)
+    for (int i = 0; i < nh; ++i) {
+      const int hi = hist(i);
+      sy[hi * M + head] = syy[kSY + hi * M + head] = val[2 * M + i];  // s_hi . y_new
+      yy[hi * M + head] = syy[kYY + hi * M + head] = val[3 * M + i];  // y_hi . y_new
+      yy[head * M + hi] = syy[kYY + head * M + hi] = val[3 * M + i];
     }
   }
+  // chronological position c (0 = oldest) -> storage index; loops unrolled over M with
+  // predicates, so that t, w and h stay in registers
+  int h[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) h[c] = c < nh ? hist(nh - 1 - c) : 0;
+  const double gamma = E.sc[slot * kNSc + SC_GAMMA];
+  double t[M], w[M];
+#pragma unroll
+  for (int c = M - 1; c >= 0; --c) {  // R t = S^T g (back substitution)
+    double r = 0.0;
+    if (c < nh) {
+      r = val[nh - 1 - c];
+#pragma unroll
+      for (int c2 = c + 1; c2 < M; ++c2)
+        if (c2 < nh) r -= sy[h[c] * M + h[c2]] * t[c2];
+      r /= sy[h[c] * M + h[c]];
+    }
+    t[c] = r;
+  }
+#pragma unroll
+  for (int c = 0; c < M; ++c) {  // (D + gamma Y^T Y) t - gamma Y^T g
+    double r = 0.0;
+    if (c < nh) {
+      r = sy[h[c] * M + h[c]] * t[c] - gamma * val[M + nh - 1 - c];
+#pragma unroll
+      for (int c2 = 0; c2 < M; ++c2)
+        if (c2 < nh) r += gamma * yy[h[c] * M + h[c2]] * t[c2];
+    }
+    w[c] = r;
+  }
+#pragma unroll
+  for (int c = 0; c < M; ++c) {  // R^T w' = w (forward substitution)
+    if (c < nh) {
+      double r = w[c];
+#pragma unroll
+      for (int c2 = 0; c2 < c; ++c2) r -= sy[h[c2] * M + h[c]] * w[c2];
+      w[c] = r / sy[h[c] * M + h[c]];
+    }
+  }
+  syy[kCoefG] = -gamma;
+#pragma unroll
+  for (int c = 0; c < M; ++c)
+    if (c < nh) {
+      syy[kCoefS + h[c]] = -w[c];
+      syy[kCoefY + h[c]] = gamma * t[c];
+    }
 }
 
-// One pass of the two-loop recursion over d, in this order per entry:
-//   if ia >= 0:  d += coef * (Y if ya else S)[hist ia]       (the previous update)
-//   if scale:    d *= gamma (H0 = gamma I) when pairs are stored
-//   if neg:      d = -d, with the partials g.d, max|d|, g.g, max|g|
-//   if ib >= 0:  partial of (Y if yb else S)[hist ib] . d     (the next coefficient)
-// Fusing an update with the next dot halves the passes over the vectors; each entry sees
-// the same operations in the same order as separate passes would apply.
-__global__ __launch_bounds__(kVB) void kb_vstep(EngineDev E, int ia, int ya, int scale, int neg,
-                                                int ib, int yb) {
+// second pass: d = cg g + sum_i (cS_i S_i + cY_i Y_i) (loop position order), with the
+// partials g.d, max|d|, g.g, max|g|
+__global__ __launch_bounds__(kVB) void kb_dir(EngineDev E) {
   __shared__ double sh[2][kVB / 64];
   const int count = E.counts[kCountVec];
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const VTile V = vtile(E, t);
     if (!needs_dir(E, V.slot)) continue;
     const SlotDev &S = E.slots[V.slot];
-    const int ha = ia >= 0 ? hist_index(E, V.slot, ia) : -1;
-    const int hb = ib >= 0 ? hist_index(E, V.slot, ib) : -1;
-    const bool sc = scale && E.st[V.slot * kNSt + ST_NH] > 0;
-    if (ha < 0 && hb < 0 && !sc && !neg) continue;
-    const double coef = E.sc[V.slot * kNSc + SC_COEF];
-    const double gamma = E.sc[V.slot * kNSc + SC_GAMMA];
-    const double *wa = ha >= 0 ? (ya ? S.Y : S.S) + (int64_t)ha * V.n : nullptr;
-    const double *wb = hb >= 0 ? (yb ? S.Y : S.S) + (int64_t)hb * V.n : nullptr;
+    const int nh = E.st[V.slot * kNSt + ST_NH];
+    const double cg = S.syy[kCoefG];
+    const double *si_[kMaxHistory], *yi_[kMaxHistory];
+    double cs[kMaxHistory], cy[kMaxHistory];
+#pragma unroll
+    for (int i = 0; i < kMaxHistory; ++i) {
+      const int64_t h = i < nh ? hist_index(E, V.slot, i) : 0;
+      si_[i] = S.S + h * V.n;
+      yi_[i] = S.Y + h * V.n;
+      cs[i] = i < nh ? S.syy[kCoefS + h] : 0.0;
+      cy[i] = i < nh ? S.syy[kCoefY + h] : 0.0;
+    }
     double s = 0.0, c = 0.0, gg = 0.0, ggc = 0.0, md = 0.0, mg = 0.0;
     for (int k = 0; k < kVecTile; k += kVB) {
       const int j = V.i0 + k + threadIdx.x;
-      if (j < V.n) {
-        double dj = S.d[j];
-        if (wa) dj = fma(coef, wa[j], dj);
-        if (sc) dj *= gamma;
-        double tt, e;
-        if (neg) {
-          dj = -dj;
-          const double gj = S.g[j];
-          two_sum(s, gj * dj, tt, e), s = tt, c += e;
-          two_sum(gg, gj * gj, tt, e), gg = tt, ggc += e;
-          md = fmax(md, fabs(dj));
-          mg = fmax(mg, fabs(gj));
-        } else if (wb) {
-          two_sum(s, wb[j] * dj, tt, e), s = tt, c += e;
-        }
-        S.d[j] = dj;
+      if (j >= V.n) continue;
+      const double gj = S.g[j];
+      double dj = cg * gj;
+#pragma unroll
+      for (int i = 0; i < kMaxHistory; ++i) {
+        if (i >= nh) break;
+        dj = fma(cs[i], si_[i][j], dj);
+        dj = fma(cy[i], yi_[i][j], dj);
       }
+      S.d[j] = dj;
+      double tt, e;
+      two_sum(s, gj * dj, tt, e), s = tt, c += e;
+      two_sum(gg, gj * gj, tt, e), gg = tt, ggc += e;
+      md = fmax(md, fabs(dj));
+      mg = fmax(mg, fabs(gj));
     }
-    if (!neg && !wb) continue;  // uniform over the block
     int cnt = 0;
     block_reduce<kVB>(s, c, cnt);
-    double2 *p = S.vpart + 4 * (V.i0 / kVecTile);
-    if (!neg) {
-      if (threadIdx.x == 0) p[0] = make_double2(s, c);
-      __syncthreads();
-      continue;
-    }
     __syncthreads();
     block_reduce<kVB>(gg, ggc, cnt);
     for (int o = 32; o > 0; o >>= 1) {
@@ -402,6 +523,7 @@ __global__ __launch_bounds__(kVB) void kb_vstep(EngineDev E, int ia, int ya, int
         md = fmax(md, sh[0][w]);
         mg = fmax(mg, sh[1][w]);
       }
+      double2 *p = S.vpart + (int64_t)kNPart * (V.i0 / kVecTile);
       p[0] = make_double2(s, c);
       p[1] = make_double2(md, 0.0);
       p[2] = make_double2(gg, ggc);
@@ -418,11 +540,11 @@ __global__ __launch_bounds__(kVB) void kb_dirfin(EngineDev E) {
   const SlotDev &S = E.slots[slot];
   double s, c, s2, c2;
   int cnt;
-  slot_sum(S.vpart, S.ntile_v, 4, 0, nullptr, s, c, cnt);
+  slot_sum(S.vpart, S.ntile_v, kNPart, 0, nullptr, s, c, cnt);
   __syncthreads();
-  slot_sum(S.vpart, S.ntile_v, 4, 2, nullptr, s2, c2, cnt);
-  const double md = slot_max(S.vpart, S.ntile_v, 4, 1);
-  const double mg = slot_max(S.vpart, S.ntile_v, 4, 3);
+  slot_sum(S.vpart, S.ntile_v, kNPart, 2, nullptr, s2, c2, cnt);
+  const double md = slot_max(S.vpart, S.ntile_v, kNPart, 1);
+  const double mg = slot_max(S.vpart, S.ntile_v, kNPart, 3);
   if (threadIdx.x == 0) {
     double *sc = E.sc + slot * kNSc;
     int *st = E.st + slot * kNSt;
@@ -496,26 +618,9 @@ int batch_step(const EngineDev &E, hipStream_t s) {
   hipLaunchKernelGGL(kb_decide, dim3(sb), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_vupdate, dim3(kGridVec), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_hist, dim3(E.max_slots), dim3(kVB), 0, s, E);
-  hipLaunchKernelGGL(kb_vcopy, dim3(kGridVec), dim3(kVB), 0, s, E);
-  // two-loop recursion: q = g; for i = newest..oldest: a_i = rho_i s_i.q, q -= a_i y_i;
-  // r = gamma q; for i = oldest..newest: b = rho_i y_i.r, r += (a_i - b) s_i; d = -r
-  const int m = E.history;
-  auto vstep = [&](int ia, int ya, int scale, int neg, int ib, int yb) {
-    hipLaunchKernelGGL(kb_vstep, dim3(kGridVec), dim3(kVB), 0, s, E, ia, ya, scale, neg, ib, yb);
-  };
-  vstep(-1, 0, 0, 0, 0, 0);
-  hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, 0, 0);
-  for (int i = 1; i < m; ++i) {
-    vstep(i - 1, 1, 0, 0, i, 0);
-    hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, i, 0);
-  }
-  vstep(m - 1, 1, 1, 0, m - 1, 1);
-  hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, m - 1, 1);
-  for (int i = m - 2; i >= 0; --i) {
-    vstep(i + 1, 0, 0, 0, i, 1);
-    hipLaunchKernelGGL(kb_coef, dim3(E.max_slots), dim3(kVB), 0, s, E, i, 1);
-  }
-  vstep(0, 0, 0, 1, -1, 0);
+  hipLaunchKernelGGL(kb_dots, dim3(kGridVec), dim3(kVB), 0, s, E);
+  hipLaunchKernelGGL(kb_compact, dim3(E.max_slots), dim3(kVB), 0, s, E);
+  hipLaunchKernelGGL(kb_dir, dim3(kGridVec), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_dirfin, dim3(E.max_slots), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_vtrial, dim3(kGridVec), dim3(kVB), 0, s, E);
   hipError_t e = hipGetLastError();

@@ -170,6 +170,11 @@ namespace p1e {
 constexpr int kMaxHistory = 8;     // L-BFGS memory m <= kMaxHistory
 constexpr int kVecTile = 1024;     // DOFs per tile of the vector kernels
 constexpr int kMaxLineTrials = 40; // backtracking halvings per iteration
+constexpr int kNPart = 4 * kMaxHistory;  // vector-reduction partials per vector tile
+// per-slot L-BFGS matrices and coefficients (doubles, storage order of the history):
+// s_a.y_b, y_a.y_b, then the direction's coefficients of g, of S_h and of Y_h
+constexpr int kSY = 0, kYY = kMaxHistory * kMaxHistory, kCoefG = 2 * kMaxHistory * kMaxHistory,
+              kCoefS = kCoefG + 1, kCoefY = kCoefS + kMaxHistory, kNSyy = kCoefY + kMaxHistory;
 
 // per-slot scalars (double) and integers (int32), one row of kNSc / kNSt per slot
 enum SlotScalar {
@@ -178,7 +183,7 @@ enum SlotScalar {
 };
 enum SlotInt {
   ST_MODE = 0, ST_ITER, ST_NH, ST_HEAD, ST_NEXT, ST_TRIALS, ST_BAD, ST_ACC, ST_NEEDDIR,
-  ST_MAXIT, ST_STATUS, ST_EVALS, ST_RESET, ST_CLASS, kNSt = 16
+  ST_MAXIT, ST_STATUS, ST_EVALS, ST_RESET, ST_CLASS, ST_NEWPAIR, kNSt = 16
 };
 enum SlotMode { MODE_FREE = 0, MODE_INIT = 1, MODE_TRIAL = 2, MODE_DONE = 3 };
 // ST_STATUS on completion
@@ -190,7 +195,8 @@ enum ElemClass { CLS_PLAP2 = 0, CLS_PLAP3, CLS_NH2, CLS_NH3, kNumClasses };
 // one slot as the batched kernels see it
 struct SlotDev {
   TileMesh M;      // the slot's mesh (layout of p1e_mesh_bind inside the slot's allocation)
-  double2 *vpart;  // [ntile_v][4] vector-reduction partials
+  double2 *vpart;  // [ntile_v][kNPart] vector-reduction partials
+  double *syy;     // [kNSyy] S^T Y, Y^T Y of the stored pairs and the direction's coefficients
   int32_t ntile_h, ntile_v;
   double C1, D1, p, dirichlet_bv;
   int32_t ortho;  // p-Laplacian with the component-wise norm

@@ -54,7 +54,7 @@ double mesh_h(const p1e_mesh *m) {
 uint64_t state_bytes(const p1e_mesh *m, int history) {
   const uint64_t n = (uint64_t)std::max<int64_t>(m->nfd, 1);
   const uint64_t ntv = (n + kVecTile - 1) / kVecTile;
-  return aup(5 * n * 8) + aup(2ull * history * n * 8) + aup(ntv * 4 * 16);
+  return aup(5 * n * 8) + aup(2ull * history * n * 8) + aup(ntv * kNPart * 16) + aup(8ull * kNSyy);
 }
 
 // capacities of the tile tables for a workspace of pool_bytes: every element tile but a
@@ -184,7 +184,8 @@ struct Engine {
     char *hist = take(2ull * E.history * n1 * 8);
     S.S = (double *)hist;
     S.Y = S.S + (uint64_t)E.history * n1;
-    S.vpart = (double2 *)take((uint64_t)S.ntile_v * 4 * 16);
+    S.vpart = (double2 *)take((uint64_t)S.ntile_v * kNPart * 16);
+    S.syy = (double *)take(8ull * kNSyy);
     slots_h[k] = S;
     cls_h[k] = class_of(m);
     // state rows
