@@ -308,22 +308,10 @@ __device__ __forceinline__ int hist_index(const EngineDev &E, int slot, int i) {
 constexpr int kNDot = 4 * kMaxHistory;  // dot products of the first pass, by loop position i:
 // [i] s_i.g, [M + i] y_i.g, [2M + i] s_i.y_new, [3M + i] y_i.y_new (M = kMaxHistory)
 
-// a double summed over the block (plain FP64 in a fixed order); thread 0 gets it
-__device__ __forceinline__ double block_sum(double x, double *sh) {
-  x = wave_sum(x);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kVB / 64; ++w) r += sh[w];
-  return r;
-}
-
 // first pass: per vector tile, the partial dot products of the stored pairs with g (and with
 // the new pair's y) into vpart[tile][0 .. kNDot)
 __global__ __launch_bounds__(kVB) void kb_dots(EngineDev E) {
-  __shared__ double sh[kVB / 64];
+  __shared__ double sh[kVB / 64][kNDot];
   const int count = E.counts[kCountVec];
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const VTile V = vtile(E, t);
@@ -358,13 +346,20 @@ __global__ __launch_bounds__(kVB) void kb_dots(EngineDev E) {
         acc[3 * kMaxHistory + i] = fma(yi, yn, acc[3 * kMaxHistory + i]);
       }
     }
-    double2 *p = S.vpart + (int64_t)kNPart * (V.i0 / kVecTile);
+    // every wavefront's sums into the LDS, then the wavefronts' in order (plain FP64)
 #pragma unroll
     for (int q = 0; q < kNDot; ++q) {
       const int i = q % kMaxHistory, kind = q / kMaxHistory;
       if (i >= nh || (kind >= 2 && !newp)) continue;  // uniform over the block
-      const double r = block_sum(acc[q], sh);
-      if (threadIdx.x == 0) p[q] = make_double2(r, 0.0);
+      const double r = wave_sum(acc[q]);
+      if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][q] = r;
+    }
+    __syncthreads();
+    const int q = threadIdx.x, i = q % kMaxHistory, kind = q / kMaxHistory;
+    if (q < kNDot && i < nh && (kind < 2 || newp)) {
+      double r = 0.0;
+      for (int w = 0; w < kVB / 64; ++w) r += sh[w][q];
+      S.vpart[(int64_t)kNPart * (V.i0 / kVecTile) + q] = make_double2(r, 0.0);
     }
     __syncthreads();
   }
@@ -373,8 +368,10 @@ __global__ __launch_bounds__(kVB) void kb_dots(EngineDev E) {
 // one block per slot: the dot products summed over the slot's tiles (fixed order), S^T Y and
 // Y^T Y extended by the new pair, the compact solve, and the coefficients of the second pass
 // in syy: [kCoefG] for g, [kCoefS + h] for S_h, [kCoefY + h] for Y_h (d = -g without pairs)
-__global__ __launch_bounds__(kVB) void kb_compact(EngineDev E) {
-  constexpr int M = kMaxHistory, CH = kVB / kNDot;  // chunks of tiles per dot product
+constexpr int kCB = 1024;  // threads of kb_compact
+__global__ __launch_bounds__(kCB) void kb_compact(EngineDev E) {
+  constexpr int M = kMaxHistory, CH = kCB / kNDot;  // chunks of tiles per dot product
+  constexpr int U = 4;                              // loads in flight per chunk
   __shared__ double red[CH][kNDot], val[kNDot], sy[M * M], yy[M * M];
   const int slot = blockIdx.x;
   if (!needs_dir(E, slot)) return;
@@ -384,7 +381,7 @@ __global__ __launch_bounds__(kVB) void kb_compact(EngineDev E) {
   const bool newp = st[ST_NEWPAIR] != 0;
   double *syy = S.syy;
   if (nh > 0) {
-    for (int i = threadIdx.x; i < M * M; i += kVB) {
+    for (int i = threadIdx.x; i < M * M; i += kCB) {
       sy[i] = syy[kSY + i];
       yy[i] = syy[kYY + i];
     }
@@ -392,8 +389,16 @@ __global__ __launch_bounds__(kVB) void kb_compact(EngineDev E) {
     double s = 0.0, c = 0.0;
     const int i = q % M, kind = q / M;
     if (i < nh && (kind < 2 || newp))
-      for (int tt = ch; tt < S.ntile_v; tt += CH)
-        pair_add(s, c, S.vpart[(int64_t)kNPart * tt + q].x, 0.0);
+      for (int t0 = ch; t0 < S.ntile_v; t0 += U * CH) {
+        double x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int tt = t0 + u * CH;
+          x[u] = tt < S.ntile_v ? S.vpart[(int64_t)kNPart * tt + q].x : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) pair_add(s, c, x[u], 0.0);
+      }
     red[ch][q] = s + c;
     __syncthreads();
     if (threadIdx.x < kNDot) {
@@ -619,7 +624,7 @@ int batch_step(const EngineDev &E, hipStream_t s) {
   hipLaunchKernelGGL(kb_vupdate, dim3(kGridVec), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_hist, dim3(E.max_slots), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_dots, dim3(kGridVec), dim3(kVB), 0, s, E);
-  hipLaunchKernelGGL(kb_compact, dim3(E.max_slots), dim3(kVB), 0, s, E);
+  hipLaunchKernelGGL(kb_compact, dim3(E.max_slots), dim3(kCB), 0, s, E);
   hipLaunchKernelGGL(kb_dir, dim3(kGridVec), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_dirfin, dim3(E.max_slots), dim3(kVB), 0, s, E);
   hipLaunchKernelGGL(kb_vtrial, dim3(kGridVec), dim3(kVB), 0, s, E);
