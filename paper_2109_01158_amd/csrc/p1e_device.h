@@ -7,7 +7,7 @@
 // Precision. P1E_FP64 runs everything in double. P1E_MIXED evaluates the element algebra in
 // float on the displacement gradient G = F - I, with the cancellation-free forms
 //   |F|^2 - dim = 2 tr G + |G|^2,  det F - 1 = tr G + s2(G) + det G  (s2: sum of principal
-//   2x2 minors, absent in 2D),  (det F - 1) - log det F  by log_excess (double),
+//   2x2 minors, absent in 2D),  (det F - 1) - log det F  by log_excess (float),
 //   F - F^-T = [(s2 + det G) I + (det F) G + G^T - cof G] / det F  (2D: cof terms reduce),
 // and accumulates the energies in double and the patch sums of the element forces in rounds:
 // each lane adds up to four forces of its node in float, and the rounds in double.
@@ -289,6 +289,39 @@ __device__ __forceinline__ double log_excess(double d) {
   return k0 ? q0 : qk;
 }
 
+// The same q(d) in float, for the mixed-precision density (whose delta is a sum of float
+// invariants): the reduction and the two forms above with float arithmetic, S(w) to w^4
+// (truncation below 2e-9 of S), log 2 split into 16 high bits (k log2Hi exact for |k| < 256)
+// and the rest; the quotient by the hardware reciprocal, one Newton step and one residual
+// correction. Within 3 float ulps of q for |d| <= 1/4 and 12 ulps near the ends of the
+// reduction interval (against a long double reference over 2e7 samples of (-1, 1000)).
+__device__ __forceinline__ float log_excess(float d) {
+  const float t = 1.0f + d;
+  int k;
+  float m = frexpf(t, &k);  // t = m 2^k, m in [1/2, 1)
+  const bool lo = m < 0.70710678f;
+  m = lo ? 2.0f * m : m;
+  k = lo ? k - 1 : k;
+  const bool k0 = k == 0;
+  const float num = k0 ? d : m - 1.0f, den = k0 ? 2.0f + d : m + 1.0f;  // den in [1.7, 2.5]
+  float r = __builtin_amdgcn_rcpf(den);
+  r = fmaf(r, fmaf(-den, r, 1.0f), r);
+  float s = num * r;
+  s = fmaf(r, fmaf(-den, s, num), s);
+  const float w = s * s;
+  float S = 1.0f / 11.0f;  // S(w) = sum w^i / (2i + 3), i = 4 .. 0 by Horner
+#pragma unroll
+  for (int i = 3; i >= 0; --i) S = fmaf(S, w, 1.0f / (2 * i + 3));
+  const float tail = 2.0f * (s * w) * S;
+  const float q0 = fmaf(s, d, -tail);
+  constexpr float kLn2Hi = 0.693145751953125f;  // 45426 / 2^16
+  constexpr float kLn2Lo = 1.4286068203e-6f;     // log 2 - kLn2Hi
+  const float kd = (float)k;
+  const float corr = (d - (t - 1.0f)) * __builtin_amdgcn_rcpf(t);
+  const float qk = ((((d - kd * kLn2Hi) - kd * kLn2Lo) - 2.0f * s) - tail) - corr;
+  return k0 ? q0 : qk;
+}
+
 // log((1 + y) / (1 - y)) = 2 atanh y for |y| < 1: the log of the det F ratio of a difference
 // step. For |y| < 1/64 by the odd series 2 (y + y^3/3 + ... + y^9/9) (the omitted terms are
 // below 1e-19 of the sum), without division; otherwise as x - log_excess(x) = log1p(x) with
@@ -345,7 +378,7 @@ __device__ __forceinline__ NhInv<DIM, T> nh_invariants(const T G[DIM][DIM]) {
 
 // Neo-Hookean density from the invariants (eq. neoHook), in double:
 //   W = C1 (|G|^2 - 2 (s2 + det G) + 2 q) + D1 delta^2,  delta = det F - 1,
-//   q = delta - log det F (log_excess), using |F|^2 - dim = 2 tr G + |G|^2.
+//   q = delta - log det F (log_excess, in T), using |F|^2 - dim = 2 tr G + |G|^2.
 template <int DIM, typename T>
 __device__ __forceinline__ double nh_density(const NhInv<DIM, T> &v, double C1, double D1,
                                              bool &bad) {
@@ -354,7 +387,11 @@ __device__ __forceinline__ double nh_density(const NhInv<DIM, T> &v, double C1, 
     bad = true;
     return 0.0;
   }
-  const double q = log_excess(delta);
+  double q;
+  if constexpr (std::is_same<T, float>::value)
+    q = (double)log_excess((float)delta);
+  else
+    q = log_excess(delta);
   const double W = C1 * ((double)v.n2 - 2.0 * ((double)v.s2 + (double)v.dG) + 2.0 * q) +
                    D1 * delta * delta;
   if (!isfinite(W)) bad = true;

@@ -163,7 +163,7 @@ def test_server_mix_equals_solo_bitwise(P):
 
 
 def test_server_mixed_precision_against_the_oracle(P, oracle_mod):
-    """Serving in mixed precision (FP32 element algebra, FP64 log term, sums and L-BFGS
+    """Serving in mixed precision (FP32 element algebra and log term, FP64 sums and L-BFGS
     vectors): every request's reported final energy agrees with the oracle's FP64 energy at
     the returned vhat to the mixed bar 1e-5, the mix equals each request run alone (bitwise)
     and p1e_minimize in mixed precision (bitwise); the distance to the FP64 server's final
