@@ -63,7 +63,7 @@ __global__ __launch_bounds__((batch_tile_threads<T>())) void kb_tile(EngineDev E
     const int2 st = tl[t];
     if (!evaluating(E, st.x)) continue;
     const SlotDev &S = E.slots[st.x];
-    const Params prm{S.C1, S.D1, S.p, 0.0, S.ortho};
+    const Params prm{S.C1, S.D1, S.p, 0.0, S.ortho, (float)(2.0 * S.C1), (float)(2.0 * S.D1)};
     const bool otf = S.M.geo_mode == GEO_OTF;
     const T *geo = sizeof(T) == 4 ? (const T *)(otf ? (const void *)S.M.txo32 : S.M.geo32)
                                   : (const T *)(otf ? (const void *)S.M.txo64 : S.M.geo64);

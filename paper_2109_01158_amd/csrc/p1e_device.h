@@ -57,8 +57,26 @@ __device__ __forceinline__ T *at32(T *p, int i) {
 
 struct Params {
   double C1, D1, p, eps;
-  int ortho;  // p-Laplacian with the component-wise norm of the gradient (uniform per mesh)
+  int ortho;       // p-Laplacian with the component-wise norm of the gradient (uniform per mesh)
+  float C1x2, D1x2;  // 2 C1 and 2 D1 rounded to float
 };
+
+// 2 C1 and 2 D1 in T. The float stresses take the host's roundings as uniform operands (no
+// conversion per element); they equal 2 (float)C1 and 2 (float)D1, the doubling being exact.
+template <typename T>
+__device__ __forceinline__ T twice_c1(const Params &prm) {
+  if constexpr (std::is_same<T, float>::value)
+    return prm.C1x2;
+  else
+    return 2.0 * prm.C1;
+}
+template <typename T>
+__device__ __forceinline__ T twice_d1(const Params &prm) {
+  if constexpr (std::is_same<T, float>::value)
+    return prm.D1x2;
+  else
+    return 2.0 * prm.D1;
+}
 
 // ----------------------------------------------------------------------- compensated sums
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
@@ -415,20 +433,21 @@ __device__ __forceinline__ double nh_energy(const T G[DIM][DIM], double C1, doub
 // P comes out multiplied by vol (the element size, folded into the three coefficients). The
 // density is bitwise the one of nh_energy.
 template <int DIM, typename T>
-__device__ __forceinline__ double nh_energy_stress(const T G[DIM][DIM], double C1, double D1,
+__device__ __forceinline__ double nh_energy_stress(const T G[DIM][DIM], const Params &prm,
                                                    T vol, bool &bad, T P[DIM][DIM]) {
   const NhInv<DIM, T> v = nh_invariants<DIM, T>(G);
-  const double W = nh_density<DIM, T>(v, C1, D1, bad);
+  const double W = nh_density<DIM, T>(v, prm.C1, prm.D1, bad);
   const T delta = v.tr + v.s2 + v.dG;
   const T J = T(1) + delta;
+  const T c1x2 = twice_c1<T>(prm);
   // a = 2 C1 / J (in float by the hardware reciprocal, within 1 ulp); a J = 2 C1 exactly
   T a;
   if constexpr (std::is_same<T, float>::value)
-    a = T(2) * (T)C1 * __builtin_amdgcn_rcpf(J);
+    a = c1x2 * __builtin_amdgcn_rcpf(J);
   else
-    a = T(2) * (T)C1 / J;
-  const T bcoef = T(2) * (T)D1 * delta;
-  const T alpha = T(2) * (T)C1 * vol, beta = (a - bcoef) * vol;
+    a = c1x2 / J;
+  const T bcoef = twice_d1<T>(prm) * delta;
+  const T alpha = c1x2 * vol, beta = (a - bcoef) * vol;
   const T gamma = mad(a, v.s2 + v.dG, bcoef * (T(1) + v.tr)) * vol;
 #pragma unroll
   for (int j = 0; j < DIM; ++j)
@@ -482,15 +501,15 @@ __device__ __forceinline__ double svk_energy(const T G[DIM][DIM], double C1, dou
 // the density and vol dW/dF = vol F S with S = dW/dE = 2 C1 E + 2 D1 (tr E) I (second
 // Piola-Kirchhoff stress), F = I + G; the density is bitwise the one of svk_energy
 template <int DIM, typename T>
-__device__ __forceinline__ double svk_energy_stress(const T G[DIM][DIM], double C1, double D1,
+__device__ __forceinline__ double svk_energy_stress(const T G[DIM][DIM], const Params &prm,
                                                     T vol, bool &bad, T P[DIM][DIM]) {
   T E[DIM][DIM];
   svk_strain<DIM, T>(G, E);
-  const double W = svk_density<DIM, T>(E, C1, D1, bad);
+  const double W = svk_density<DIM, T>(E, prm.C1, prm.D1, bad);
   T tr = T(0);
 #pragma unroll
   for (int j = 0; j < DIM; ++j) tr += E[j][j];
-  const T a = T(2) * (T)C1 * vol, b = T(2) * (T)D1 * vol * tr;
+  const T a = twice_c1<T>(prm) * vol, b = twice_d1<T>(prm) * vol * tr;
   T Sv[DIM][DIM];  // vol S
 #pragma unroll
   for (int j = 0; j < DIM; ++j)
@@ -776,12 +795,12 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
   T P[D][DIM];
   NhInv<DIM, T> nv;  // (Neo-Hookean patch differences) the invariants, kept for the steps
   if constexpr (MODE == MODE_FORCE && KIND == P1E_NEOHOOKE) {
-    W = nh_energy_stress<DIM, T>(G, prm.C1, prm.D1, vol, bad, P);  // P = |T| dW/dF
+    W = nh_energy_stress<DIM, T>(G, prm, vol, bad, P);  // P = |T| dW/dF
   } else if constexpr (MODE == MODE_FORCE && KIND == P1E_SVK) {
-    W = svk_energy_stress<DIM, T>(G, prm.C1, prm.D1, vol, bad, P);
+    W = svk_energy_stress<DIM, T>(G, prm, vol, bad, P);
   } else if constexpr (MODE == MODE_FORCE && KIND == P1E_GINZBURG_LANDAU) {
     W = density<DIM, D, KIND, T>(G, prm, bad);
-    const T a = T(2) * (T)prm.C1 * vol;  // vol dW/dgrad u = 2 C1 vol grad u
+    const T a = twice_c1<T>(prm) * vol;  // vol dW/dgrad u = 2 C1 vol grad u
 #pragma unroll
     for (int m = 0; m < DIM; ++m) P[0][m] = a * G[0][m];
   } else if constexpr (MODE == MODE_FORCE) {
@@ -1335,7 +1354,7 @@ __device__ __forceinline__ void tile_pass(const TileMesh &M,
   // 3. patch sums of the tile's free nodes
   if constexpr (MODE != MODE_ENERGY || kLdsEnergy) {
     __syncthreads();
-    if constexpr (kLdsEnergy) reinterpret_cast<double *>(sh.us)[tid] = s + c;
+    if constexpr (kLdsEnergy) reinterpret_cast<double *>(sh.us)[tid] = EPT == 1 ? s : s + c;
     if constexpr (MODE != MODE_ENERGY) {
       if (nloc <= NT / 2)
         tile_patch_sums<D, T, NT, 2>(M, r0, nloc, scale, g, sh, h.prec, pb, tid);

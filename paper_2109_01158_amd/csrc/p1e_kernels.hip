@@ -223,7 +223,7 @@ int check_launch(const char *what) {
 }
 
 Params params_of(const p1e_mesh *m, double eps) {
-  return Params{m->C1, m->D1, m->p, eps, m->ortho};
+  return Params{m->C1, m->D1, m->p, eps, m->ortho, (float)(2.0 * m->C1), (float)(2.0 * m->D1)};
 }
 
 // Blocks of a persistent grid over n tiles: as many as the device holds at once (occupancy

@@ -98,6 +98,73 @@ def test_table6_reproduced_with_the_componentwise_plaplace(P, level, iters):
     assert round(rep["J"], 4) == pytest.approx(g["energy_printed"][level - 1], abs=1e-12)
 
 
+def _lbfgs_two_loop_replica(O, v0, h, m, iters):
+    """The minimizer's rules (L-BFGS with memory m, H0 = gamma I from the newest kept pair,
+    a pair kept when s.y > 1e-12 |s||y|, restart from -g when the direction does not
+    descend, first step after a restart scaled to a largest update of 0.1 h, Armijo
+    c1 = 1e-4 with halving) on the oracle's energy and gradient, with the direction from
+    the two-loop recursion (Nocedal and Wright, Algorithm 7.4) instead of the compact form."""
+    v = v0.copy()
+    J, g = O.energy(v)["J"], O.grad_exact(v)
+    pairs, gamma = [], 1.0
+    for _ in range(iters):
+        if pairs:
+            q, a = g.copy(), []
+            for s, y in reversed(pairs):
+                a.append((s @ q) / (y @ s))
+                q -= a[-1] * y
+            r = gamma * q
+            for (s, y), ai in zip(pairs, reversed(a)):
+                r += (ai - (y @ r) / (y @ s)) * s
+            d = -r
+        else:
+            d = -g
+        gtd, maxd = g @ d, np.abs(d).max()
+        if not (gtd < 0 and np.isfinite(gtd) and maxd > 0 and np.isfinite(maxd)):
+            pairs, d = [], -g
+            gtd, maxd = -(g @ g), np.abs(g).max()
+        alpha = min(1.0, 0.1 * h / maxd) if not pairs else 1.0
+        for _ in range(40):
+            vt = v + alpha * d
+            e = O.energy(vt)
+            if e["nbad"] == 0 and np.isfinite(e["J"]) and e["J"] <= J + 1e-4 * alpha * gtd:
+                break
+            alpha *= 0.5
+        else:
+            raise AssertionError("replica line search stalled")
+        gt = O.grad_exact(vt)
+        s, y = vt - v, gt - g
+        v, g, J = vt, gt, e["J"]
+        ys, yy, ss = y @ s, y @ y, s @ s
+        if ys > 1e-12 * np.sqrt(yy * ss) and np.isfinite(ys) and yy > 0:
+            pairs = (pairs + [(s, y)])[-m:]
+            gamma = ys / yy
+        elif len(pairs) == m:
+            pairs = pairs[1:]
+    return v, J
+
+
+@pytest.mark.parametrize("m", [1, 2, 8])
+def test_lbfgs_iterates_match_a_two_loop_replica(P, oracle_mod, m):
+    """The device's direction (compact form of the L-BFGS matrix) against the two-loop
+    recursion, the same product in exact arithmetic: after 12 iterations (past the history's
+    wrap-around for every m) the library's iterate and energy agree with a NumPy replica of
+    the minimizer's rules on the oracle. Memories 1 (H is one rank-two update of gamma I),
+    2 and 8 (the largest the engine holds)."""
+    prob = S.plaplace_square(n=12, p=3.0, f=-10.0, seed=4)
+    O = oracle_mod.Oracle(prob)
+    h = float(np.sqrt(2.0 * O.vol.min()))
+    iters = 12
+    v_ref, J_ref = _lbfgs_two_loop_replica(O, prob.vhat(), h, m, iters)
+    rep, v, _ = _minimize(P, prob, iters, history=m)
+    assert rep["iterations"] == iters
+    err = np.abs(v - v_ref).max() / np.abs(v_ref).max()
+    print(f"[two-loop replica] m {m}: max |v - v_ref| / max |v_ref| {err:.2e}, "
+          f"J rel {abs(rep['J'] - J_ref) / abs(J_ref):.2e}", flush=True)
+    assert err <= 1e-9
+    assert abs(rep["J"] - J_ref) <= 1e-12 * abs(J_ref)
+
+
 def test_neohooke_minimization_decreases_energy(P, oracle_mod):
     prob = S.neohooke_beam_2d(40, 8, 2.0, 0.4, seed=0, amp=0.0)
     O = oracle_mod.Oracle(prob)
