@@ -8,8 +8,13 @@ precision, inputs resident in HBM. Prints ONE JSON line with:
 
 * value / ms_per_step: K steps bracketed by device synchronisations (wall clock), after W
   untimed steps (the default W = 500, about 60 ms of work, brings the GPU out of the idle
-  clock state the host-side oracle timing leaves it in), and the median step from HIP events
-  around each step of a second pass;
+  clock state the host-side oracle timing leaves it in), and the median from HIP events around
+  each step of a second pass; the step is timed in two forms, issued eagerly from Python
+  (eager_autograd) and as replays of the step captured once in a HIP graph (GraphedStep,
+  graph_replay), and the faster is reported (step_form): the eager rate depends on how fast
+  the host issues a step, a replay costs a few microseconds of GPU time for the graph launch.
+  The replays' J and gradient equal the eager step's bitwise
+  (graph_replay_bitwise_equal_eager);
 * roofline: the dominant kernel against the HBM roofline (HIP events around each kernel over
   a third pass), with the counter-measured traffic and VALU-issue fraction when a profile of
   the current kernel sources is committed;
@@ -26,6 +31,7 @@ precision, inputs resident in HBM. Prints ONE JSON line with:
   batching vs one-at-a-time FP64 solves: req/s, p50/p99 latency, with and without mesh setup).
 
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 500] [--no-cpu-baseline] [--no-serve]
+                [--no-graph]
 """
 
 import argparse
@@ -52,6 +58,8 @@ def _args():
     ap.add_argument("--no-extras", action="store_true", help="skip FP64, FD and 48M timings")
     ap.add_argument("--no-large", action="store_true", help="skip the 48M-tet timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving benchmark")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the eager step only (no HIP graph capture)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-iters", type=int, default=200)
     ap.add_argument("--fd-sample", type=int, default=3000,
@@ -379,20 +387,42 @@ def main():
 
     for _ in range(a.warmup):
         step()
-    # timed region: K steps bracketed by device synchronisations
-    ms = time_steps(step, a.steps)
-    value = info["ne"] / (ms * 1e-3)
-    J_timed = float(res["J"].item())
-    g_timed = vhat.grad.detach().cpu().numpy()
-    # the same K steps with HIP events around each step: the median step
-    ms_median = median_step_ms(step, a.steps)
-    # and with every library kernel bracketed by HIP events on its launch stream: per-kernel
-    # durations for the roofline (the events themselves cost a few us per kernel)
+    # eager autograd steps: K steps bracketed by device synchronisations, then the median of
+    # per-step HIP events (these include the host's time to issue each step whenever the host
+    # is slower than the GPU)
+    ms_eager = time_steps(step, a.steps)
+    ms_median_eager = median_step_ms(step, a.steps)
+    J_eager = float(res["J"].item())
+    g_eager = vhat.grad.detach().clone()
+    # every library kernel bracketed by HIP events on its launch stream: per-kernel durations
+    # for the roofline (the events themselves cost a few us per kernel)
     P.prof_reset()
     P.prof_enable(True)
     ms_events = time_steps(step, a.steps)
     P.prof_enable(False)
     kern = P.prof_collect()
+    # the same autograd step captured once in a HIP graph and replayed (the step's kernels for
+    # one graph launch), K replays bracketed by device synchronisations, then the median of
+    # per-replay HIP events; J and the gradient of the replays must equal the eager step's
+    # bitwise. The faster of the two forms is reported (a slow host favours the graph, whose
+    # launch costs a few microseconds of GPU time).
+    if a.no_graph:
+        gstep, ms_graph, ms_median_graph, graph_bitwise = None, float("inf"), None, None
+        J_timed, g_timed = J_eager, g_eager.cpu().numpy()
+    else:
+        gstep = P.GraphedStep(vhat, mesh, a.prec)
+        for _ in range(20):
+            gstep.replay()
+        ms_graph = time_steps(gstep.replay, a.steps)
+        ms_median_graph = median_step_ms(gstep.replay, a.steps)
+        J_timed = float(gstep.J.item())
+        graph_bitwise = J_timed == J_eager and bool(torch.equal(gstep.grad, g_eager))
+        g_timed = gstep.grad.detach().cpu().numpy()
+    del g_eager
+    step_form = "graph" if ms_graph < ms_eager else "eager"
+    ms, ms_median = (ms_graph, ms_median_graph) if step_form == "graph" else (ms_eager,
+                                                                           ms_median_eager)
+    value = info["ne"] / (ms * 1e-3)
 
     abytes = algorithmic_bytes(info, a.prec)
     kstats = {k: {"launches": c, "avg_us": 1e3 * t / c} for k, (c, t) in kern.items()}
@@ -471,7 +501,9 @@ def main():
         "config": {
             "workload": f"{a.config}: 3D Neo-Hookean box [0,1]x[0,0.1]^2, 460x46x46 cubes x 6 Kuhn "
                         f"tets, E=2e8 nu=0.3, x=0 face clamped, u=amp*U[-1,1] (amp={prob.amp:.3g}); "
-                        f"J + exact grad J through the autograd hook, {a.prec}",
+                        f"J + exact grad J through the autograd hook, {a.prec}; timed as "
+                        f"issued eagerly and as replays of the step captured in a HIP graph, "
+                        f"the faster reported (step_form)",
             "ne": info["ne"], "nn": info["nn"], "n_free_dofs": info["n_free_dofs"],
             "patch_incidences": info["nnz"], "parallelism": "single GPU",
         },
@@ -483,6 +515,13 @@ def main():
                      "valu_issue_frac_profiled": issue_frac,
                      "limiter": limiter},
         "ms_per_step_with_kernel_events": ms_events,
+        "step_form": step_form,
+        "eager_autograd": {"value": info["ne"] / (ms_eager * 1e-3), "ms_per_step": ms_eager,
+                           "ms_per_step_median": ms_median_eager},
+        "graph_replay": None if a.no_graph else {
+            "value": info["ne"] / (ms_graph * 1e-3), "ms_per_step": ms_graph,
+            "ms_per_step_median": ms_median_graph},
+        "graph_replay_bitwise_equal_eager": graph_bitwise,
         "step_alg_bytes_per_element": step_bytes / info["ne"],
         "step_alg_GBs": step_bytes / (ms * 1e-3) / 1e9,
         "kernels": kstats,
@@ -493,7 +532,7 @@ def main():
     }
     if base is not None:
         out["cpu_baseline"] = base
-    del mesh, vhat, vhat0
+    del gstep, mesh, vhat, vhat0
     torch.cuda.empty_cache()
     if not a.no_extras and not a.no_large:
         extras["nh3d_box_48M_mixed_jgrad"] = large_timing(P, a.steps, a.warmup)

@@ -16,6 +16,6 @@ from .api import (  # noqa: F401
     minimize_workspace_bytes, mesh_get_info, neohooke_constants, prof_collect, prof_enable,
     prof_reset, svk_constants, workspace_bytes,
 )
-from .autograd import P1Energy, p1_energy  # noqa: F401
+from .autograd import GraphedStep, P1Energy, p1_energy  # noqa: F401
 
 lib()  # fail loudly at import if libp1e.so is missing

@@ -8,6 +8,8 @@ context, and the backward pass hands that buffer back scaled in place by the inc
 gradient, a device-side scalar (``p1e_grad_scale``, which writes nothing when the scale is 1).
 A second backward through the same graph (``retain_graph=True``) recomputes the gradient at
 the saved input. The bad-element count of the forward pass is kept on ``mesh.last_flag``.
+
+``GraphedStep`` captures one such step (forward and backward) in a HIP graph and replays it.
 """
 
 import torch
@@ -40,3 +42,46 @@ class P1Energy(torch.autograd.Function):
 def p1_energy(vhat, mesh, prec="mixed"):
     """J(vhat) as a differentiable 0-d tensor."""
     return P1Energy.apply(vhat, mesh, prec)
+
+
+class GraphedStep:
+    """One J + exact grad J step through the autograd hook, captured once in a HIP graph
+    (``torch.cuda.CUDAGraph``) and replayed: the step's kernels (element tiles, halo rows, the
+    in-place scaling of the backward pass) for one graph launch on the host.
+
+    Every replay reads ``vhat``'s memory as it is then (change it in place, e.g.
+    ``vhat.data.copy_(...)``) and rewrites ``J`` (0-d) and ``grad`` in place. The step runs on
+    a leaf of its own that shares ``vhat``'s memory, so that its gradient accumulator is made
+    on the capture's stream: one that earlier eager backward passes made for ``vhat`` would sit
+    on another stream, and the captured step would have to synchronise with it, which a
+    capture cannot hold. The capture runs ``warmup`` eager steps on a side stream first, as
+    torch requires; ``replay`` launches on the current stream. The mesh's scratch arrays are
+    shared with eager calls on the same mesh, so replays and eager calls must not overlap
+    (issue them on one stream)."""
+
+    def __init__(self, vhat, mesh, prec="mixed", warmup=3):
+        dev = vhat.device
+        x = vhat.detach().requires_grad_(True)  # a new leaf on vhat's memory
+        seed = torch.ones((), dtype=torch.float64, device=dev)
+
+        def step():
+            x.grad = None
+            J = p1_energy(x, mesh, prec)
+            torch.autograd.backward(J, seed)
+            return J
+
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                step()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.J = step()
+        self.vhat, self.grad, self._leaf, self._seed = vhat, x.grad, x, seed
+
+    def replay(self):
+        """Runs the step; returns (J, grad), the tensors it rewrites."""
+        self.graph.replay()
+        return self.J, self.grad

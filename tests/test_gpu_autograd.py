@@ -121,3 +121,32 @@ def test_grad_scale_in_place(P):
     h.copy_(ref)
     mesh.grad_scale(h, s)
     assert torch.equal(h, ref * -2.5)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_graph_replays_match_eager_steps(P, prec):
+    """The autograd step captured in a HIP graph (GraphedStep) after eager backward passes on
+    the same vhat: every replay, with eager steps, synchronisations and an in-place change of
+    vhat between the replays, gives J and the gradient of an eager step at the same vhat,
+    bitwise."""
+    prob = S.neohooke_box_3d(17, 6, 5, 1.0, 6 / 17, 5 / 17, seed=4)
+    mesh = _mesh(P, prob)
+    v = torch.tensor(prob.vhat(), device="cuda", requires_grad=True)
+    for _ in range(2):
+        v.grad = None
+        P.p1_energy(v, mesh, prec).backward()
+    gs = P.GraphedStep(v, mesh, prec)
+    rng = np.random.default_rng(7)
+    for k in range(5):
+        if k:
+            dv = torch.tensor(1e-4 * rng.standard_normal(v.numel()), device="cuda")
+            v.data.add_(dv)
+        ve = v.detach().clone().requires_grad_(True)
+        Je = P.p1_energy(ve, mesh, prec)
+        Je.backward()
+        torch.cuda.synchronize()
+        J, g = gs.replay()
+        torch.cuda.synchronize()
+        assert g is gs.grad
+        assert J.item() == Je.item()
+        assert torch.equal(g, ve.grad)
