@@ -9,8 +9,9 @@
 //   |F|^2 - dim = 2 tr G + |G|^2,  det F - 1 = tr G + s2(G) + det G  (s2: sum of principal
 //   2x2 minors, absent in 2D),  (det F - 1) - log det F  by log_excess (float),
 //   F - F^-T = [(s2 + det G) I + (det F) G + G^T - cof G] / det F  (2D: cof terms reduce),
-// and accumulates the energies in double and the patch sums of the element forces in rounds:
-// each lane adds up to four forces of its node in float, and the rounds in double.
+// forms the Neo-Hookean density from these in float, and accumulates the energies in double
+// and the patch sums of the element forces in rounds: each lane adds up to four forces of its
+// node in float, and the rounds in double.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -394,33 +395,36 @@ __device__ __forceinline__ NhInv<DIM, T> nh_invariants(const T G[DIM][DIM]) {
   return v;
 }
 
-// Neo-Hookean density from the invariants (eq. neoHook), in double:
+// Neo-Hookean density from the invariants (eq. neoHook), returned in double:
 //   W = C1 (|G|^2 - 2 (s2 + det G) + 2 q) + D1 delta^2,  delta = det F - 1,
-//   q = delta - log det F (log_excess, in T), using |F|^2 - dim = 2 tr G + |G|^2.
+//   q = delta - log det F (log_excess), using |F|^2 - dim = 2 tr G + |G|^2.
+// In T: for float (mixed precision) as 2W with the uniform 2 C1 and 2 D1, every term of the
+// size of the float invariants it is formed from, so their own rounding already sets the
+// accuracy.
 template <int DIM, typename T>
-__device__ __forceinline__ double nh_density(const NhInv<DIM, T> &v, double C1, double D1,
+__device__ __forceinline__ double nh_density(const NhInv<DIM, T> &v, const Params &prm,
                                              bool &bad) {
-  const double delta = (double)v.tr + (double)v.s2 + (double)v.dG;
-  if (!(delta > -1.0)) {
+  const T delta = v.tr + v.s2 + v.dG;
+  if (!(delta > T(-1))) {
     bad = true;
     return 0.0;
   }
-  double q;
-  if constexpr (std::is_same<T, float>::value)
-    q = (double)log_excess((float)delta);
-  else
-    q = log_excess(delta);
-  const double W = C1 * ((double)v.n2 - 2.0 * ((double)v.s2 + (double)v.dG) + 2.0 * q) +
-                   D1 * delta * delta;
+  const T q = log_excess(delta);
+  T W;
+  if constexpr (std::is_same<T, float>::value) {
+    const float a = fmaf(2.0f, q, v.n2 - 2.0f * (v.s2 + v.dG));
+    W = 0.5f * fmaf(prm.D1x2 * delta, delta, prm.C1x2 * a);
+  } else {
+    W = prm.C1 * (v.n2 - 2.0 * (v.s2 + v.dG) + 2.0 * q) + prm.D1 * delta * delta;
+  }
   if (!isfinite(W)) bad = true;
-  return W;
+  return (double)W;
 }
 
 // Neo-Hookean density at F = I + G (eq. neoHook), returned in double.
 template <int DIM, typename T>
-__device__ __forceinline__ double nh_energy(const T G[DIM][DIM], double C1, double D1,
-                                            bool &bad) {
-  return nh_density<DIM, T>(nh_invariants<DIM, T>(G), C1, D1, bad);
+__device__ __forceinline__ double nh_energy(const T G[DIM][DIM], const Params &prm, bool &bad) {
+  return nh_density<DIM, T>(nh_invariants<DIM, T>(G), prm, bad);
 }
 
 // Density and first Piola stress P = dW/dF at F = I + G from one set of invariants:
@@ -436,7 +440,7 @@ template <int DIM, typename T>
 __device__ __forceinline__ double nh_energy_stress(const T G[DIM][DIM], const Params &prm,
                                                    T vol, bool &bad, T P[DIM][DIM]) {
   const NhInv<DIM, T> v = nh_invariants<DIM, T>(G);
-  const double W = nh_density<DIM, T>(v, prm.C1, prm.D1, bad);
+  const double W = nh_density<DIM, T>(v, prm, bad);
   const T delta = v.tr + v.s2 + v.dG;
   const T J = T(1) + delta;
   const T c1x2 = twice_c1<T>(prm);
@@ -662,7 +666,7 @@ __device__ __forceinline__ double gl_potential_d3(const PowerSums &q, double x, 
 template <int DIM, int D, int KIND, typename T>
 __device__ __forceinline__ double density(const T G[D][DIM], const Params &prm, bool &bad) {
   if constexpr (KIND == P1E_NEOHOOKE) {
-    return nh_energy<DIM, T>(G, prm.C1, prm.D1, bad);
+    return nh_energy<DIM, T>(G, prm, bad);
   } else if constexpr (KIND == P1E_SVK) {
     return svk_energy<DIM, T>(G, prm.C1, prm.D1, bad);
   } else if constexpr (KIND == P1E_GINZBURG_LANDAU) {  // the gradient part only
@@ -807,7 +811,7 @@ __device__ __forceinline__ void element_pass(int e, int ne, const T (&uu)[DIM + 
     W = pl_energy_stress<DIM, T>(G[0], prm.p, prm.ortho != 0, vol, bad, P[0]);
   } else if constexpr (is_fd(MODE) && KIND == P1E_NEOHOOKE) {
     nv = nh_invariants<DIM, T>(G);
-    W = nh_density<DIM, T>(nv, prm.C1, prm.D1, bad);
+    W = nh_density<DIM, T>(nv, prm, bad);
   } else {
     W = density<DIM, D, KIND, T>(G, prm, bad);
   }
