@@ -79,7 +79,8 @@ class GraphedStep:
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self.J = step()
-        self.vhat, self.grad, self._leaf, self._seed = vhat, x.grad, x, seed
+        # the graph's kernels read the mesh's device arrays: keep the mesh alive with it
+        self.vhat, self.mesh, self.grad, self._leaf, self._seed = vhat, mesh, x.grad, x, seed
 
     def replay(self):
         """Runs the step; returns (J, grad), the tensors it rewrites."""
