@@ -406,20 +406,26 @@ def main():
     # per-replay HIP events; J and the gradient of the replays must equal the eager step's
     # bitwise. The faster of the two forms is reported (a slow host favours the graph, whose
     # launch costs a few microseconds of GPU time).
-    if a.no_graph:
-        gstep, ms_graph, ms_median_graph, graph_bitwise = None, float("inf"), None, None
-        J_timed, g_timed = J_eager, g_eager.cpu().numpy()
-    else:
-        gstep = P.GraphedStep(vhat, mesh, a.prec)
-        for _ in range(20):
-            gstep.replay()
-        ms_graph = time_steps(gstep.replay, a.steps)
-        ms_median_graph = median_step_ms(gstep.replay, a.steps)
-        J_timed = float(gstep.J.item())
-        graph_bitwise = J_timed == J_eager and bool(torch.equal(gstep.grad, g_eager))
-        g_timed = gstep.grad.detach().cpu().numpy()
+    gstep, ms_graph, ms_median_graph, graph_bitwise, graph_error = None, None, None, None, None
+    J_timed, g_timed = J_eager, g_eager.cpu().numpy()
+    if not a.no_graph:
+        try:
+            gstep = P.GraphedStep(vhat, mesh, a.prec)
+        except RuntimeError as e:  # a capture the runtime refuses: report the eager step only
+            graph_error = str(e)[:200]
+            torch.cuda.synchronize()
+        if gstep is not None:
+            for _ in range(20):
+                gstep.replay()
+            ms_graph = time_steps(gstep.replay, a.steps)
+            ms_median_graph = median_step_ms(gstep.replay, a.steps)
+            graph_bitwise = (float(gstep.J.item()) == J_eager
+                             and bool(torch.equal(gstep.grad, g_eager)))
+            if graph_bitwise:
+                J_timed, g_timed = float(gstep.J.item()), gstep.grad.detach().cpu().numpy()
     del g_eager
-    step_form = "graph" if ms_graph < ms_eager else "eager"
+    # the graph form is reported only if its results equal the eager step's
+    step_form = "graph" if graph_bitwise and ms_graph < ms_eager else "eager"
     ms, ms_median = (ms_graph, ms_median_graph) if step_form == "graph" else (ms_eager,
                                                                            ms_median_eager)
     value = info["ne"] / (ms * 1e-3)
@@ -518,9 +524,10 @@ def main():
         "step_form": step_form,
         "eager_autograd": {"value": info["ne"] / (ms_eager * 1e-3), "ms_per_step": ms_eager,
                            "ms_per_step_median": ms_median_eager},
-        "graph_replay": None if a.no_graph else {
-            "value": info["ne"] / (ms_graph * 1e-3), "ms_per_step": ms_graph,
-            "ms_per_step_median": ms_median_graph},
+        "graph_replay": None if a.no_graph else (
+            {"error": graph_error} if gstep is None else {
+                "value": info["ne"] / (ms_graph * 1e-3), "ms_per_step": ms_graph,
+                "ms_per_step_median": ms_median_graph}),
         "graph_replay_bitwise_equal_eager": graph_bitwise,
         "step_alg_bytes_per_element": step_bytes / info["ne"],
         "step_alg_GBs": step_bytes / (ms * 1e-3) / 1e9,
