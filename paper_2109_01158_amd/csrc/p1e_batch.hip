@@ -208,6 +208,7 @@ __device__ __forceinline__ VTile vtile(const EngineDev &E, int t) {
 // accepted slots: newest (s, y) pair and v, g <- vt, gt, with the partial dots y.s, y.y, s.s;
 // rejected slots: the next trial point v + alpha d
 __global__ __launch_bounds__(kVB) void kb_vupdate(EngineDev E) {
+  __shared__ double sh[3][2][kVB / 64];
   const int count = E.counts[kCountVec];
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const VTile V = vtile(E, t);
@@ -243,14 +244,28 @@ __global__ __launch_bounds__(kVB) void kb_vupdate(EngineDev E) {
         S.g[i] = gt;
       }
     }
-    if (acc == 2) {
-      int cnt = 0;
+    if (acc == 2) {  // (uniform over the block) the three pairs' block sums together: the
+      // shuffle trees of block_reduce, then one LDS exchange
+      for (int o = 32; o > 0; o >>= 1) {
+        double q2[3][2];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        block_reduce<kVB>(q[j][0], q[j][1], cnt);
-        if (threadIdx.x == 0) S.vpart[kNPart * (V.i0 / kVecTile) + j] = make_double2(q[j][0], q[j][1]);
-        __syncthreads();
+        for (int j = 0; j < 3; ++j)
+          q2[j][0] = __shfl_down(q[j][0], o, 64), q2[j][1] = __shfl_down(q[j][1], o, 64);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) pair_add(q[j][0], q[j][1], q2[j][0], q2[j][1]);
       }
+      if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          sh[j][0][threadIdx.x >> 6] = q[j][0], sh[j][1][threadIdx.x >> 6] = q[j][1];
+      __syncthreads();
+      if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          for (int w = 1; w < kVB / 64; ++w) pair_add(q[j][0], q[j][1], sh[j][0][w], sh[j][1][w]);
+          S.vpart[kNPart * (V.i0 / kVecTile) + j] = make_double2(q[j][0], q[j][1]);
+        }
+      __syncthreads();
     }
   }
 }
@@ -473,7 +488,7 @@ __global__ __launch_bounds__(kCB) void kb_compact(EngineDev E) {
 // second pass: d = cg g + sum_i (cS_i S_i + cY_i Y_i) (loop position order), with the
 // partials g.d, max|d|, g.g, max|g|
 __global__ __launch_bounds__(kVB) void kb_dir(EngineDev E) {
-  __shared__ double sh[2][kVB / 64];
+  __shared__ double sh[6][kVB / 64];
   const int count = E.counts[kCountVec];
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const VTile V = vtile(E, t);
@@ -510,23 +525,27 @@ __global__ __launch_bounds__(kVB) void kb_dir(EngineDev E) {
       md = fmax(md, fabs(dj));
       mg = fmax(mg, fabs(gj));
     }
-    int cnt = 0;
-    block_reduce<kVB>(s, c, cnt);
-    __syncthreads();
-    block_reduce<kVB>(gg, ggc, cnt);
+    // the two compensated sums and the two maxima together: the shuffle trees of block_reduce
+    // within each wavefront, then one LDS exchange (the same results, fewer barriers)
     for (int o = 32; o > 0; o >>= 1) {
+      const double s2 = __shfl_down(s, o, 64), c2 = __shfl_down(c, o, 64);
+      const double g2 = __shfl_down(gg, o, 64), gc2 = __shfl_down(ggc, o, 64);
+      pair_add(s, c, s2, c2);
+      pair_add(gg, ggc, g2, gc2);
       md = fmax(md, __shfl_down(md, o, 64));
       mg = fmax(mg, __shfl_down(mg, o, 64));
     }
     if ((threadIdx.x & 63) == 0) {
-      sh[0][threadIdx.x >> 6] = md;
-      sh[1][threadIdx.x >> 6] = mg;
+      const int w = threadIdx.x >> 6;
+      sh[0][w] = s, sh[1][w] = c, sh[2][w] = gg, sh[3][w] = ggc, sh[4][w] = md, sh[5][w] = mg;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       for (int w = 1; w < kVB / 64; ++w) {
-        md = fmax(md, sh[0][w]);
-        mg = fmax(mg, sh[1][w]);
+        pair_add(s, c, sh[0][w], sh[1][w]);
+        pair_add(gg, ggc, sh[2][w], sh[3][w]);
+        md = fmax(md, sh[4][w]);
+        mg = fmax(mg, sh[5][w]);
       }
       double2 *p = S.vpart + (int64_t)kNPart * (V.i0 / kVecTile);
       p[0] = make_double2(s, c);
